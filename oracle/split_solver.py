@@ -1,0 +1,270 @@
+"""Plain FP64 oracle for the split potential solve -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, the smoke check and the CPU-baseline leg of the benchmark may use
+this module.  The GPU library never imports, links or calls it.
+
+What it computes (Mauser, Stimming, Zhang, "A novel nonlocal potential solver
+based on nonuniform FFT ..."):
+
+    Phi(x) = int -kx^2/|k|^2 rho_hat(k) e^{2 pi i k.x} dk            (Sec. 1, eq. 4)
+    rho_hat(k) = int rho(x) e^{-2 pi i k.x} dx                       (Sec. 1, eq. 5)
+
+split with the partition p(k) = exp(-|k|^2 / sigma^2) into
+
+    I1 = high-frequency part, integrand continuous and zero at k = 0,
+         evaluated with the trapezoidal rule on a zero-padded box     (Sec. 2.1, eq. 9)
+    I2 = low-frequency part on the disk |k| <= c, polar coordinates,
+         radial Gauss rule x azimuthal trapezoid rule                 (Sec. 2.1, eqs. 10-12)
+
+The oracle evaluates every discrete sum exactly as it is defined: I1 through
+the 2-D DFT of the zero-padded density (numpy.fft serves as the DFT, a library
+step), rho_hat at the polar nodes and the I2 sum as direct nonuniform DFT sums
+(Sec. 2.1: the direct evaluation costs O(N N_r N_theta)), written as separable
+matrix products.  No NUFFT appears here: the GPU path's NUFFTs approximate
+exactly these direct sums.
+
+Readings of points the paper leaves open (each is listed in the design notes):
+  * 2 pi convention of eqs. 4-5 throughout; the Fourier grid of I1 is
+    k_m = m / (kappa N h), m in FFT order (-M/2 .. M/2-1).
+  * the grid holds N points x_n = -L + n h, n = 0..N-1 (periodic box).
+  * g1(0) = 0, its limit (Sec. 2.1: the I1 integrand vanishes at the origin).
+  * sigma = sqrt(lambda) / (2 pi (kappa-1) L), lambda = ln(1/eps_s): the
+    periodic images of the I1 kernel on the padded box are suppressed to
+    eps_s (Sec. 2.1 only fixes sigma = O(1/P)); c = sqrt(lambda) sigma, so that
+    p(c) = eps_s (Sec. 2.1: c is a multiple of sigma).
+  * radial rule: Gauss-Legendre on [0, c] with the polar Jacobian r folded into
+    the weight (the paper names a Gauss-Jacobi rule; both integrate the same
+    smooth radial integrand); azimuthal rule: trapezoid theta_j = 2 pi j/N_theta.
+  * I2 is complex in eq. 12; its real part is taken (the imaginary part is
+    zero by the k -> -k symmetry of the node set when N_theta is even).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+__all__ = [
+    "SplitParams",
+    "split_constants",
+    "grid_points",
+    "highfreq_multiplier",
+    "i1_padded_fft",
+    "i1_padded_dft_matrix",
+    "polar_nodes_weights",
+    "polar_rule",
+    "type2_direct",
+    "type1_direct",
+    "i2_direct",
+    "phi",
+    "phi_parts",
+    "phi_transpose",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class SplitParams:
+    """Discretisation of one potential solve.
+
+    n        grid points per side (even), spacing h, box [-L, L)^2 with L = n h / 2
+    n_r      radial Gauss nodes;  n_theta  azimuthal trapezoid nodes
+    kappa    zero-padding factor of the I1 box (Sec. 2.1: kappa >= 2)
+    sigma    partition width; cutoff  disk radius c (None -> default reading)
+    eps_split   target size of the neglected tails (defines the defaults)
+    component   "xx": multiplier -kx^2/|k|^2 (the DS potential, eq. 4);
+                "yy": -ky^2/|k|^2 (its companion; the two sum to -1)
+    """
+    n: int
+    h: float
+    n_r: int
+    n_theta: int
+    kappa: int = 2
+    sigma: float | None = None
+    cutoff: float | None = None
+    eps_split: float = 1e-16
+    component: str = "xx"
+
+    @property
+    def half_width(self) -> float:
+        return 0.5 * self.n * self.h
+
+
+def split_constants(p: SplitParams) -> tuple[float, float]:
+    """(sigma, c) following the reading of Sec. 2.1 stated in the module doc."""
+    lam = math.log(1.0 / p.eps_split)
+    sigma = p.sigma
+    if sigma is None:
+        sigma = math.sqrt(lam) / (2.0 * math.pi * (p.kappa - 1) * p.half_width)
+    c = p.cutoff
+    if c is None:
+        c = math.sqrt(lam) * sigma
+    return sigma, c
+
+
+def grid_points(p: SplitParams) -> np.ndarray:
+    """x_n = -L + n h, n = 0..N-1 (Sec. 2.1 and Sec. 3)."""
+    return -p.half_width + p.h * np.arange(p.n, dtype=np.float64)
+
+
+def highfreq_multiplier(kx: np.ndarray, ky: np.ndarray, sigma: float,
+                        component: str = "xx") -> np.ndarray:
+    """g1(k) = -(k_a^2/|k|^2) (1 - exp(-|k|^2/sigma^2)), g1(0) = 0.
+
+    The integrand of I1 (Sec. 2.1, eq. 9) divided by rho_hat.  1 - e^{-s} is
+    formed as -expm1(-s) so that it keeps full relative accuracy near k = 0."""
+    k2 = kx * kx + ky * ky
+    num = kx * kx if component == "xx" else ky * ky
+    out = np.zeros_like(k2)
+    nz = k2 > 0.0
+    out[nz] = -(num[nz] / k2[nz]) * (-np.expm1(-k2[nz] / sigma ** 2))
+    return out
+
+
+def _padded_frequencies(p: SplitParams) -> tuple[np.ndarray, np.ndarray]:
+    m_side = p.kappa * p.n
+    k = np.fft.fftfreq(m_side, d=p.h)           # k_m = m / (kappa N h)
+    ky, kx = np.meshgrid(k, k, indexing="ij")
+    return kx, ky
+
+
+def i1_padded_fft(rho: np.ndarray, p: SplitParams) -> np.ndarray:
+    """I1 on the grid (Sec. 2.1, eq. 9 by the trapezoidal rule on the padded box).
+
+    rho_hat(k_m) ~ h^2 sum_n rho_n e^{-2 pi i k_m.x_n} (trapezoid on B_p), the k
+    integral ~ (Delta k)^2 sum_m with Delta k = 1/(kappa N h); the phases only
+    involve x_n - x_n', so the density sits at the corner of the padded array:
+        I1_n = Re[(kappa N)^-2 sum_m g1(k_m) S_m e^{+2 pi i m.n/(kappa N)}],
+        S_m  = sum_n P_n e^{-2 pi i m.n/(kappa N)},  P = zero-padded rho."""
+    sigma, _ = split_constants(p)
+    m_side = p.kappa * p.n
+    padded = np.zeros((m_side, m_side), dtype=np.float64)
+    padded[: p.n, : p.n] = rho
+    s_hat = np.fft.fft2(padded)                      # S_m (unnormalised DFT)
+    kx, ky = _padded_frequencies(p)
+    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    full = np.fft.ifft2(g1 * s_hat)                  # includes (kappa N)^-2
+    return full[: p.n, : p.n].real.copy()
+
+
+def i1_padded_dft_matrix(rho: np.ndarray, p: SplitParams) -> np.ndarray:
+    """Same sum as i1_padded_fft written with explicit DFT matrices (small N only)."""
+    sigma, _ = split_constants(p)
+    m_side = p.kappa * p.n
+    m = np.arange(m_side)
+    n = np.arange(p.n)
+    fwd = np.exp(-2j * np.pi * np.outer(m, n) / m_side)    # [m][n]
+    s_hat = fwd @ rho @ fwd.T                               # S[m_y][m_x]
+    kx, ky = _padded_frequencies(p)
+    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    inv = np.exp(+2j * np.pi * np.outer(n, m) / m_side)    # [n][m]
+    return (inv @ (g1 * s_hat) @ inv.T).real / m_side ** 2
+
+
+def polar_nodes_weights(p: SplitParams):
+    """Radial Gauss-Legendre nodes/weights on [0, c] (Jacobian r folded into the
+    weight) and the azimuthal trapezoid nodes/weight (Sec. 2.1, eq. 12)."""
+    _, c = split_constants(p)
+    x, w = np.polynomial.legendre.leggauss(p.n_r)
+    r = 0.5 * c * (1.0 + x)
+    w_r = 0.5 * c * w * r
+    theta = 2.0 * np.pi * np.arange(p.n_theta) / p.n_theta
+    w_t = 2.0 * np.pi / p.n_theta
+    return r, w_r, theta, w_t
+
+
+def polar_rule(p: SplitParams):
+    """Polar nodes k_j and the I2 weights q_j (Sec. 2.1, eqs. 11-12).
+
+    Radial Gauss-Legendre on [0, c]: r_i = c (1 + x_i)/2 with weight
+    (c/2) w_i r_i (the Jacobian r of eq. 11 folded in); azimuthal trapezoid
+    theta_j = 2 pi j / N_theta with weight 2 pi / N_theta.  The I2 weight is
+        q_ij = -omega_i omega_j cos^2(theta_j) p(k_ij)      ("xx")
+    (sin^2 for "yy").  Returns flattened arrays kx, ky, q of length N_r N_theta
+    in (radial-major, angle-minor) order."""
+    sigma, _ = split_constants(p)
+    r, w_r, theta, w_t = polar_nodes_weights(p)
+    rr, tt = np.meshgrid(r, theta, indexing="ij")
+    kx = rr * np.cos(tt)
+    ky = rr * np.sin(tt)
+    ang = np.cos(tt) ** 2 if p.component == "xx" else np.sin(tt) ** 2
+    q = -(w_r[:, None] * w_t) * ang * np.exp(-(rr ** 2) / sigma ** 2)
+    return kx.ravel(), ky.ravel(), q.ravel()
+
+
+def type2_direct(rho: np.ndarray, h: float, xs: np.ndarray, kx: np.ndarray,
+                 ky: np.ndarray) -> np.ndarray:
+    """rho_hat(k_j) = h^2 sum_{n1,n2} rho[n2][n1] e^{-2 pi i (kx_j x_n1 + ky_j y_n2)}.
+
+    The trapezoidal rule applied to eq. 5 on the grid, at nonuniform k_j: the
+    type-2 sum of Sec. 2.2, eq. 16, evaluated directly (separably)."""
+    ex = np.exp(-2j * np.pi * np.outer(kx, xs))      # [j][n1]
+    ey = np.exp(-2j * np.pi * np.outer(ky, xs))      # [j][n2]
+    partial = ex @ rho.T                              # [j][n2] = sum_n1 ex rho[n2][n1]
+    return h * h * np.einsum("jn,jn->j", partial, ey)
+
+
+def type1_direct(coef: np.ndarray, xs: np.ndarray, kx: np.ndarray,
+                 ky: np.ndarray) -> np.ndarray:
+    """f[n2][n1] = sum_j coef_j e^{+2 pi i (kx_j x_n1 + ky_j y_n2)} (complex).
+
+    The type-1 sum of Sec. 2.2, eq. 15, evaluated directly (separably)."""
+    ex = np.exp(2j * np.pi * np.outer(kx, xs))       # [j][n1]
+    ey = np.exp(2j * np.pi * np.outer(ky, xs))       # [j][n2]
+    return (ey.T * coef[None, :]) @ ex                # [n2][n1]
+
+
+def i2_direct(rho: np.ndarray, p: SplitParams, return_imag: bool = False):
+    """I2 on the grid: eq. 12 with rho_hat from the direct type-2 sum."""
+    kx, ky, q = polar_rule(p)
+    xs = grid_points(p)
+    rho_hat = type2_direct(rho, p.h, xs, kx, ky)
+    field = type1_direct(q * rho_hat, xs, kx, ky)
+    if return_imag:
+        return field.real.copy(), field.imag.copy()
+    return field.real.copy()
+
+
+def phi_parts(rho: np.ndarray, p: SplitParams) -> dict:
+    """I1, I2, Phi = I1 + I2 (Sec. 2.1, eq. 8) and max |Im I2| as a diagnostic."""
+    rho = np.asarray(rho, dtype=np.float64)
+    if rho.shape != (p.n, p.n):
+        raise ValueError(f"rho must be {p.n}x{p.n}, got {rho.shape}")
+    i1 = i1_padded_fft(rho, p)
+    i2, i2_imag = i2_direct(rho, p, return_imag=True)
+    return {"i1": i1, "i2": i2, "phi": i1 + i2,
+            "max_imag_i2": float(np.max(np.abs(i2_imag)))}
+
+
+def phi(rho: np.ndarray, p: SplitParams) -> np.ndarray:
+    """Phi on the grid, FP64."""
+    return phi_parts(rho, p)["phi"]
+
+
+def phi_transpose(g: np.ndarray, p: SplitParams) -> np.ndarray:
+    """The literal transpose A^T g of the discrete operator A: rho -> Phi.
+
+    Not assumed symmetric: every factor is transposed and the order reversed.
+      A1 = crop . F^-1 . diag(g1) . F . pad  ->  A1^T = crop . F . diag(g1) . F^-1 . pad
+           (the 2-D DFT matrix F and F^-1 are symmetric; crop^T = pad).
+      A2 = Re(E1 . diag(q) . E2), E2[j][n] = h^2 e^{-2 pi i k_j.x_n},
+           E1[n][j] = e^{+2 pi i k_j.x_n}  ->  A2^T = Re(E2^T . diag(q) . E1^T).
+    For a complex matrix C acting on real vectors, (Re C)^T = Re(C^T)."""
+    g = np.asarray(g, dtype=np.float64)
+    sigma, _ = split_constants(p)
+    m_side = p.kappa * p.n
+    padded = np.zeros((m_side, m_side), dtype=np.float64)
+    padded[: p.n, : p.n] = g
+    kx, ky = _padded_frequencies(p)
+    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    a1t = np.fft.fft2(g1 * np.fft.ifft2(padded))[: p.n, : p.n].real
+
+    nkx, nky, q = polar_rule(p)
+    xs = grid_points(p)
+    e1t_x = np.exp(2j * np.pi * np.outer(nkx, xs))   # E1^T[j][n] factors
+    e1t_y = np.exp(2j * np.pi * np.outer(nky, xs))
+    s = np.einsum("jn,jn->j", e1t_x @ g.T, e1t_y)    # (E1^T g)_j
+    e2t_x = np.exp(-2j * np.pi * np.outer(nkx, xs))  # E2^T[n][j] = h^2 e^{-...}
+    e2t_y = np.exp(-2j * np.pi * np.outer(nky, xs))
+    a2t = (p.h * p.h) * ((e2t_y.T * (q * s)[None, :]) @ e2t_x)
+    return a1t + a2t.real
