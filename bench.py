@@ -1,0 +1,219 @@
+"""Throughput of the split potential solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: one density on a 2048 x 2048 grid over [-16, 16)^2, rho = |u|^2 with
+u a seeded sum of 8 anisotropic complex Gaussians (centres in [-6, 6]^2,
+widths in [0.5, 2], random phases; seed 0), 64 radial x 128 azimuthal polar
+nodes, NUFFT tolerance 1e-7 (FP32 data path) and 1e-12 (FP64 data path).
+
+A step is one potential solve Phi = I1 + I2 (every kernel of the chain) with
+rho already resident in device memory.  `value` is FP32 solves/s over K timed
+steps; the same line carries the FP64 rate, the FP32/FP64 ratio, the rate of
+forward + transposed solve pairs, the relative errors of both data paths
+against the FP64 oracle, the dominant kernel's HBM roofline figure (HIP events
+recorded around every kernel on its launch stream) and the oracle's own rate
+on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Φ solves/s at 2048² grid: FP32 vs FP64 at rel-err 1e-6; fwd+bwd solves/s"
+HBM_PEAK_GBS = 8000.0
+
+N = 2048
+HALF = 16.0
+N_R, N_THETA = 64, 128
+TOL32, TOL64 = 1e-7, 1e-12
+SEED = 0
+
+
+def kernel_bytes(info: dict, real_bytes: int) -> dict:
+    """Algorithmic HBM bytes of one launch of each kernel: what the kernel must
+    read and write at least (inputs once, outputs once), from the plan's sizes."""
+    n, q, m = info["n"], info["patch"], info["n_nodes"]
+    sr, sc = real_bytes, 2 * real_bytes
+    spec = (n + 1) * n * sc            # I1 half spectrum, N+1 columns of N values
+    return {
+        "rows_forward": n * n * sr + spec + q * n * sc,
+        "cols_highfreq": 2 * spec,
+        "cols_type2": q * n * sc + q * q * sc,
+        "interp": q * q * sc + m * sc + 3 * m * 8,
+        "spread": m * sc + q * q * sc + 2 * m * 8,
+        "cols_type1": q * q * sc + n * q * sc,
+        "rows_inverse": spec + n * q * sc + n * n * sr,
+    }
+
+
+def timed_rate(fn, steps: int, torch) -> float:
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def rel_errs(got: np.ndarray, ref: np.ndarray) -> dict:
+    return {"rel_linf": float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))),
+            "rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+
+
+def cpu_baseline(rho_used: np.ndarray):
+    """The FP64 oracle, as it is, on the host cores: one full solve of the same
+    2048^2 density (direct nonuniform sums through BLAS, I1 through numpy's FFT)."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+    except ImportError:          # pragma: no cover
+        threadpool_info = None
+    p = O.SplitParams(n=N, h=2 * HALF / N, n_r=N_R, n_theta=N_THETA)
+    # repeat whole solves until about 10 s of host time has been spent
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        ref = O.phi(rho_used, p)
+        runs += 1
+        if time.perf_counter() - t0 >= 10.0:
+            break
+    dt = (time.perf_counter() - t0) / runs
+    threads = 1
+    if threadpool_info is not None:
+        blas = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if blas:
+            threads = int(max(d.get("num_threads", 1) for d in blas))
+    return ref, {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+                 "sample": f"{runs} FP64 oracle solve(s) of the same 2048^2 density, {dt:.2f} s each ("
+                           f"{len(os.sched_getaffinity(0))} host cores visible)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (and the error figures that need it)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is not sharded "
+              "across GPUs in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    import paper_1409_2014_amd as ps
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    h = 2 * HALF / N
+    print(f"[bench] building the {N}x{N} density (seed {SEED})", file=sys.stderr, flush=True)
+    rho64 = W.mixture_density(N, HALF, W.draw_mixture(SEED))
+    rho32_dev = torch.as_tensor(rho64, dtype=torch.float32, device=dev)
+    # both data paths see the same (FP32-rounded) input, so one oracle run serves both
+    rho_used = rho32_dev.double().cpu().numpy()
+    rho64_dev = torch.as_tensor(rho_used, dtype=torch.float64, device=dev)
+
+    plan32 = ps.Plan(N, h, dtype=torch.float32, n_r=N_R, n_theta=N_THETA, tol=TOL32)
+    plan64 = ps.Plan(N, h, dtype=torch.float64, n_r=N_R, n_theta=N_THETA, tol=TOL64)
+    out32 = torch.empty_like(rho32_dev)
+    out64 = torch.empty_like(rho64_dev)
+    back32 = torch.empty_like(rho32_dev)
+    back64 = torch.empty_like(rho64_dev)
+
+    def fwd32():
+        plan32.solve(rho32_dev, out32)
+
+    def fwd64():
+        plan64.solve(rho64_dev, out64)
+
+    def pair32():
+        plan32.solve(rho32_dev, out32)
+        plan32.solve_adjoint(out32, back32)
+
+    def pair64():
+        plan64.solve(rho64_dev, out64)
+        plan64.solve_adjoint(out64, back64)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for fn in (fwd32, fwd64, pair32, pair64):
+        for _ in range(args.warmup):
+            fn()
+    torch.cuda.synchronize()
+
+    k = args.steps
+    print(f"[bench] timing {k} steps per leg", file=sys.stderr, flush=True)
+    t32 = timed_rate(fwd32, k, torch)
+    t64 = timed_rate(fwd64, k, torch)
+    tp32 = timed_rate(pair32, k, torch)
+    tp64 = timed_rate(pair64, k, torch)
+    phi32 = out32.double().cpu().numpy()
+    phi64 = out64.double().cpu().numpy()
+
+    # per-kernel durations from HIP events on the launch stream, FP32 data path
+    print("[bench] per-kernel event timing", file=sys.stderr, flush=True)
+    acc: dict[str, float] = {}
+    for _ in range(k):
+        for name, ms in plan32.solve_timed(rho32_dev, out32):
+            acc[name] = acc.get(name, 0.0) + ms
+    avg_ms = {name: v / k for name, v in acc.items()}
+    nbytes = kernel_bytes(plan32.info, 4)
+    dominant = max(avg_ms, key=avg_ms.get)
+    achieved = nbytes[dominant] / (avg_ms[dominant] * 1e-3) / 1e9
+    kernels = {name: {"avg_us": round(avg_ms[name] * 1e3, 2),
+                      "alg_bytes": nbytes.get(name),
+                      "gbs": round(nbytes[name] / (avg_ms[name] * 1e-3) / 1e9, 1) if name in nbytes else None}
+               for name in avg_ms}
+
+    result = {
+        "metric": METRIC,
+        "value": k / t32,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": k,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / k,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single potential solve, 2048x2048 grid over [-16,16)^2, 8-Gaussian mixture "
+                               "density (seed 0), 64x128 polar nodes, NUFFT tol 1e-7 (f32) / 1e-12 (f64)",
+                   "grid": N, "half_width": HALF, "n_r": N_R, "n_theta": N_THETA,
+                   "tol_f32": TOL32, "tol_f64": TOL64},
+        "fp64_solves_per_s": k / t64,
+        "fp32_over_fp64": t64 / t32,
+        "fwd_bwd_solves_per_s": {"f32": k / tp32, "f64": k / tp64},
+        "kernels_f32": kernels,
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle leg on the host cores", file=sys.stderr, flush=True)
+        ref, base = cpu_baseline(rho_used)
+        result["cpu_baseline"] = base
+        result["rel_err_vs_oracle"] = {"f32": rel_errs(phi32, ref), "f64": rel_errs(phi64, ref)}
+    plan32.close()
+    plan64.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

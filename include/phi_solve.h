@@ -1,0 +1,163 @@
+/*
+ * phi_solve.h -- C ABI of the MI355X (gfx950) solver for the nonlocal
+ * Davey-Stewartson potential
+ *
+ *     Phi = F^-1[ -kx^2/|k|^2 rho_hat ],   rho_hat(k) = int rho e^{-2 pi i k.x} dx
+ *
+ * (Mauser, Stimming, Zhang, "A novel nonlocal potential solver based on
+ * nonuniform FFT for efficient simulation of the Davey-Stewartson equations",
+ * Sec. 1, eqs. 4-5), evaluated with the split of Sec. 2.1, eqs. 8-12:
+ *
+ *   I1  high-frequency part: trapezoidal rule on the zero-padded box, i.e. a
+ *       padded 2-D FFT, the multiplier g1(k) = -(kx^2/|k|^2)(1 - e^{-|k|^2/sigma^2}),
+ *       and the inverse FFT (Sec. 2.1, eq. 9);
+ *   I2  low-frequency part: polar quadrature on the disk |k| <= c (radial
+ *       Gauss-Legendre x azimuthal trapezoid, eq. 12), where rho_hat at the
+ *       polar nodes is a type-2 NUFFT and the sum back onto the grid a type-1
+ *       NUFFT (Sec. 2.2, eqs. 15-16).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: N x N points x_n = -L + n h, n = 0..N-1, L = N h / 2 (the periodic
+ *     box [-L, L)^2; Sec. 3).  Arrays are row-major [iy][ix], x fastest,
+ *     contiguous, element type fixed by the plan's dtype (double or float).
+ *   - All array arguments of phi_solve* / phi_nodes_* are DEVICE pointers on
+ *     the plan's device, owned by the caller; they must not alias each other.
+ *   - Streams are passed as void* holding a hipStream_t (NULL = null stream).
+ *     Solves only enqueue work on that stream: they are asynchronous,
+ *     stream-ordered and never synchronize with the host.
+ *   - A plan owns its tables and workspace.  One solve may be in flight per
+ *     plan at a time (the workspace is shared): order solves on one stream, or
+ *     use one plan per concurrent stream.
+ *   - Errors are returned as phi_status; no C++ exception crosses the ABI.
+ *     phi_last_error() gives a human-readable message for the last failure.
+ */
+#ifndef PHI_SOLVE_H
+#define PHI_SOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct phi_plan_s* phi_plan_t;
+
+typedef enum {
+    PHI_OK = 0,
+    PHI_ERR_INVALID_ARG = 1,     /* NULL pointer, destroyed plan, bad size/spacing */
+    PHI_ERR_UNSUPPORTED = 2,     /* valid for the paper, not implemented here     */
+    PHI_ERR_TOL_UNREACHABLE = 3, /* NUFFT tolerance outside the dtype's range     */
+    PHI_ERR_OUT_OF_MEMORY = 4,   /* device or host allocation failed              */
+    PHI_ERR_DEVICE = 5,          /* a HIP call failed; see phi_last_error         */
+    PHI_ERR_INTERNAL = 6
+} phi_status;
+
+typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
+
+/* phi_params.flags */
+#define PHI_COMPONENT_Y 1u   /* multiplier -ky^2/|k|^2 instead of -kx^2/|k|^2 (their sum is -1) */
+
+/* Problem statement as the paper gives it (Sec. 2.1): the density on a uniform
+ * box with spacing, the padding factor kappa, the partition width sigma and
+ * disk radius c, the polar node counts and the NUFFT accuracy. */
+typedef struct {
+    int32_t nx, ny;        /* grid points per side; must be equal, a power of two, 8..4096      */
+    double hx, hy;         /* spacings; must be equal and > 0; box side = n h, centred at 0     */
+    int32_t n_r;           /* radial Gauss-Legendre nodes, 1..1024                              */
+    int32_t n_theta;       /* azimuthal trapezoid nodes, even, 2..4096                          */
+    double tol;            /* NUFFT relative accuracy: F64 [1e-15, 1e-1], F32 [1e-7, 1e-1]      */
+    int32_t pad;           /* zero-padding factor kappa of the I1 box; only 2 is supported      */
+    double sigma;          /* partition width (<= 0: sqrt(ln 1e16) / (2 pi (kappa-1) L))       */
+    double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
+    phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
+    uint32_t flags;        /* PHI_COMPONENT_Y                                                    */
+} phi_params;
+
+/* Derived quantities of a plan (filled by phi_describe / phi_plan_get_info). */
+typedef struct {
+    int32_t n;             /* grid side N                                        */
+    int32_t n_fine;        /* FFT / fine-grid side 2N                            */
+    int32_t n_nodes;       /* M = n_r * n_theta                                  */
+    int32_t kernel_width;  /* exponential-of-semicircle kernel width w (cells)   */
+    int32_t patch;         /* side Q of the fine-grid window the nodes touch     */
+    int32_t patch_lo;      /* lowest fine-grid index of that window (= -Q/2)     */
+    int32_t n_subproblems; /* bin-sorted node chunks used by interp / spread     */
+    int32_t bin_size;      /* bin side in fine-grid cells                        */
+    double h, half_width, sigma, cutoff, beta;
+    size_t device_bytes;   /* tables + workspace allocated by phi_plan           */
+} phi_plan_info;
+
+/* Fill *p with defaults for an n x n grid of spacing h: 64 x 128 polar nodes,
+ * kappa = 2, default sigma and c, tol 1e-12 (F64) or 1e-7 (F32). */
+phi_status phi_params_default(phi_params* p, int32_t n, double h, phi_dtype dtype);
+
+/* Validate *p and compute the derived quantities without touching a GPU. */
+phi_status phi_describe(const phi_params* p, phi_plan_info* info);
+
+/* Build a plan on the current HIP device: host-side FP64 tables (Gauss-Legendre
+ * nodes, polar weights, kernel deconvolution factors, twiddles, multiplier
+ * tables, bin sort) are computed and copied to device memory on `stream`.
+ * This is the only host-to-device transfer; the copy is complete on return. */
+phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out);
+
+/* Phi = A rho (Sec. 2.1, eq. 8: I1 + I2).  rho, phi: N x N device arrays. */
+phi_status phi_solve(phi_plan_t plan, const void* rho, void* phi, void* stream);
+
+/* g_rho = A^T g_phi: the transposed chain (every transform direction reversed:
+ * the grid-to-node NUFFT becomes the transpose of the node-to-grid one and vice
+ * versa, the diagonal multipliers are their own transposes).  Used for the
+ * gradient of a loss of Phi with respect to rho. */
+phi_status phi_solve_adjoint(phi_plan_t plan, const void* g_phi, void* g_rho, void* stream);
+
+/* Frees the plan's device memory after synchronizing its device.  NULL is a no-op. */
+phi_status phi_destroy(phi_plan_t plan);
+
+phi_status phi_plan_get_info(phi_plan_t plan, phi_plan_info* info);
+
+/* Host copies (FP64, plan order, M entries) of the polar nodes k_j (in the
+ * 2 pi convention of eq. 5) and the I2 weights q_j of eq. 12 (without h^2). */
+phi_status phi_plan_nodes(phi_plan_t plan, double* kx, double* ky, double* q);
+
+/* Type-2 stage alone (Sec. 2.2, eq. 16; the trapezoidal rule for eq. 5 at the
+ * polar nodes): rho_hat[j] = h^2 sum_n rho_n e^{-2 pi i k_j.x_n}, j in plan
+ * order.  rho: N x N device array; rho_hat: M interleaved (re, im) pairs. */
+phi_status phi_nodes_type2(phi_plan_t plan, const void* rho, void* rho_hat, void* stream);
+
+/* Type-1 stage alone (Sec. 2.2, eq. 15): field_n = Re sum_j coef_j e^{+2 pi i k_j.x_n}.
+ * coef: M interleaved (re, im) pairs in plan order; field: N x N device array. */
+phi_status phi_nodes_type1(phi_plan_t plan, const void* coef, void* field, void* stream);
+
+/* I1 alone (Sec. 2.1, eq. 9) and I2 alone (eq. 12); phi_solve = their sum. */
+phi_status phi_solve_highfreq(phi_plan_t plan, const void* rho, void* i1, void* stream);
+phi_status phi_solve_lowfreq(phi_plan_t plan, const void* rho, void* i2, void* stream);
+
+/* Measurement only: enqueues the same kernels as phi_solve (adjoint = 0) or
+ * phi_solve_adjoint (adjoint = 1) with a HIP event recorded on `stream` before
+ * each kernel and after the last, then waits for the stream.  Writes the
+ * number of kernels to *count and, for i < min(*count, capacity), the i-th
+ * kernel's duration in milliseconds to kernel_ms[i] and its name (a static
+ * string owned by the library) to names[i].  Unlike phi_solve it blocks the
+ * calling thread. */
+phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t adjoint, void* stream,
+                           float* kernel_ms, const char** names, int32_t capacity, int32_t* count);
+
+/* Host-only helpers used by the plan (exported for CPU tests). */
+phi_status phi_host_gauss_legendre(int32_t n, double* x, double* w);
+/* Exponential-of-semicircle kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| < 1,
+ * and its Fourier integral int_{-1}^{1} phi(z) cos(omega z) dz at omega[i]. */
+phi_status phi_host_es_kernel(int32_t count, const double* z, double beta, double* out);
+phi_status phi_host_es_transform(int32_t count, const double* omega, double beta, double* out);
+/* Polar nodes and q_j exactly as phi_plan builds them (plan order, without h^2). */
+phi_status phi_host_polar_nodes(const phi_params* p, double* kx, double* ky, double* q);
+
+const char* phi_status_string(phi_status s);
+/* Message of the last failure on this plan (plan != NULL) or of the last failure
+ * in this thread (plan == NULL).  Valid until the next call on the same object. */
+const char* phi_last_error(phi_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHI_SOLVE_H */

@@ -1,0 +1,115 @@
+"""ctypes declarations of the C ABI in include/phi_solve.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libphisolve.so")
+
+PHI_F64 = 0
+PHI_F32 = 1
+PHI_COMPONENT_Y = 1
+
+STATUS_NAMES = {
+    0: "PHI_OK", 1: "PHI_ERR_INVALID_ARG", 2: "PHI_ERR_UNSUPPORTED", 3: "PHI_ERR_TOL_UNREACHABLE",
+    4: "PHI_ERR_OUT_OF_MEMORY", 5: "PHI_ERR_DEVICE", 6: "PHI_ERR_INTERNAL",
+}
+
+
+class PhiParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+        ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("pad", ctypes.c_int32),
+        ("sigma", ctypes.c_double), ("cutoff", ctypes.c_double),
+        ("dtype", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class PhiPlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("n_fine", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+        ("kernel_width", ctypes.c_int32), ("patch", ctypes.c_int32), ("patch_lo", ctypes.c_int32),
+        ("n_subproblems", ctypes.c_int32), ("bin_size", ctypes.c_int32),
+        ("h", ctypes.c_double), ("half_width", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("cutoff", ctypes.c_double), ("beta", ctypes.c_double),
+        ("device_bytes", ctypes.c_size_t),
+    ]
+
+
+class PhiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.status_name = STATUS_NAMES.get(status, f"status {status}")
+        super().__init__(f"{self.status_name}: {message}")
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def _declare(lib):
+    st = ctypes.c_int
+    sig = {
+        "phi_params_default": (st, [ctypes.POINTER(PhiParams), ctypes.c_int32, ctypes.c_double, ctypes.c_int]),
+        "phi_describe": (st, [ctypes.POINTER(PhiParams), ctypes.POINTER(PhiPlanInfo)]),
+        "phi_plan": (st, [ctypes.POINTER(PhiParams), _P, ctypes.POINTER(_P)]),
+        "phi_solve": (st, [_P, _P, _P, _P]),
+        "phi_solve_adjoint": (st, [_P, _P, _P, _P]),
+        "phi_solve_highfreq": (st, [_P, _P, _P, _P]),
+        "phi_solve_lowfreq": (st, [_P, _P, _P, _P]),
+        "phi_nodes_type2": (st, [_P, _P, _P, _P]),
+        "phi_nodes_type1": (st, [_P, _P, _P, _P]),
+        "phi_destroy": (st, [_P]),
+        "phi_solve_timed": (st, [_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float),
+                                 ctypes.POINTER(ctypes.c_char_p), ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int32)]),
+        "phi_plan_get_info": (st, [_P, ctypes.POINTER(PhiPlanInfo)]),
+        "phi_plan_nodes": (st, [_P, _DP, _DP, _DP]),
+        "phi_host_gauss_legendre": (st, [ctypes.c_int32, _DP, _DP]),
+        "phi_host_es_kernel": (st, [ctypes.c_int32, _DP, ctypes.c_double, _DP]),
+        "phi_host_es_transform": (st, [ctypes.c_int32, _DP, ctypes.c_double, _DP]),
+        "phi_host_polar_nodes": (st, [ctypes.POINTER(PhiParams), _DP, _DP, _DP]),
+        "phi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "phi_last_error": (ctypes.c_char_p, [_P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1409_2014_amd.build_lib` "
+                "(the solver has no CPU fallback)")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def check(status: int, plan=None) -> None:
+    if status != 0:
+        msg = lib().phi_last_error(plan)
+        raise PhiError(status, msg.decode() if msg else "")
+
+
+def exported_symbols():
+    """Names declared by include/phi_solve.h that the binding uses."""
+    return [
+        "phi_params_default", "phi_describe", "phi_plan", "phi_solve", "phi_solve_adjoint",
+        "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1",
+        "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre",
+        "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",
+        "phi_status_string", "phi_last_error",
+    ]

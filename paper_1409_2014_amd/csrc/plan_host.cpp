@@ -1,0 +1,348 @@
+// Host-side plan construction (see plan_host.hpp).
+#include "plan_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+namespace phi {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+// Size of the neglected tails that fixes the default sigma and c (Sec. 2.1
+// leaves the constants to the cost trade-off sigma = O(1/P)): the periodic
+// images of the I1 kernel on the 2x padded box and the disk tail e^{-c^2/sigma^2}
+// are both exp(-lambda) with lambda = ln(1e16).
+constexpr double kLogInvEpsSplit = 36.841361487904734;  // ln(1e16)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+std::string fmt(const char* f, double a = 0, double b = 0) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), f, a, b);
+    return buf;
+}
+
+// Floor division / modulo for possibly negative numerators.
+int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+int posmod(int a, int b) { int r = a % b; return r < 0 ? r + b : r; }
+
+}  // namespace
+
+phi_status fill_defaults(phi_params* p, int32_t n, double h, phi_dtype dtype) {
+    if (!p) return PHI_ERR_INVALID_ARG;
+    p->nx = p->ny = n;
+    p->hx = p->hy = h;
+    p->n_r = 64;
+    p->n_theta = 128;
+    p->tol = (dtype == PHI_F32) ? 1e-7 : 1e-12;
+    p->pad = 2;
+    p->sigma = 0.0;
+    p->cutoff = 0.0;
+    p->dtype = dtype;
+    p->flags = 0;
+    return PHI_OK;
+}
+
+// Gauss-Legendre rule on [-1, 1], nodes ascending.  Newton's method is run on
+// the angle theta (x = cos theta) with P_n from the three-term recurrence
+// n P_n = (2n-1) x P_{n-1} - (n-1) P_{n-2} and the identity
+// (1 - x^2) P_n'(x) = n (P_{n-1} - x P_n); the weight
+// 2 / ((1 - x^2) P_n'^2) = 2 sin^2(theta) / (n (P_{n-1} - x P_n))^2 then never
+// forms 1 - x^2 by cancellation near the interval ends.
+void gauss_legendre(int n, double* x, double* w) {
+    auto legendre = [n](double z, double* pn, double* pn1) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        *pn = p1;
+        *pn1 = p0;
+    };
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double th = kPi * (i + 0.75) / (n + 0.5);
+        for (int it = 0; it < 100; ++it) {
+            double pn, pn1;
+            const double z = std::cos(th);
+            legendre(z, &pn, &pn1);
+            const double s = std::sin(th);
+            // d/dtheta P_n(cos theta) = -sin(theta) P_n'(x) = -n (P_{n-1} - x P_n) / sin(theta)
+            const double deriv = -n * (pn1 - z * pn) / s;
+            const double dth = pn / deriv;
+            th -= dth;
+            if (std::fabs(dth) < 1e-16) break;
+        }
+        double pn, pn1;
+        const double z = std::cos(th);
+        legendre(z, &pn, &pn1);
+        const double s = std::sin(th);
+        const double d = n * (pn1 - z * pn);
+        const double wi = 2.0 * s * s / (d * d);
+        x[i] = -z;            // theta increases from 0: the largest nodes come first
+        x[n - 1 - i] = z;
+        w[i] = wi;
+        w[n - 1 - i] = wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+double es_kernel(double z, double beta) {
+    if (!(std::fabs(z) < 1.0)) return 0.0;
+    return std::exp(beta * (std::sqrt(1.0 - z * z) - 1.0));
+}
+
+double es_transform(double omega, double beta) {
+    // phi is even: 2 int_0^1 phi(z) cos(omega z) dz by a 512-point Gauss rule on
+    // [0, 1].  The integrand is analytic inside the interval; the square-root
+    // branch points sit at z = +-1 where phi is e^{-beta}, far below rounding.
+    static thread_local std::vector<double> gx, gw;
+    const int nq = 512;
+    if (gx.empty()) {
+        gx.resize(nq);
+        gw.resize(nq);
+        gauss_legendre(nq, gx.data(), gw.data());
+    }
+    double s = 0.0;
+    for (int i = 0; i < nq; ++i) {
+        double z = 0.5 * (gx[i] + 1.0);
+        s += 0.5 * gw[i] * es_kernel(z, beta) * std::cos(omega * z);
+    }
+    return 2.0 * s;
+}
+
+phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
+    if (!p || !hp) { *err = "NULL argument"; return PHI_ERR_INVALID_ARG; }
+    if (p->nx != p->ny) { *err = "nx != ny: only square grids are implemented"; return PHI_ERR_UNSUPPORTED; }
+    if (!(p->hx > 0.0) || !(p->hy > 0.0) || !std::isfinite(p->hx) || !std::isfinite(p->hy)) {
+        *err = "spacing must be positive and finite"; return PHI_ERR_INVALID_ARG;
+    }
+    if (p->hx != p->hy) { *err = "hx != hy: only equal spacings are implemented"; return PHI_ERR_UNSUPPORTED; }
+    const int n = p->nx;
+    if (n < 2 || n % 2 != 0) { *err = fmt("grid side must be even and >= 2 (got %g)", n); return PHI_ERR_INVALID_ARG; }
+    if (!is_pow2(n) || n < (1 << (kMinLogFine - 1)) || n > (1 << (kMaxLogFine - 1))) {
+        *err = fmt("grid side %g: only powers of two from 8 to 4096 are implemented", n);
+        return PHI_ERR_UNSUPPORTED;
+    }
+    if (p->n_r < 1 || p->n_r > 1024) { *err = "n_r must be in [1, 1024]"; return PHI_ERR_INVALID_ARG; }
+    if (p->n_theta < 2 || p->n_theta > 4096 || p->n_theta % 2 != 0) {
+        *err = "n_theta must be even and in [2, 4096]"; return PHI_ERR_INVALID_ARG;
+    }
+    if (p->pad != 2 && p->pad != 0) {
+        if (p->pad < 2) { *err = "padding factor kappa must be >= 2"; return PHI_ERR_INVALID_ARG; }
+        *err = "only the padding factor kappa = 2 is implemented"; return PHI_ERR_UNSUPPORTED;
+    }
+    if (p->dtype != PHI_F64 && p->dtype != PHI_F32) { *err = "unknown dtype"; return PHI_ERR_INVALID_ARG; }
+    if (!(p->tol > 0.0) || !std::isfinite(p->tol)) { *err = "tol must be positive"; return PHI_ERR_INVALID_ARG; }
+    const double tol_min = (p->dtype == PHI_F32) ? 1e-7 : 1e-15;
+    if (p->tol < tol_min * (1.0 - 1e-9) || p->tol > 0.1) {
+        *err = fmt("tol %g outside [%g, 0.1] for this dtype", p->tol, tol_min);
+        return PHI_ERR_TOL_UNREACHABLE;
+    }
+    if ((p->flags & ~PHI_COMPONENT_Y) != 0) { *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG; }
+
+    hp->n = n;
+    hp->n_fine = 2 * n;
+    hp->log_fine = ilog2(2 * n);
+    hp->n_r = p->n_r;
+    hp->n_theta = p->n_theta;
+    hp->n_nodes = p->n_r * p->n_theta;
+    hp->component_y = (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
+    hp->dtype = p->dtype;
+    hp->h = p->hx;
+    hp->half_width = 0.5 * n * p->hx;
+    const int kappa = 2;
+    hp->sigma = (p->sigma > 0.0) ? p->sigma
+                                 : std::sqrt(kLogInvEpsSplit) / (2.0 * kPi * (kappa - 1) * hp->half_width);
+    hp->cutoff = (p->cutoff > 0.0) ? p->cutoff : std::sqrt(kLogInvEpsSplit) * hp->sigma;
+    if (!std::isfinite(hp->sigma) || !std::isfinite(hp->cutoff)) { *err = "sigma / cutoff not finite"; return PHI_ERR_INVALID_ARG; }
+
+    // Kernel width from the requested accuracy (published rule for the
+    // exponential-of-semicircle kernel at oversampling 2: w = ceil(log10 1/tol) + 1,
+    // beta = 2.30 w).
+    int w = static_cast<int>(std::ceil(std::log10(1.0 / p->tol) - 1e-9)) + 1;
+    w = std::max(2, std::min(kMaxKernelWidth, w));
+    hp->width = w;
+    hp->beta = 2.30 * w;
+
+    // Window of fine-grid cells touched by the kernel taps of the nodes.  The
+    // nodes lie in |k| <= c, i.e. within n_fine h c cells of the origin.
+    const double umax = hp->n_fine * hp->h * hp->cutoff;
+    int lmax = static_cast<int>(std::ceil(umax + 0.5 * w)) + 1;
+    int q = 16;
+    while (q / 2 < lmax + 1 && q < hp->n_fine) q *= 2;
+    if (q > hp->n_fine) q = hp->n_fine;
+    hp->patch = q;
+    hp->patch_lo = -q / 2;
+    return PHI_OK;
+}
+
+void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double>* ky,
+                 std::vector<double>* q) {
+    // Sec. 2.1, eq. 12: radial Gauss rule on [0, c] (r_i = c (1 + x_i)/2, weight
+    // (c/2) w_i r_i with the polar Jacobian folded in), azimuthal trapezoid
+    // theta_j = 2 pi j / N_theta with weight 2 pi / N_theta;
+    // q_ij = -w_r w_theta cos^2(theta_j) exp(-r_i^2 / sigma^2)   (sin^2 for the y component).
+    std::vector<double> gx(hp.n_r), gw(hp.n_r);
+    gauss_legendre(hp.n_r, gx.data(), gw.data());
+    const int m = hp.n_r * hp.n_theta;
+    kx->resize(m);
+    ky->resize(m);
+    q->resize(m);
+    const double wt = 2.0 * kPi / hp.n_theta;
+    for (int i = 0; i < hp.n_r; ++i) {
+        const double r = 0.5 * hp.cutoff * (1.0 + gx[i]);
+        const double wr = 0.5 * hp.cutoff * gw[i] * r;
+        const double damp = std::exp(-(r * r) / (hp.sigma * hp.sigma));
+        for (int j = 0; j < hp.n_theta; ++j) {
+            // angle 2 pi j / N_theta evaluated as pi * (2j / N_theta) in [0, 2 pi)
+            const double th = kPi * (2.0 * j / hp.n_theta);
+            const double cs = std::cos(th), sn = std::sin(th);
+            const double ang = hp.component_y ? sn * sn : cs * cs;
+            const int idx = i * hp.n_theta + j;
+            (*kx)[idx] = r * cs;
+            (*ky)[idx] = r * sn;
+            (*q)[idx] = -wr * wt * ang * damp;
+        }
+    }
+}
+
+phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) {
+    phi_status st = derive(p, hp, err);
+    if (st != PHI_OK) return st;
+    const int n = hp->n, nf = hp->n_fine, w = hp->width;
+    const double half_w = 0.5 * w;
+
+    // ---- polar nodes, positions in fine-grid cells, bin sort -------------------
+    std::vector<double> kx, ky, q;
+    polar_nodes(*hp, &kx, &ky, &q);
+    const int m = hp->n_nodes;
+    std::vector<double> ux(m), uy(m);
+    std::vector<int> l0x(m), l0y(m);
+    const int q_side = hp->patch, lo = hp->patch_lo;
+    for (int j = 0; j < m; ++j) {
+        // t_j / Delta with t_j = 2 pi h k_j, Delta = 2 pi / n_fine
+        ux[j] = nf * hp->h * kx[j];
+        uy[j] = nf * hp->h * ky[j];
+        int ax = static_cast<int>(std::ceil(ux[j] - half_w));
+        int ay = static_cast<int>(std::ceil(uy[j] - half_w));
+        // first tap, wrapped into [lo, lo + n_fine) (only matters when the window
+        // is the whole periodic fine grid)
+        ax = lo + posmod(ax - lo, nf);
+        ay = lo + posmod(ay - lo, nf);
+        if (q_side < nf && (ax + w - 1 >= lo + q_side || ay + w - 1 >= lo + q_side)) {
+            *err = "internal: node taps outside the fine-grid window";
+            return PHI_ERR_INTERNAL;
+        }
+        l0x[j] = ax;
+        l0y[j] = ay;
+    }
+    const int bin = kBinSize;
+    const int nb = (std::max(q_side, 1) + bin - 1) / bin;
+    std::vector<int> key(m);
+    for (int j = 0; j < m; ++j) {
+        int bx = floordiv(l0x[j] - lo, bin);
+        int by = floordiv(l0y[j] - lo, bin);
+        key[j] = by * nb + bx;
+    }
+    std::vector<int> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    hp->kx.resize(m); hp->ky.resize(m); hp->q.resize(m); hp->ux.resize(m); hp->uy.resize(m);
+    for (int i = 0; i < m; ++i) {
+        const int j = order[i];
+        hp->kx[i] = kx[j]; hp->ky[i] = ky[j]; hp->q[i] = q[j];
+        hp->ux[i] = ux[j]; hp->uy[i] = uy[j];
+    }
+    hp->sub.clear();
+    for (int i = 0; i < m;) {
+        const int k = key[order[i]];
+        int e = i;
+        while (e < m && key[order[e]] == k) ++e;
+        const int bx = k % nb, by = k / nb;
+        for (int s = i; s < e; s += kMaxNodesPerSub) {
+            hp->sub.push_back(lo + bx * bin);
+            hp->sub.push_back(lo + by * bin);
+            hp->sub.push_back(s);
+            hp->sub.push_back(std::min(kMaxNodesPerSub, e - s));
+        }
+        i = e;
+    }
+    hp->bin = bin;
+    hp->n_sub = static_cast<int>(hp->sub.size() / 4);
+
+    // ---- deconvolution factors 2 pi / (n_fine psi_hat(n')) ---------------------
+    // psi(x) = phi(x / a) with a = (w/2) Delta the kernel half-width in radians:
+    // psi_hat(k) = a int_{-1}^{1} phi(z) cos(k a z) dz.
+    hp->deconv.resize(n);
+    const double a_rad = half_w * 2.0 * kPi / nf;
+    for (int i = 0; i < n; ++i) {
+        const int np = i - n / 2;
+        const double ph = a_rad * es_transform(np * a_rad, hp->beta);
+        hp->deconv[i] = 2.0 * kPi / (nf * ph);
+    }
+
+    // ---- I1 multiplier tables --------------------------------------------------
+    const double s2 = hp->sigma * hp->sigma;
+    hp->gx.resize(2 * (n + 1));
+    for (int m1 = 0; m1 <= n; ++m1) {
+        const double k = m1 / (nf * hp->h);
+        const double a = k * k / s2;
+        hp->gx[2 * m1] = a;
+        hp->gx[2 * m1 + 1] = -std::expm1(-a);
+    }
+    hp->gy.resize(2 * nf);
+    for (int m2 = 0; m2 < nf; ++m2) {
+        const int ms = (m2 < nf / 2) ? m2 : m2 - nf;
+        const double k = ms / (nf * hp->h);
+        const double b = k * k / s2;
+        hp->gy[2 * m2] = b;
+        hp->gy[2 * m2 + 1] = -std::expm1(-b);
+    }
+
+    // ---- twiddles, two-level: e^{-2 pi i m / n_fine} for m < S and m = k S -----
+    const int lg = hp->log_fine;
+    hp->tw_lo_log = (lg + 1) / 2;
+    const int s_lo = 1 << hp->tw_lo_log;
+    const int s_hi = nf / s_lo;
+    hp->tw_lo.resize(2 * s_lo);
+    hp->tw_hi.resize(2 * s_hi);
+    auto expi = [&](long long mm, double* out) {
+        // e^{-2 pi i mm / nf} with the angle reduced to the first octant so that
+        // sin/cos see arguments in [0, pi/4]
+        const long long r = ((mm % nf) + nf) % nf;
+        const long long e8 = 8 * r;                 // angle in units of 2 pi / (8 nf)
+        const long long oct = e8 / nf;              // octant 0..7
+        const double frac = static_cast<double>(e8 - oct * nf) / nf;  // [0, 1)
+        const double th = frac * (kPi / 4.0);
+        double c = std::cos(th), s = std::sin(th);
+        double cr, sr;  // cos, sin of the full angle
+        const double cq = std::cos(kPi / 4.0 - th), sq = std::sin(kPi / 4.0 - th);
+        switch (oct) {
+            case 0: cr = c; sr = s; break;
+            case 1: cr = sq; sr = cq; break;
+            case 2: cr = -s; sr = c; break;
+            case 3: cr = -cq; sr = sq; break;
+            case 4: cr = -c; sr = -s; break;
+            case 5: cr = -sq; sr = -cq; break;
+            case 6: cr = s; sr = -c; break;
+            default: cr = cq; sr = -sq; break;
+        }
+        out[0] = cr;
+        out[1] = -sr;
+    };
+    for (int i = 0; i < s_lo; ++i) expi(i, &hp->tw_lo[2 * i]);
+    for (int k = 0; k < s_hi; ++k) expi(static_cast<long long>(k) * s_lo, &hp->tw_hi[2 * k]);
+    return PHI_OK;
+}
+
+}  // namespace phi

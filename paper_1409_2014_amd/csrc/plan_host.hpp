@@ -1,0 +1,65 @@
+// Host-side (CPU, FP64) construction of a solve plan: parameter defaults and
+// validation, the polar quadrature of Sec. 2.1 (eq. 12), the NUFFT kernel and
+// its deconvolution factors, the I1 multiplier tables, FFT twiddles and the
+// bin sort of the polar nodes.  No HIP calls: everything here runs and is
+// tested without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "phi_solve.h"
+
+namespace phi {
+
+constexpr int kMaxLogFine = 13;        // fine grid up to 8192 (N up to 4096)
+constexpr int kMinLogFine = 4;         // fine grid from 16 (N from 8)
+constexpr int kBinSize = 8;            // bin side in fine-grid cells
+constexpr int kMaxNodesPerSub = 64;    // nodes per interp / spread subproblem
+constexpr int kMaxKernelWidth = 16;
+
+struct HostPlan {
+    // problem
+    int n = 0;            // grid side N
+    int n_fine = 0;       // FFT side 2N (kappa = 2, NUFFT oversampling 2)
+    int log_fine = 0;
+    int n_r = 0, n_theta = 0, n_nodes = 0;
+    int component_y = 0;
+    phi_dtype dtype = PHI_F64;
+    double h = 0, half_width = 0, sigma = 0, cutoff = 0;
+    // NUFFT kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1, z = offset / (w/2)
+    int width = 0;
+    double beta = 0;
+    // fine-grid window touched by the nodes' kernel taps: [patch_lo, patch_lo + patch)
+    int patch = 0, patch_lo = 0;
+    // bin sort
+    int bin = kBinSize, n_sub = 0;
+
+    // node data in plan order (bin-sorted)
+    std::vector<double> kx, ky, q;      // k_j and q_j of eq. 12 (q without h^2)
+    std::vector<double> ux, uy;         // node positions in fine-grid cells: n_fine h k
+    std::vector<int32_t> sub;           // per subproblem: tile_lo1, tile_lo2, first node, count
+    // tables
+    std::vector<double> deconv;         // [N] 2 pi / (n_fine psi_hat(n')), n' = i - N/2
+    std::vector<double> gx;             // [2 (N+1)] (a, 1 - e^{-a}),  a = kx^2 / sigma^2, kx = m/(n_fine h)
+    std::vector<double> gy;             // [2 n_fine] (b, 1 - e^{-b}), signed frequency
+    std::vector<double> tw_lo, tw_hi;   // (re, im) of e^{-2 pi i m / n_fine}: m < S and m = k S
+    int tw_lo_log = 0;
+};
+
+phi_status fill_defaults(phi_params* p, int32_t n, double h, phi_dtype dtype);
+// Checks the parameters and derives the scalar quantities (no tables).
+phi_status derive(const phi_params* p, HostPlan* hp, std::string* err);
+// derive() plus every table.
+phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err);
+
+void gauss_legendre(int n, double* x, double* w);
+double es_kernel(double z, double beta);
+// int_{-1}^{1} phi(z) cos(omega z) dz
+double es_transform(double omega, double beta);
+// Polar nodes and weights in the natural (radial-major) order.
+void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double>* ky,
+                 std::vector<double>* q);
+
+}  // namespace phi

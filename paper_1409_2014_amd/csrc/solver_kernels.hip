@@ -1,0 +1,596 @@
+// HIP kernels of the split potential solve for gfx950 (see phi_solve.h).
+//
+// One solve runs seven stream-ordered kernels (N = grid side, F = 2N the side
+// of both the zero-padded I1 box and the NUFFT fine grid, Q = side of the
+// fine-grid window the polar nodes touch):
+//
+//   rows_forward   per grid row: z = rho + i rho d(n1) d(n2) at centred
+//                  positions, one F-point FFT, then split the two real
+//                  transforms: the I1 half spectrum (N+1 values) goes to the
+//                  column-major buffer XT, the type-2 window (Q values) to TT.
+//                  [Sec. 2.1, eq. 9 zero-padded FFT; Sec. 2.2 type 2: deconvolve + FFT]
+//   cols_highfreq  per spectrum column: F-point FFT, times g1(k)/F^2, inverse
+//                  FFT, keep the N centred rows, in place in XT.   [eq. 9]
+//   cols_type2     per window column of TT: F-point FFT, keep the Q window rows.
+//   interp         per bin-sorted subproblem: stage the fine-grid tile in LDS,
+//                  interpolate rho_hat(k_j) = h^2 sum_taps b psi psi with 16-lane
+//                  reductions, multiply by q_j.             [eq. 12, a_j = q_j rho_hat_j]
+//   spread         per subproblem: the transposed taps accumulate a_j psi psi
+//                  into an LDS tile (compensated sums in FP32), then the tile
+//                  is added to the fine-grid window with atomics.  [type 1 spreading]
+//   cols_type1     per window column: F-point FFT of the spread window (only Q
+//                  non-zero inputs), keep the N centred rows, times d(n2).
+//   rows_inverse   per grid row: rebuild the full Hermitian I1 row spectrum plus
+//                  i times the Hermitian part of the type-1 row, one F-point
+//                  FFT; Phi = Re + Im d(n1).       [eq. 8: Phi = I1 + Re I2]
+//
+// The transposed solve runs the same kernels with every FFT direction reversed.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "fft_lds.hpp"
+#include "solver_kernels.hpp"
+
+namespace phi {
+
+namespace {
+
+__device__ __forceinline__ int posmod_dev(int a, int b) {
+    int r = a % b;
+    return r < 0 ? r + b : r;
+}
+
+// Centred grid index n (0..N-1, n' = n - N/2) -> position n' mod F on the fine grid.
+template <int LOG>
+__device__ __forceinline__ int centred_pos(int n) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    return (n - N / 2) & (F - 1);
+}
+
+// Inverse of centred_pos: position p -> grid index, or -1 for a padding position.
+template <int LOG>
+__device__ __forceinline__ int pos_to_grid(int p) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    if (p < N / 2) return p + N / 2;
+    if (p >= F - N / 2) return p - (F - N / 2);
+    return -1;
+}
+
+template <int LOG>
+constexpr int threads_for() {
+    constexpr int F = 1 << LOG;
+    return (F / 16 < 64) ? 64 : (F / 16 > 256 ? 256 : F / 16);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// rows_forward
+// ---------------------------------------------------------------------------
+template <typename R, int LOG, int NT>
+__global__ __launch_bounds__(NT) void k_rows_forward(DevPlan P, const R* __restrict__ rho, R dir) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    __shared__ cpx<R> buf[lds_padded_size(F)];
+    __shared__ TwiddleLds<R, LOG> tw;
+    const int tid = threadIdx.x;
+    const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    const double dy = P.deconv[row];
+    const R* src = rho + static_cast<size_t>(row) * N;
+    for (int p = tid; p < F; p += NT) {
+        const int n1 = pos_to_grid<LOG>(p);
+        cpx<R> z = {R(0), R(0)};
+        if (n1 >= 0) {
+            const R r = src[n1];
+            z.x = r;
+            z.y = static_cast<R>(static_cast<double>(r) * P.deconv[n1] * dy);
+        }
+        buf[lds_pad(p)] = z;
+    }
+    __syncthreads();
+    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+    // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2, m = 0..N
+    cpx<R>* xt = static_cast<cpx<R>*>(P.xt);
+    for (int m = tid; m <= N; m += NT) {
+        const cpx<R> a = buf[lds_pad(m)];
+        const cpx<R> b = buf[lds_pad((F - m) & (F - 1))];
+        xt[static_cast<size_t>(m) * N + row] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+    }
+    // transform of the imaginary part on the window: (Z[l] - conj Z[-l]) / (2i)
+    cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
+    for (int i = tid; i < P.patch; i += NT) {
+        const int l = P.patch_lo + i;
+        const cpx<R> a = buf[lds_pad(l & (F - 1))];
+        const cpx<R> b = buf[lds_pad((-l) & (F - 1))];
+        tt[static_cast<size_t>(i) * N + row] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cols_highfreq: FFT along y, multiplier, inverse FFT along y (in place in XT)
+// ---------------------------------------------------------------------------
+template <typename R, int LOG, int NT>
+__global__ __launch_bounds__(NT) void k_cols_highfreq(DevPlan P, R dir) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    __shared__ cpx<R> buf[lds_padded_size(F)];
+    __shared__ TwiddleLds<R, LOG> tw;
+    const int tid = threadIdx.x;
+    const int m1 = xcd_logical_block(blockIdx.x, gridDim.x);   // 0..N
+    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(m1) * N;
+    for (int p = tid; p < F; p += NT) {
+        const int n2 = pos_to_grid<LOG>(p);
+        buf[lds_pad(p)] = (n2 >= 0) ? col[n2] : cpx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+    // g1 = -(k_a^2/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with
+    // 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a}, B = 1 - e^{-b} (all terms >= 0)
+    const R a = static_cast<R>(P.gx[2 * m1]);
+    const R A = static_cast<R>(P.gx[2 * m1 + 1]);
+    const R scale = static_cast<R>(P.inv_f2);
+    for (int m2 = tid; m2 < F; m2 += NT) {
+        const R b = static_cast<R>(P.gy[2 * m2]);
+        const R B = static_cast<R>(P.gy[2 * m2 + 1]);
+        const R num = P.component_y ? b : a;
+        const R den = a + b;
+        const R g = (den > R(0)) ? -(num / den) * (A + B - A * B) * scale : R(0);
+        const int idx = lds_pad(m2);
+        buf[idx] = cscale(buf[idx], g);
+    }
+    __syncthreads();
+    fft_lds<R, LOG, NT>(buf, tw, tid, -dir);
+    for (int n2 = tid; n2 < N; n2 += NT) col[n2] = buf[lds_pad(centred_pos<LOG>(n2))];
+}
+
+// ---------------------------------------------------------------------------
+// cols_type2: FFT along y of the type-2 row window, keep the Q window rows
+// ---------------------------------------------------------------------------
+template <typename R, int LOG, int NT>
+__global__ __launch_bounds__(NT) void k_cols_type2(DevPlan P, R dir) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    __shared__ cpx<R> buf[lds_padded_size(F)];
+    __shared__ TwiddleLds<R, LOG> tw;
+    const int tid = threadIdx.x;
+    const int i1 = blockIdx.x;
+    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(i1) * N;
+    for (int p = tid; p < F; p += NT) {
+        const int n2 = pos_to_grid<LOG>(p);
+        buf[lds_pad(p)] = (n2 >= 0) ? col[n2] : cpx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+    cpx<R>* win = static_cast<cpx<R>*>(P.win);
+    for (int i2 = tid; i2 < P.patch; i2 += NT)
+        win[static_cast<size_t>(i2) * P.patch + i1] = buf[lds_pad((P.patch_lo + i2) & (F - 1))];
+}
+
+// ---------------------------------------------------------------------------
+// cols_type1: inverse-direction FFT along y of the spread window, times d(n2)
+// ---------------------------------------------------------------------------
+template <typename R, int LOG, int NT>
+__global__ __launch_bounds__(NT) void k_cols_type1(DevPlan P, R dir) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    __shared__ cpx<R> buf[lds_padded_size(F)];
+    __shared__ TwiddleLds<R, LOG> tw;
+    const int tid = threadIdx.x;
+    const int i1 = blockIdx.x;
+    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    for (int p = tid; p < F; p += NT) buf[lds_pad(p)] = {R(0), R(0)};
+    __syncthreads();
+    const cpx<R>* win = static_cast<const cpx<R>*>(P.spread);
+    for (int i2 = tid; i2 < P.patch; i2 += NT)
+        buf[lds_pad((P.patch_lo + i2) & (F - 1))] = win[static_cast<size_t>(i2) * P.patch + i1];
+    __syncthreads();
+    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+    cpx<R>* u = static_cast<cpx<R>*>(P.u);
+    for (int n2 = tid; n2 < N; n2 += NT) {
+        const cpx<R> v = buf[lds_pad(centred_pos<LOG>(n2))];
+        const double d = P.deconv[n2];
+        u[static_cast<size_t>(n2) * P.patch + i1] = {static_cast<R>(v.x * d), static_cast<R>(v.y * d)};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rows_inverse: Phi row = Re IFFT(S1 + i H) + Im IFFT(S1 + i H) d(n1)
+// ---------------------------------------------------------------------------
+template <typename R, int LOG, int NT>
+__global__ __launch_bounds__(NT) void k_rows_inverse(DevPlan P, R* __restrict__ out, R dir, int use_i1,
+                                                      int use_i2) {
+    constexpr int F = 1 << LOG;
+    constexpr int N = F / 2;
+    __shared__ cpx<R> buf[lds_padded_size(F)];
+    __shared__ TwiddleLds<R, LOG> tw;
+    const int tid = threadIdx.x;
+    const int row = xcd_logical_block(blockIdx.x, gridDim.x);
+    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    const cpx<R>* xt = static_cast<const cpx<R>*>(P.xt);
+    const cpx<R>* urow = static_cast<const cpx<R>*>(P.u) + static_cast<size_t>(row) * P.patch;
+    const int q = P.patch;
+    for (int p = tid; p < F; p += NT) {
+        cpx<R> v = {R(0), R(0)};
+        if (use_i1) {
+            // Hermitian extension of the real row's half spectrum
+            if (p <= N) {
+                v = xt[static_cast<size_t>(p) * N + row];
+            } else {
+                v = cconj(xt[static_cast<size_t>(F - p) * N + row]);
+            }
+        }
+        if (use_i2) {
+            const int l = (p < F / 2) ? p : p - F;          // signed fine-grid index
+            const int i = posmod_dev(l - P.patch_lo, F);
+            if (i < q) {
+                const cpx<R> ua = urow[i];
+                const int im = posmod_dev(-l - P.patch_lo, F);
+                const cpx<R> ub = (im < q) ? urow[im] : cpx<R>{R(0), R(0)};
+                // Hermitian part H = (U[l] + conj U[-l]) / 2; add i H
+                const cpx<R> hh = {R(0.5) * (ua.x + ub.x), R(0.5) * (ua.y - ub.y)};
+                v.x -= hh.y;
+                v.y += hh.x;
+            }
+        }
+        buf[lds_pad(p)] = v;
+    }
+    __syncthreads();
+    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+    R* dst = out + static_cast<size_t>(row) * N;
+    for (int n1 = tid; n1 < N; n1 += NT) {
+        const cpx<R> z = buf[lds_pad(centred_pos<LOG>(n1))];
+        dst[n1] = static_cast<R>(static_cast<double>(z.x) + static_cast<double>(z.y) * P.deconv[n1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel taps of the bin-sorted subproblems
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kSubThreads = 256;
+constexpr int kTileMax = kBinSize + kMaxKernelWidth - 1;
+
+template <typename R>
+struct SubLds {
+    cpx<R> tile[kTileMax * kTileMax];
+    R psx[kMaxNodesPerSub][kMaxKernelWidth];
+    R psy[kMaxNodesPerSub][kMaxKernelWidth];
+    int offx[kMaxNodesPerSub];
+    int offy[kMaxNodesPerSub];
+    cpx<R> val[kMaxNodesPerSub];
+};
+
+__device__ __forceinline__ double es_kernel_dev(double z, double beta) {
+    return (fabs(z) < 1.0) ? exp(beta * (sqrt(1.0 - z * z) - 1.0)) : 0.0;
+}
+
+// Kernel values psi(u_j - l) for the w taps l = l0 .. l0+w-1 of every node of
+// the subproblem (separable in x and y), and each node's first-tap offset in
+// the tile.  FP64 evaluation, stored in the data precision.
+template <typename R>
+__device__ void subproblem_taps(const DevPlan& P, SubLds<R>& s, int tile_lo1, int tile_lo2, int first,
+                                int count) {
+    const int w = P.width;
+    const double half = 0.5 * w;
+    const int F = P.n_fine;
+    for (int e = threadIdx.x; e < count * w * 2; e += kSubThreads) {
+        const int axis = e / (count * w);
+        const int r = e - axis * count * w;
+        const int jj = r / w;
+        const int t = r - jj * w;
+        const int j = first + jj;
+        const double u = axis ? P.uy[j] : P.ux[j];
+        const int l0 = static_cast<int>(ceil(u - half));
+        const R v = static_cast<R>(es_kernel_dev((u - (l0 + t)) / half, P.beta));
+        if (axis == 0) {
+            s.psx[jj][t] = v;
+            if (t == 0) s.offx[jj] = P.patch_lo + posmod_dev(l0 - P.patch_lo, F) - tile_lo1;
+        } else {
+            s.psy[jj][t] = v;
+            if (t == 0) s.offy[jj] = P.patch_lo + posmod_dev(l0 - P.patch_lo, F) - tile_lo2;
+        }
+    }
+}
+
+}  // namespace
+
+// rho_hat_j = h^2 sum_taps b[l] psi(u_jx - l1) psi(u_jy - l2); a_j = q_j rho_hat_j
+// (mode 0: q_j h^2 from the plan; mode 1: h^2 only, for the type-2 entry point).
+template <typename R>
+__global__ __launch_bounds__(kSubThreads) void k_interp(DevPlan P, cpx<R>* __restrict__ out, int mode) {
+    __shared__ SubLds<R> s;
+    const int* sub = P.sub + 4 * blockIdx.x;
+    const int lo1 = sub[0], lo2 = sub[1], first = sub[2], count = sub[3];
+    const int w = P.width;
+    const int E = P.bin + w - 1;
+    const int F = P.n_fine;
+    const int q = P.patch;
+    const cpx<R>* win = static_cast<const cpx<R>*>(P.win);
+    // clear the spread target for the next stage of the solve
+    {
+        cpx<R>* sp = static_cast<cpx<R>*>(P.spread);
+        const int total = q * q;
+        for (int i = blockIdx.x * kSubThreads + threadIdx.x; i < total; i += gridDim.x * kSubThreads)
+            sp[i] = {R(0), R(0)};
+    }
+    for (int c = threadIdx.x; c < E * E; c += kSubThreads) {
+        const int ca = c % E, cb = c / E;
+        const int wi1 = posmod_dev(lo1 + ca - P.patch_lo, F);
+        const int wi2 = posmod_dev(lo2 + cb - P.patch_lo, F);
+        s.tile[c] = (wi1 < q && wi2 < q) ? win[static_cast<size_t>(wi2) * q + wi1] : cpx<R>{R(0), R(0)};
+    }
+    subproblem_taps<R>(P, s, lo1, lo2, first, count);
+    __syncthreads();
+    // 16 lanes per node, tree reduction over the lanes of the group
+    const int lane = threadIdx.x & 15;
+    const int group = threadIdx.x >> 4;
+    const int ntap = w * w;
+    for (int jj0 = 0; jj0 < count; jj0 += kSubThreads / 16) {
+        const int jj = jj0 + group;
+        cpx<R> acc = {R(0), R(0)};
+        if (jj < count) {
+            const int ox = s.offx[jj], oy = s.offy[jj];
+            for (int t = lane; t < ntap; t += 16) {
+                const int ay = t / w;
+                const int ax = t - ay * w;
+                const R k = s.psx[jj][ax] * s.psy[jj][ay];
+                const cpx<R> b = s.tile[(oy + ay) * E + ox + ax];
+                acc.x += b.x * k;
+                acc.y += b.y * k;
+            }
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            acc.x += __shfl_xor(acc.x, off, 16);
+            acc.y += __shfl_xor(acc.y, off, 16);
+        }
+        if (jj < count && lane == 0) {
+            const int j = first + jj;
+            const double scale = (mode == 0) ? P.q[j] * P.h2 : P.h2;
+            out[j] = {static_cast<R>(acc.x * scale), static_cast<R>(acc.y * scale)};
+        }
+    }
+}
+
+// b[l] += sum_j a_j psi(l1 - u_jx) psi(l2 - u_jy) over the subproblem's nodes:
+// each thread owns tile cells and sums the taps that land on them (compensated
+// summation in FP32), then the tile is added to the fine-grid window.
+template <typename R>
+__global__ __launch_bounds__(kSubThreads) void k_spread(DevPlan P, const cpx<R>* __restrict__ coef) {
+    __shared__ SubLds<R> s;
+    const int* sub = P.sub + 4 * blockIdx.x;
+    const int lo1 = sub[0], lo2 = sub[1], first = sub[2], count = sub[3];
+    const int w = P.width;
+    const int E = P.bin + w - 1;
+    const int F = P.n_fine;
+    const int q = P.patch;
+    subproblem_taps<R>(P, s, lo1, lo2, first, count);
+    for (int jj = threadIdx.x; jj < count; jj += kSubThreads) s.val[jj] = coef[first + jj];
+    __syncthreads();
+    R* win = static_cast<R*>(P.spread);
+    for (int c = threadIdx.x; c < E * E; c += kSubThreads) {
+        const int ca = c % E, cb = c / E;
+        R sx = 0, sy = 0, cx = 0, cy = 0;   // sums and compensations
+        bool any = false;
+        for (int jj = 0; jj < count; ++jj) {
+            const int ax = ca - s.offx[jj];
+            const int ay = cb - s.offy[jj];
+            if (static_cast<unsigned>(ax) < static_cast<unsigned>(w) &&
+                static_cast<unsigned>(ay) < static_cast<unsigned>(w)) {
+                const R k = s.psx[jj][ax] * s.psy[jj][ay];
+                const R vx = s.val[jj].x * k;
+                const R vy = s.val[jj].y * k;
+                any = true;
+                if constexpr (sizeof(R) == 4) {
+                    const R yx = vx - cx, tx = sx + yx;
+                    cx = (tx - sx) - yx;
+                    sx = tx;
+                    const R yy = vy - cy, ty = sy + yy;
+                    cy = (ty - sy) - yy;
+                    sy = ty;
+                } else {
+                    sx += vx;
+                    sy += vy;
+                }
+            }
+        }
+        if (any) {
+            const int wi1 = posmod_dev(lo1 + ca - P.patch_lo, F);
+            const int wi2 = posmod_dev(lo2 + cb - P.patch_lo, F);
+            if (wi1 < q && wi2 < q) {
+                R* dst = win + 2 * (static_cast<size_t>(wi2) * q + wi1);
+                atomicAdd(dst, sx - cx);
+                atomicAdd(dst + 1, sy - cy);
+            }
+        }
+    }
+}
+
+// Fill kernel (used instead of a memset so the solve chain can be captured in
+// a graph).
+template <typename T>
+__global__ void k_fill_zero(T* __restrict__ p, size_t count) {
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename R, int LOG>
+hipError_t launch_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
+    constexpr int NT = threads_for<LOG>();
+    hipLaunchKernelGGL((k_rows_forward<R, LOG, NT>), dim3(P.n), dim3(NT), 0, s, P,
+                       static_cast<const R*>(rho), dir);
+    return hipGetLastError();
+}
+
+template <typename R, int LOG>
+hipError_t launch_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
+    constexpr int NT = threads_for<LOG>();
+    hipLaunchKernelGGL((k_cols_highfreq<R, LOG, NT>), dim3(P.n + 1), dim3(NT), 0, s, P, dir);
+    return hipGetLastError();
+}
+
+template <typename R, int LOG>
+hipError_t launch_cols_type2(const DevPlan& P, R dir, hipStream_t s) {
+    constexpr int NT = threads_for<LOG>();
+    hipLaunchKernelGGL((k_cols_type2<R, LOG, NT>), dim3(P.patch), dim3(NT), 0, s, P, dir);
+    return hipGetLastError();
+}
+
+template <typename R, int LOG>
+hipError_t launch_cols_type1(const DevPlan& P, R dir, hipStream_t s) {
+    constexpr int NT = threads_for<LOG>();
+    hipLaunchKernelGGL((k_cols_type1<R, LOG, NT>), dim3(P.patch), dim3(NT), 0, s, P, dir);
+    return hipGetLastError();
+}
+
+template <typename R, int LOG>
+hipError_t launch_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int use_i2, hipStream_t s) {
+    constexpr int NT = threads_for<LOG>();
+    hipLaunchKernelGGL((k_rows_inverse<R, LOG, NT>), dim3(P.n), dim3(NT), 0, s, P, static_cast<R*>(out), dir,
+                       use_i1, use_i2);
+    return hipGetLastError();
+}
+
+#define PHI_DISPATCH_LOG(LOGV, CALL)        \
+    switch (LOGV) {                         \
+        case 4: { constexpr int L_ = 4; return CALL; }   \
+        case 5: { constexpr int L_ = 5; return CALL; }   \
+        case 6: { constexpr int L_ = 6; return CALL; }   \
+        case 7: { constexpr int L_ = 7; return CALL; }   \
+        case 8: { constexpr int L_ = 8; return CALL; }   \
+        case 9: { constexpr int L_ = 9; return CALL; }   \
+        case 10: { constexpr int L_ = 10; return CALL; } \
+        case 11: { constexpr int L_ = 11; return CALL; } \
+        case 12: { constexpr int L_ = 12; return CALL; } \
+        case 13: { constexpr int L_ = 13; return CALL; } \
+        default: return hipErrorInvalidValue;           \
+    }
+
+template <typename R>
+hipError_t run_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
+    PHI_DISPATCH_LOG(P.log_fine, (launch_rows_forward<R, L_>(P, rho, dir, s)));
+}
+template <typename R>
+hipError_t run_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
+    PHI_DISPATCH_LOG(P.log_fine, (launch_cols_highfreq<R, L_>(P, dir, s)));
+}
+template <typename R>
+hipError_t run_cols_type2(const DevPlan& P, R dir, hipStream_t s) {
+    PHI_DISPATCH_LOG(P.log_fine, (launch_cols_type2<R, L_>(P, dir, s)));
+}
+template <typename R>
+hipError_t run_cols_type1(const DevPlan& P, R dir, hipStream_t s) {
+    PHI_DISPATCH_LOG(P.log_fine, (launch_cols_type1<R, L_>(P, dir, s)));
+}
+template <typename R>
+hipError_t run_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int use_i2, hipStream_t s) {
+    PHI_DISPATCH_LOG(P.log_fine, (launch_rows_inverse<R, L_>(P, out, dir, use_i1, use_i2, s)));
+}
+
+template <typename R>
+hipError_t run_interp(const DevPlan& P, void* out, int mode, hipStream_t s) {
+    hipLaunchKernelGGL((k_interp<R>), dim3(P.n_sub), dim3(kSubThreads), 0, s, P, static_cast<cpx<R>*>(out), mode);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t run_spread(const DevPlan& P, const void* coef, hipStream_t s) {
+    hipLaunchKernelGGL((k_spread<R>), dim3(P.n_sub), dim3(kSubThreads), 0, s, P,
+                       static_cast<const cpx<R>*>(coef));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t run_zero(void* p, size_t count, hipStream_t s) {
+    const int blocks = static_cast<int>(std::min<size_t>((count + 255) / 256, 1024));
+    hipLaunchKernelGGL((k_fill_zero<R>), dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, static_cast<R*>(p), count);
+    return hipGetLastError();
+}
+
+#define PHI_TRY(expr)                    \
+    do {                                 \
+        hipError_t e_ = (expr);          \
+        if (e_ != hipSuccess) return e_; \
+    } while (0)
+
+// Records an event on s before kernel `name` when a timer is attached.
+hipError_t mark(KernelTimer* t, const char* name, hipStream_t s) {
+    if (!t) return hipSuccess;
+    if (t->count >= KernelTimer::kMax) return hipErrorInvalidValue;
+    t->names[t->count] = name;
+    return hipEventRecord(t->ev[t->count++], s);
+}
+
+#define PHI_STEP(name, expr)                   \
+    do {                                       \
+        PHI_TRY(mark(timer, name, s));         \
+        PHI_TRY(expr);                         \
+    } while (0)
+
+template <typename R>
+hipError_t enqueue_typed(const DevPlan& P, Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
+                         KernelTimer* timer) {
+    // forward solve: type-2 side and the first I1 transforms with e^{-...};
+    // the transposed solve reverses every direction
+    const R dir = adjoint ? R(1) : R(-1);
+    switch (stage) {
+        case Stage::Solve:
+            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_highfreq", (run_cols_highfreq<R>(P, dir, s)));
+            PHI_STEP("cols_type2", (run_cols_type2<R>(P, dir, s)));
+            PHI_STEP("interp", (run_interp<R>(P, P.pts, 0, s)));
+            PHI_STEP("spread", (run_spread<R>(P, P.pts, s)));
+            PHI_STEP("cols_type1", (run_cols_type1<R>(P, -dir, s)));
+            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
+            break;
+        case Stage::HighFreq:
+            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_highfreq", (run_cols_highfreq<R>(P, dir, s)));
+            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, -dir, 1, 0, s)));
+            break;
+        case Stage::LowFreq:
+            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_type2", (run_cols_type2<R>(P, dir, s)));
+            PHI_STEP("interp", (run_interp<R>(P, P.pts, 0, s)));
+            PHI_STEP("spread", (run_spread<R>(P, P.pts, s)));
+            PHI_STEP("cols_type1", (run_cols_type1<R>(P, -dir, s)));
+            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, -dir, 0, 1, s)));
+            break;
+        case Stage::Type2:
+            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_type2", (run_cols_type2<R>(P, dir, s)));
+            PHI_STEP("interp", (run_interp<R>(P, out, 1, s)));
+            break;
+        case Stage::Type1:
+            PHI_STEP("fill_zero", (run_zero<R>(P.spread, static_cast<size_t>(2) * P.patch * P.patch, s)));
+            PHI_STEP("spread", (run_spread<R>(P, in, s)));
+            PHI_STEP("cols_type1", (run_cols_type1<R>(P, R(1), s)));
+            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, R(1), 0, 1, s)));
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return mark(timer, nullptr, s);   // end of the last kernel
+}
+
+}  // namespace
+
+hipError_t enqueue(const DevPlan& P, Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
+                   KernelTimer* timer) {
+    if (P.dtype == PHI_F32) return enqueue_typed<float>(P, stage, in, out, adjoint, s, timer);
+    return enqueue_typed<double>(P, stage, in, out, adjoint, s, timer);
+}
+
+}  // namespace phi

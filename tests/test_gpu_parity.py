@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Bars: rel L-inf and L2 <= 1e-10 (FP64 data path) and
+<= 1e-6 (FP32 data path, oracle run on the FP32-rounded input promoted to
+FP64); each NUFFT stage alone within 10x its tolerance in relative l2."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel_linf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def ps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_2014_amd as ps
+    return ps
+
+
+def to_dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def run_solve(ps, rho64, n, h, dtype, **kw):
+    plan = ps.Plan(n, h, dtype=dtype, **kw)
+    rho_dev = to_dev(rho64, dtype)
+    out = plan.solve(rho_dev)
+    torch.cuda.synchronize()
+    rho_used = rho_dev.double().cpu().numpy()
+    return plan, rho_used, out.double().cpu().numpy()
+
+
+# --------------------------------------------------------------------------
+# the small FP64 case: 64 x 64 over [-8, 8)^2, exp(-r^2), 32 x 64 nodes, tol 1e-12
+# --------------------------------------------------------------------------
+
+def test_small_gaussian_fp64_matches_oracle(ps):
+    print("case: 64x64 Gaussian FP64", flush=True)
+    rho = W.gaussian_density(64, 8.0)
+    plan, rho_used, got = run_solve(ps, rho, 64, 0.25, torch.float64, n_r=32, n_theta=64, tol=1e-12)
+    ref = O.phi(rho_used, O.SplitParams(n=64, h=0.25, n_r=32, n_theta=64))
+    assert rel_linf(got, ref) <= 1e-10
+    assert rel_l2(got, ref) <= 1e-10
+
+
+def test_highfreq_and_lowfreq_parts_fp64(ps):
+    print("case: parts 128x128 mixture FP64", flush=True)
+    n, half = 128, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(3, 8, 4.0, (0.5, 1.5)))
+    plan = ps.Plan(n, 2 * half / n, dtype=torch.float64, tol=1e-12)
+    r = to_dev(rho, torch.float64)
+    i1 = plan.highfreq(r).cpu().numpy()
+    i2 = plan.lowfreq(r).cpu().numpy()
+    parts = O.phi_parts(rho, O.SplitParams(n=n, h=2 * half / n, n_r=64, n_theta=128))
+    scale = np.max(np.abs(parts["phi"]))
+    # I1 is an exact FFT chain: rounding only
+    assert np.max(np.abs(i1 - parts["i1"])) <= 1e-13 * scale
+    assert np.max(np.abs(i2 - parts["i2"])) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("dtype,tol,bar", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-7, 1e-5),
+                                           (torch.float64, 1e-6, 1e-5)])
+def test_type2_stage_against_direct_sums(ps, dtype, tol, bar):
+    print(f"case: type2 {dtype} tol={tol}", flush=True)
+    n, half = 256, 8.0
+    rho = np.random.default_rng(21).standard_normal((n, n))
+    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol)
+    r = to_dev(rho, dtype)
+    got = plan.type2(r).cpu().numpy().astype(np.complex128)
+    kx, ky, _ = plan.nodes()
+    ref = O.type2_direct(r.double().cpu().numpy(), 2 * half / n, O.grid_points(O.SplitParams(n, 2 * half / n, 1, 2)),
+                         kx, ky)
+    assert rel_l2(got, ref) <= bar
+
+
+@pytest.mark.parametrize("dtype,tol,bar", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-7, 1e-5)])
+def test_type1_stage_against_direct_sums(ps, dtype, tol, bar):
+    print(f"case: type1 {dtype}", flush=True)
+    n, half = 256, 8.0
+    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol)
+    m = plan.info["n_nodes"]
+    rng = np.random.default_rng(22)
+    coef = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    cdt = torch.complex128 if dtype == torch.float64 else torch.complex64
+    c = torch.as_tensor(coef, dtype=cdt, device="cuda")
+    got = plan.type1(c).double().cpu().numpy()
+    kx, ky, _ = plan.nodes()
+    xs = O.grid_points(O.SplitParams(n, 2 * half / n, 1, 2))
+    ref = O.type1_direct(c.cpu().numpy().astype(np.complex128), xs, kx, ky).real
+    assert rel_l2(got, ref) <= bar
+
+
+# --------------------------------------------------------------------------
+# sizes spanning several tiles, both precisions
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_mixture_sizes_match_oracle(ps, n, dtype):
+    print(f"case: mixture n={n} {dtype}", flush=True)
+    half = max(4.0, n / 64.0)
+    h = 2 * half / n
+    spec = W.draw_mixture(100 + n, 8, 0.375 * half, (0.5, 2.0))
+    spec = W.MixtureSpec(spec.cx, spec.cy, spec.wx * half / 16, spec.wy * half / 16, spec.phase) \
+        if half > 16 else spec
+    rho = W.mixture_density(n, half, spec)
+    kw = dict(tol=1e-12) if dtype == torch.float64 else dict(tol=1e-7)
+    # tiny grids: the default disk reaches past the Nyquist frequency, shrink it
+    if n <= 16:
+        kw.update(sigma=0.35 / half, cutoff=1.6 / half)
+    plan, rho_used, got = run_solve(ps, rho, n, h, dtype, **kw)
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=h, n_r=64, n_theta=128, sigma=kw.get("sigma"),
+                                        cutoff=kw.get("cutoff")))
+    bar = 1e-10 if dtype == torch.float64 else 1e-6
+    assert rel_linf(got, ref) <= bar, (rel_linf(got, ref), rel_l2(got, ref))
+    assert rel_l2(got, ref) <= bar
+
+
+def test_tiny_grid_brute_size(ps):
+    print("case: 8x8 FP64", flush=True)
+    n, h = 8, 0.5
+    rho = np.random.default_rng(9).standard_normal((n, n))
+    kw = dict(n_r=3, n_theta=4, sigma=0.4, cutoff=0.9, tol=1e-12)
+    plan, rho_used, got = run_solve(ps, rho, n, h, torch.float64, **kw)
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=h, n_r=3, n_theta=4, sigma=0.4, cutoff=0.9))
+    assert rel_linf(got, ref) <= 1e-10
+
+
+def test_zero_density_gives_zero(ps):
+    plan = ps.Plan(128, 0.125, dtype=torch.float32)
+    out = plan.solve(torch.zeros(128, 128, dtype=torch.float32, device="cuda"))
+    assert torch.count_nonzero(out).item() == 0
+
+
+# --------------------------------------------------------------------------
+# full-size single solve: 2048^2 over [-16, 16)^2, 64 x 128 nodes
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def big_case():
+    spec = W.draw_mixture(0)
+    rho = W.mixture_density(2048, 16.0, spec)
+    return rho
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_full_size_single_solve(ps, big_case, dtype):
+    print(f"case: 2048x2048 {dtype}", flush=True)
+    tol = 1e-7 if dtype == torch.float32 else 1e-12
+    plan, rho_used, got = run_solve(ps, big_case, 2048, 1 / 64, dtype, tol=tol)
+    ref = O.phi(rho_used, O.SplitParams(n=2048, h=1 / 64, n_r=64, n_theta=128))
+    bar = 1e-10 if dtype == torch.float64 else 1e-6
+    print(f"  rel_linf={rel_linf(got, ref):.3e} rel_l2={rel_l2(got, ref):.3e}", flush=True)
+    assert rel_linf(got, ref) <= bar
+    assert rel_l2(got, ref) <= bar
+
+
+# --------------------------------------------------------------------------
+# transposed solve, second component, invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_adjoint_against_oracle_transpose(ps, dtype):
+    print(f"case: adjoint {dtype}", flush=True)
+    n, half = 256, 8.0
+    h = 2 * half / n
+    rng = np.random.default_rng(31)
+    g = rng.standard_normal((n, n))
+    rho = W.mixture_density(n, half, W.draw_mixture(5, 8, 3.0, (0.5, 1.5)))
+    plan = ps.Plan(n, h, dtype=dtype, tol=1e-12 if dtype == torch.float64 else 1e-7)
+    gd = to_dev(g, dtype)
+    rd = to_dev(rho, dtype)
+    at_g = plan.solve_adjoint(gd).double().cpu().numpy()
+    a_r = plan.solve(rd).double().cpu().numpy()
+    ref = O.phi_transpose(gd.double().cpu().numpy(), O.SplitParams(n=n, h=h, n_r=64, n_theta=128))
+    bar = 1e-10 if dtype == torch.float64 else 1e-6
+    assert rel_l2(at_g, ref) <= bar
+    lhs = float(np.vdot(a_r, gd.double().cpu().numpy()))
+    rhs = float(np.vdot(rd.double().cpu().numpy(), at_g))
+    assert abs(lhs - rhs) <= (1e-12 if dtype == torch.float64 else 1e-5) * abs(lhs)
+
+
+def test_components_sum_to_minus_rho(ps):
+    print("case: xx + yy", flush=True)
+    n, half = 256, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(6, 8, 3.0, (0.5, 1.5)))
+    px = ps.Plan(n, 2 * half / n, dtype=torch.float64)
+    py = ps.Plan(n, 2 * half / n, dtype=torch.float64, component="y")
+    r = to_dev(rho, torch.float64)
+    total = (px.solve(r) + py.solve(r)).cpu().numpy()
+    assert np.max(np.abs(total + rho)) <= 1e-11 * rho.max()
+
+
+def test_transposed_density_swaps_components(ps):
+    n, half = 256, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(7, 8, 3.0, (0.5, 1.5)))
+    px = ps.Plan(n, 2 * half / n, dtype=torch.float64)
+    py = ps.Plan(n, 2 * half / n, dtype=torch.float64, component="y")
+    a = px.solve(to_dev(rho.T, torch.float64)).cpu().numpy()
+    b = py.solve(to_dev(rho, torch.float64)).cpu().numpy().T
+    assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(b))
+
+
+def test_repeated_solves_agree(ps):
+    n = 512
+    rho = W.mixture_density(n, 8.0, W.draw_mixture(8, 8, 3.0, (0.5, 1.5)))
+    plan = ps.Plan(n, 16.0 / n, dtype=torch.float32)
+    r = to_dev(rho, torch.float32)
+    a = plan.solve(r).double().cpu().numpy()
+    b = plan.solve(r).double().cpu().numpy()
+    # atomics in the spread may reorder sums; results agree far inside the bar
+    assert rel_linf(a, b) <= 1e-7
+
+
+def test_autograd_backward_is_the_adjoint(ps):
+    n, half = 128, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(9, 8, 3.0, (0.5, 1.5)))
+    plan = ps.Plan(n, 2 * half / n, dtype=torch.float64)
+    r = to_dev(rho, torch.float64).requires_grad_(True)
+    target = to_dev(np.random.default_rng(4).standard_normal((n, n)) * 0.01, torch.float64)
+    phi = ps.phi_solve(r, plan)
+    loss = ((phi - target) ** 2).sum()
+    loss.backward()
+    g = 2 * (phi.detach() - target)
+    ref = plan.solve_adjoint(g)
+    assert torch.allclose(r.grad, ref, rtol=0, atol=1e-14 * ref.abs().max().item())

@@ -1,0 +1,143 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, and
+its host-side plan logic (quadrature, kernel transform, parameter readings,
+error codes) is right.  No GPU calls."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+from conftest import ROOT
+
+B = pytest.importorskip("paper_1409_2014_amd._binding")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail(f"library not built: {B.LIB_PATH} (run python -m paper_1409_2014_amd.build_lib)")
+    return B.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "phi_solve.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(phi_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    raw = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+    assert set(B.exported_symbols()) <= set(names)
+
+
+def test_status_strings(lib):
+    for code, name in B.STATUS_NAMES.items():
+        assert lib.phi_status_string(code).decode() == name
+
+
+def test_gauss_legendre_matches_numpy(lib):
+    import paper_1409_2014_amd.solver as S
+    for n in (1, 2, 5, 32, 64, 127, 512):
+        x, w = S.host_gauss_legendre(n)
+        xr, wr = np.polynomial.legendre.leggauss(n)
+        assert np.max(np.abs(x - xr)) < 2e-15
+        # numpy's endpoint weights drift from the exact ones by up to ~1e-10
+        # relative at n = 512 (checked against 40-digit values); the exactness
+        # test below pins this rule independently
+        assert np.max(np.abs(w - wr) / wr) < 1e-9
+    for n in (3, 16, 64):
+        x, w = S.host_gauss_legendre(n)
+        for k in range(0, 2 * n, 2):
+            assert abs(np.sum(w * x ** k) - 2.0 / (k + 1)) < 1e-14
+
+
+def test_es_transform_against_adaptive_quadrature(lib):
+    from scipy import integrate
+    import paper_1409_2014_amd.solver as S
+    for beta in (2.30 * 8, 2.30 * 13):
+        omegas = np.array([0.0, 0.7, 3.1, 9.0])
+        got = S.host_es_transform(omegas, beta)
+        for om, g in zip(omegas, got):
+            ref = integrate.quad(lambda z: math.exp(beta * (math.sqrt(1 - z * z) - 1)) * math.cos(om * z),
+                                 -1, 1, limit=200, epsabs=1e-15, epsrel=1e-14)[0]
+            assert abs(g - ref) < 1e-13 * max(1.0, abs(ref))
+        z = np.array([-1.0, -0.5, 0.0, 0.3, 1.0, 1.5])
+        k = S.host_es_kernel(z, beta)
+        assert k[2] == 1.0 and k[0] == 0.0 and k[4] == 0.0 and k[5] == 0.0
+        assert abs(k[1] - math.exp(beta * (math.sqrt(0.75) - 1))) < 1e-15
+
+
+def test_plan_nodes_equal_the_oracle_rule(lib):
+    import paper_1409_2014_amd.solver as S
+    for comp, ocomp in (("x", "xx"), ("y", "yy")):
+        kx, ky, q = S.host_polar_nodes(n=64, h=0.25, n_r=32, n_theta=64, component=comp)
+        okx, oky, oq = O.polar_rule(O.SplitParams(n=64, h=0.25, n_r=32, n_theta=64, component=ocomp))
+        a = np.stack([kx, ky, q], 1)
+        b = np.stack([okx, oky, oq], 1)
+        a = a[np.lexsort((a[:, 1], a[:, 0]))]
+        b = b[np.lexsort((b[:, 1], b[:, 0]))]
+        assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_describe_defaults_small_case(lib):
+    import paper_1409_2014_amd.solver as S
+    d = S.describe(n=64, h=0.25, n_r=32, n_theta=64, tol=1e-12)
+    assert d["n_fine"] == 128 and d["n_nodes"] == 2048
+    assert abs(d["sigma"] - 0.120753014) < 1e-8
+    assert abs(d["cutoff"] - 0.732935599) < 1e-8
+    assert d["kernel_width"] == 13 and abs(d["beta"] - 29.9) < 1e-12
+    # nodes reach n_fine h c = 23.45 cells; window covers them plus half a kernel
+    assert d["patch"] == 64 and d["patch_lo"] == -32
+    d = S.describe(n=2048, h=1 / 64, dtype="float32")
+    assert d["kernel_width"] == 8 and d["patch"] == 64 and d["n_nodes"] == 8192
+
+
+def test_describe_small_grid_uses_whole_fine_grid(lib):
+    import paper_1409_2014_amd.solver as S
+    d = S.describe(n=16, h=1.0)
+    assert d["patch"] == d["n_fine"] == 32
+
+
+@pytest.mark.parametrize("kwargs,status", [
+    (dict(n=64, h=0.25, n_theta=63), 1),            # odd azimuthal count
+    (dict(n=64, h=-1.0), 1),                        # negative spacing
+    (dict(n=60, h=0.25), 2),                        # not a power of two
+    (dict(n=8192, h=0.25), 2),                      # too large
+    (dict(n=64, h=0.25, tol=1e-9, dtype="float32"), 3),
+    (dict(n=64, h=0.25, tol=1e-16), 3),
+    (dict(n=64, h=0.25, pad=3), 2),
+    (dict(n=64, h=0.25, pad=1), 1),
+])
+def test_invalid_parameters_return_documented_codes(lib, kwargs, status):
+    import paper_1409_2014_amd.solver as S
+    with pytest.raises(B.PhiError) as exc:
+        S.describe(**kwargs)
+    assert exc.value.status == status
+
+
+def test_null_and_destroyed_plans_are_rejected(lib):
+    st = lib.phi_solve(None, ctypes.c_void_p(1), ctypes.c_void_p(2), None)
+    assert st == 1
+    assert lib.phi_destroy(None) == 0
+    assert b"plan" in lib.phi_last_error(None)
+    info = B.PhiPlanInfo()
+    assert lib.phi_plan_get_info(ctypes.c_void_p(12345), ctypes.byref(info)) == 1
+
+
+def test_nonsquare_grid_is_unsupported(lib):
+    p = B.PhiParams()
+    assert lib.phi_params_default(ctypes.byref(p), 64, 0.25, 0) == 0
+    p.ny = 32
+    info = B.PhiPlanInfo()
+    assert lib.phi_describe(ctypes.byref(p), ctypes.byref(info)) == 2
+    p.ny = 64
+    p.hy = 0.5
+    assert lib.phi_describe(ctypes.byref(p), ctypes.byref(info)) == 2
