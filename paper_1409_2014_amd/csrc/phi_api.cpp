@@ -168,11 +168,13 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         Part p_uy = take(m * 8);
         Part p_q = take(m * 8);
         Part p_sub = take(hp.sub.size() * 4);
+        Part p_bins = take(hp.bin_start.size() * 4);
         Part p_xt = take((n + 1) * n * 2 * es);
         Part p_tt = take(q * n * 2 * es);
         Part p_win = take(q * q * 2 * es);
         Part p_pts = take(m * 2 * es);
-        Part p_spread = take(q * q * 2 * es);
+        const size_t tile = static_cast<size_t>(hp.bin + hp.width - 1);
+        Part p_tiles = take(static_cast<size_t>(hp.n_sub) * tile * tile * 2 * es);
         Part p_u = take(n * q * 2 * es);
         plan->block_bytes = cursor;
         e = hipMalloc(&plan->block, cursor);
@@ -197,6 +199,7 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         if (ce == hipSuccess) ce = up(p_uy, hp.uy.data());
         if (ce == hipSuccess) ce = up(p_q, hp.q.data());
         if (ce == hipSuccess) ce = up(p_sub, hp.sub.data());
+        if (ce == hipSuccess) ce = up(p_bins, hp.bin_start.data());
         if (ce == hipSuccess) ce = hipStreamSynchronize(s);
         if (ce != hipSuccess) {
             (void)hipFree(plan->block);
@@ -227,11 +230,14 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         d.uy = reinterpret_cast<const double*>(base + p_uy.off);
         d.q = reinterpret_cast<const double*>(base + p_q.off);
         d.sub = reinterpret_cast<const int*>(base + p_sub.off);
+        d.bin_start = reinterpret_cast<const int*>(base + p_bins.off);
+        d.nb = hp.nb;
+        d.tile = static_cast<int>(tile);
         d.xt = base + p_xt.off;
         d.tt = base + p_tt.off;
         d.win = base + p_win.off;
         d.pts = base + p_pts.off;
-        d.spread = base + p_spread.off;
+        d.tiles = base + p_tiles.off;
         d.u = base + p_u.off;
         {
             std::lock_guard<std::mutex> lock(g_registry_mutex);

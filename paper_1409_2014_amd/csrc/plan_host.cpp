@@ -264,6 +264,7 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
         hp->ux[i] = ux[j]; hp->uy[i] = uy[j];
     }
     hp->sub.clear();
+    hp->bin_start.assign(static_cast<size_t>(nb) * nb + 1, 0);
     for (int i = 0; i < m;) {
         const int k = key[order[i]];
         int e = i;
@@ -274,10 +275,13 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
             hp->sub.push_back(lo + by * bin);
             hp->sub.push_back(s);
             hp->sub.push_back(std::min(kMaxNodesPerSub, e - s));
+            hp->bin_start[k + 1] += 1;
         }
         i = e;
     }
+    for (size_t b = 1; b < hp->bin_start.size(); ++b) hp->bin_start[b] += hp->bin_start[b - 1];
     hp->bin = bin;
+    hp->nb = nb;
     hp->n_sub = static_cast<int>(hp->sub.size() / 4);
 
     // ---- deconvolution factors 2 pi / (n_fine psi_hat(n')) ---------------------

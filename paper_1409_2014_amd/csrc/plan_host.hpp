@@ -33,13 +33,14 @@ struct HostPlan {
     double beta = 0;
     // fine-grid window touched by the nodes' kernel taps: [patch_lo, patch_lo + patch)
     int patch = 0, patch_lo = 0;
-    // bin sort
-    int bin = kBinSize, n_sub = 0;
+    // bin sort: bins of bin x bin cells tile the window, nb per side
+    int bin = kBinSize, n_sub = 0, nb = 0;
 
     // node data in plan order (bin-sorted)
     std::vector<double> kx, ky, q;      // k_j and q_j of eq. 12 (q without h^2)
     std::vector<double> ux, uy;         // node positions in fine-grid cells: n_fine h k
     std::vector<int32_t> sub;           // per subproblem: tile_lo1, tile_lo2, first node, count
+    std::vector<int32_t> bin_start;     // [nb*nb + 1] subproblems of bin b are bin_start[b] .. bin_start[b+1]-1
     // tables
     std::vector<double> deconv;         // [N] 2 pi / (n_fine psi_hat(n')), n' = i - N/2
     std::vector<double> gx;             // [2 (N+1)] (a, 1 - e^{-a}),  a = kx^2 / sigma^2, kx = m/(n_fine h)

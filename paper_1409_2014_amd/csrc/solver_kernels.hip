@@ -16,10 +16,11 @@
 //                  interpolate rho_hat(k_j) = h^2 sum_taps b psi psi with 16-lane
 //                  reductions, multiply by q_j.             [eq. 12, a_j = q_j rho_hat_j]
 //   spread         per subproblem: the transposed taps accumulate a_j psi psi
-//                  into an LDS tile (compensated sums in FP32), then the tile
-//                  is added to the fine-grid window with atomics.  [type 1 spreading]
-//   cols_type1     per window column: F-point FFT of the spread window (only Q
-//                  non-zero inputs), keep the N centred rows, times d(n2).
+//                  into an LDS tile (compensated sums in FP32); the tile goes
+//                  to the subproblem's own slot (no atomics).  [type 1 spreading]
+//   cols_type1     per window column: sum the tiles covering it in a fixed
+//                  order, F-point FFT (only Q non-zero inputs), keep the N
+//                  centred rows, times d(n2).
 //   rows_inverse   per grid row: rebuild the full Hermitian I1 row spectrum plus
 //                  i times the Hermitian part of the type-1 row, one F-point
 //                  FFT; Phi = Re + Im d(n1).       [eq. 8: Phi = I1 + Re I2]
@@ -172,8 +173,65 @@ __global__ __launch_bounds__(NT) void k_cols_type2(DevPlan P, R dir) {
 }
 
 // ---------------------------------------------------------------------------
-// cols_type1: inverse-direction FFT along y of the spread window, times d(n2)
+// cols_type1: sum the spread tiles onto one column of the fine-grid window,
+// FFT along y (only the Q window rows are non-zero), keep the N centred rows,
+// times d(n2)
 // ---------------------------------------------------------------------------
+
+// Range of bins b (0 <= b < nb) whose tile starts at b * bin and covers window
+// index i (i - b * bin in [0, E)).
+__device__ __forceinline__ void covering_bins(int i, int bin, int E, int nb, int* lo, int* hi) {
+    const int a = i - E + 1;
+    int b0 = (a >= 0) ? (a + bin - 1) / bin : -((-a) / bin);   // ceil(a / bin)
+    *lo = b0 > 0 ? b0 : 0;
+    const int b1 = i / bin;
+    *hi = b1 < nb - 1 ? b1 : nb - 1;
+}
+
+// b[i1][i2] = sum of the tile values of every subproblem whose tile covers
+// window cell (i1, i2), in the fixed order (x period, x bin, y period, y bin,
+// subproblem).  When the window is the whole periodic fine grid (Q = F) a
+// tile may wrap around it, possibly more than once.
+template <typename R>
+__device__ __forceinline__ cpx<R> gather_tiles(const DevPlan& P, int i1, int i2) {
+    const int q = P.patch, E = P.tile, bin = P.bin, nb = P.nb;
+    const int periods = (q == P.n_fine) ? (q + E - 2) / q + 1 : 1;
+    const cpx<R>* tiles = static_cast<const cpx<R>*>(P.tiles);
+    R sx = 0, sy = 0, cx = 0, cy = 0;
+    for (int t1 = 0; t1 < periods; ++t1) {
+        const int x = i1 + t1 * q;
+        int bx0, bx1;
+        covering_bins(x, bin, E, nb, &bx0, &bx1);
+        for (int bx = bx0; bx <= bx1; ++bx) {
+            const int ox = x - bx * bin;
+            for (int t2 = 0; t2 < periods; ++t2) {
+                const int y = i2 + t2 * q;
+                int by0, by1;
+                covering_bins(y, bin, E, nb, &by0, &by1);
+                for (int by = by0; by <= by1; ++by) {
+                    const int oy = y - by * bin;
+                    const int b = by * nb + bx;
+                    for (int sidx = P.bin_start[b]; sidx < P.bin_start[b + 1]; ++sidx) {
+                        const cpx<R> v = tiles[static_cast<size_t>(sidx) * E * E + oy * E + ox];
+                        if constexpr (sizeof(R) == 4) {
+                            const R yx = v.x - cx, tx = sx + yx;
+                            cx = (tx - sx) - yx;
+                            sx = tx;
+                            const R yy = v.y - cy, ty = sy + yy;
+                            cy = (ty - sy) - yy;
+                            sy = ty;
+                        } else {
+                            sx += v.x;
+                            sy += v.y;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return {sx - cx, sy - cy};
+}
+
 template <typename R, int LOG, int NT>
 __global__ __launch_bounds__(NT) void k_cols_type1(DevPlan P, R dir) {
     constexpr int F = 1 << LOG;
@@ -185,9 +243,8 @@ __global__ __launch_bounds__(NT) void k_cols_type1(DevPlan P, R dir) {
     twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
     for (int p = tid; p < F; p += NT) buf[lds_pad(p)] = {R(0), R(0)};
     __syncthreads();
-    const cpx<R>* win = static_cast<const cpx<R>*>(P.spread);
     for (int i2 = tid; i2 < P.patch; i2 += NT)
-        buf[lds_pad((P.patch_lo + i2) & (F - 1))] = win[static_cast<size_t>(i2) * P.patch + i1];
+        buf[lds_pad((P.patch_lo + i2) & (F - 1))] = gather_tiles<R>(P, i1, i2);
     __syncthreads();
     fft_lds<R, LOG, NT>(buf, tw, tid, dir);
     cpx<R>* u = static_cast<cpx<R>*>(P.u);
@@ -312,13 +369,6 @@ __global__ __launch_bounds__(kSubThreads) void k_interp(DevPlan P, cpx<R>* __res
     const int F = P.n_fine;
     const int q = P.patch;
     const cpx<R>* win = static_cast<const cpx<R>*>(P.win);
-    // clear the spread target for the next stage of the solve
-    {
-        cpx<R>* sp = static_cast<cpx<R>*>(P.spread);
-        const int total = q * q;
-        for (int i = blockIdx.x * kSubThreads + threadIdx.x; i < total; i += gridDim.x * kSubThreads)
-            sp[i] = {R(0), R(0)};
-    }
     for (int c = threadIdx.x; c < E * E; c += kSubThreads) {
         const int ca = c % E, cb = c / E;
         const int wi1 = posmod_dev(lo1 + ca - P.patch_lo, F);
@@ -358,26 +408,26 @@ __global__ __launch_bounds__(kSubThreads) void k_interp(DevPlan P, cpx<R>* __res
     }
 }
 
-// b[l] += sum_j a_j psi(l1 - u_jx) psi(l2 - u_jy) over the subproblem's nodes:
-// each thread owns tile cells and sums the taps that land on them (compensated
-// summation in FP32), then the tile is added to the fine-grid window.
+// Tile of subproblem s: T_s[l] = sum_j a_j psi(l1 - u_jx) psi(l2 - u_jy) over the
+// subproblem's nodes, for the E x E cells l of its bin's tile.  Each thread owns
+// tile cells and sums the taps that land on them in node order (compensated
+// summation in FP32), then writes the whole tile, zeros included, to the
+// subproblem's own slot: no atomics, so the result is bitwise reproducible.
+// The tiles are summed onto the fine-grid window by cols_type1.
 template <typename R>
 __global__ __launch_bounds__(kSubThreads) void k_spread(DevPlan P, const cpx<R>* __restrict__ coef) {
     __shared__ SubLds<R> s;
     const int* sub = P.sub + 4 * blockIdx.x;
     const int lo1 = sub[0], lo2 = sub[1], first = sub[2], count = sub[3];
     const int w = P.width;
-    const int E = P.bin + w - 1;
-    const int F = P.n_fine;
-    const int q = P.patch;
+    const int E = P.tile;
     subproblem_taps<R>(P, s, lo1, lo2, first, count);
     for (int jj = threadIdx.x; jj < count; jj += kSubThreads) s.val[jj] = coef[first + jj];
     __syncthreads();
-    R* win = static_cast<R*>(P.spread);
+    cpx<R>* tile = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(blockIdx.x) * E * E;
     for (int c = threadIdx.x; c < E * E; c += kSubThreads) {
         const int ca = c % E, cb = c / E;
         R sx = 0, sy = 0, cx = 0, cy = 0;   // sums and compensations
-        bool any = false;
         for (int jj = 0; jj < count; ++jj) {
             const int ax = ca - s.offx[jj];
             const int ay = cb - s.offy[jj];
@@ -386,7 +436,6 @@ __global__ __launch_bounds__(kSubThreads) void k_spread(DevPlan P, const cpx<R>*
                 const R k = s.psx[jj][ax] * s.psy[jj][ay];
                 const R vx = s.val[jj].x * k;
                 const R vy = s.val[jj].y * k;
-                any = true;
                 if constexpr (sizeof(R) == 4) {
                     const R yx = vx - cx, tx = sx + yx;
                     cx = (tx - sx) - yx;
@@ -400,25 +449,8 @@ __global__ __launch_bounds__(kSubThreads) void k_spread(DevPlan P, const cpx<R>*
                 }
             }
         }
-        if (any) {
-            const int wi1 = posmod_dev(lo1 + ca - P.patch_lo, F);
-            const int wi2 = posmod_dev(lo2 + cb - P.patch_lo, F);
-            if (wi1 < q && wi2 < q) {
-                R* dst = win + 2 * (static_cast<size_t>(wi2) * q + wi1);
-                atomicAdd(dst, sx - cx);
-                atomicAdd(dst + 1, sy - cy);
-            }
-        }
+        tile[c] = {sx - cx, sy - cy};
     }
-}
-
-// Fill kernel (used instead of a memset so the solve chain can be captured in
-// a graph).
-template <typename T>
-__global__ void k_fill_zero(T* __restrict__ p, size_t count) {
-    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        p[i] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -512,13 +544,6 @@ hipError_t run_spread(const DevPlan& P, const void* coef, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t run_zero(void* p, size_t count, hipStream_t s) {
-    const int blocks = static_cast<int>(std::min<size_t>((count + 255) / 256, 1024));
-    hipLaunchKernelGGL((k_fill_zero<R>), dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, static_cast<R*>(p), count);
-    return hipGetLastError();
-}
-
 #define PHI_TRY(expr)                    \
     do {                                 \
         hipError_t e_ = (expr);          \
@@ -574,7 +599,6 @@ hipError_t enqueue_typed(const DevPlan& P, Stage stage, const void* in, void* ou
             PHI_STEP("interp", (run_interp<R>(P, out, 1, s)));
             break;
         case Stage::Type1:
-            PHI_STEP("fill_zero", (run_zero<R>(P.spread, static_cast<size_t>(2) * P.patch * P.patch, s)));
             PHI_STEP("spread", (run_spread<R>(P, in, s)));
             PHI_STEP("cols_type1", (run_cols_type1<R>(P, R(1), s)));
             PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, R(1), 0, 1, s)));

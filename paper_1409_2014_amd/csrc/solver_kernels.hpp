@@ -25,12 +25,15 @@ struct DevPlan {
     const double* uy;       // [M]
     const double* q;        // [M] (without h^2)
     const int* sub;         // [4 n_sub]
+    const int* bin_start;   // [nb*nb + 1] subproblem range of each bin
+    int nb;                 // bins per window side (window side = nb * bin)
+    int tile;               // tile side E = bin + width - 1
     // workspace, element type = data precision
     void* xt;       // (N+1) x N complex: I1 half spectrum, column-major
     void* tt;       // Q x N complex: type-2 row window, column-major
     void* win;      // Q x Q complex: type-2 fine-grid window
     void* pts;      // M complex: a_j = q_j rho_hat_j
-    void* spread;   // Q x Q complex: type-1 spread window
+    void* tiles;    // n_sub x E x E complex: each subproblem's spread tile
     void* u;        // N x Q complex: type-1 column transforms
 };
 
