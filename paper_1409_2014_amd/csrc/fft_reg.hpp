@@ -1,0 +1,134 @@
+// Register-resident Stockham FFT of one power-of-two sequence of length
+// F = 2^LOG, computed by a group of NT = F/16 threads that each hold 16 points.
+//
+// Layout contract: on entry and on exit thread `tid` of the group holds the
+// points at positions tid + NT*i, i = 0..15, in v[i].  Stage 0 is radix 16
+// with no twiddles; the following stages are radix 16 except a last radix
+// 2^(LOG mod 4) stage.  Between stages the points are exchanged through one LDS
+// buffer of F complex values (padded every 16 entries); the last stage writes
+// its outputs back to registers in the same positions the first stage reads,
+// so a forward transform, a pointwise multiply and an inverse transform chain
+// without an extra exchange, and zero inputs / unused outputs at positions
+// known at compile time are pruned by the compiler.
+//
+// Stage s of radix R with sub-transform length p (the product of the previous
+// radices) and NB = F/R butterflies: butterfly b reads positions b + t NB,
+// multiplies input t by W_{pR}^{t k} (k = b mod p), takes a length-R DFT in
+// registers, and writes output t to position (b - k) R + k + t p (Stockham
+// auto-sort: natural order out, no bit reversal).
+//
+// Twiddles come from a per-stage table in device memory, rounded once to the
+// data precision from FP64 values: stage s (s >= 1) holds W_{p R}^{t k} for
+// t = 1..R-1, k = 0..p-1 at index (t-1) p + k, and the stages are stored back
+// to back in order.  Forward tables; the inverse takes conjugates.
+//
+// dir = -1: X(k) = sum_j x(j) e^{-2 pi i k j / F} (forward DFT, Sec. 2.2,
+// eq. (13)); dir = +1: the same sum with e^{+...} (eq. (14) times F).
+#pragma once
+
+#include "device_common.hpp"
+#include "fft_lds.hpp"   // RegDft, root16
+
+namespace phi {
+
+template <int LOG>
+struct FftShape {
+    static constexpr int F = 1 << LOG;
+    static constexpr int NT = F / 16;                  // threads per sequence
+    static constexpr int S16 = LOG / 4;                // radix-16 stages
+    static constexpr int REM = LOG % 4;                // radix 2^REM final stage (0: none)
+    static constexpr int NSTAGE = S16 + (REM ? 1 : 0);
+    static_assert(LOG >= 4, "FFT length must be at least 16");
+
+    static constexpr int radix(int s) { return (s < S16) ? 16 : (1 << REM); }
+    static constexpr int span(int s) {                 // p of stage s
+        int p = 1;
+        for (int i = 0; i < s; ++i) p *= radix(i);
+        return p;
+    }
+    static constexpr int tw_offset(int s) {            // start of stage s in the table
+        int off = 0;
+        for (int i = 1; i < s; ++i) off += (radix(i) - 1) * span(i);
+        return off;
+    }
+    static constexpr int tw_size() { return tw_offset(NSTAGE); }
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> tw_load(const cpx<R>* __restrict__ tw, int idx, R dir) {
+    cpx<R> w = tw[idx];
+    w.y = -dir * w.y;   // table holds e^{-i theta}
+    return w;
+}
+
+// Stage S of the transform.  v holds the thread's 16 points in the register
+// layout; stages after the first read their inputs from LDS.
+template <typename R, int LOG, int S>
+__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw,
+                                          int tid, R dir) {
+    using Sh = FftShape<LOG>;
+    constexpr int F = Sh::F;
+    constexpr int NT = Sh::NT;
+    constexpr int RAD = Sh::radix(S);
+    constexpr int P = Sh::span(S);
+    constexpr int NB = F / RAD;
+    constexpr int C = 16 / RAD;          // butterflies per thread
+    constexpr bool LAST = (S == Sh::NSTAGE - 1);
+    if constexpr (S > 0) {
+        // inputs of this stage: positions tid + NT i
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
+        if constexpr (!LAST) __syncthreads();   // all reads done before this stage overwrites
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int b = tid + NT * c;
+        const int k = b & (P - 1);
+        cpx<R> x[RAD];
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) {
+            x[t] = v[c + C * t];
+            if constexpr (S > 0) {
+                if (t > 0) x[t] = cmul(x[t], tw_load<R>(tw, Sh::tw_offset(S) + (t - 1) * P + k, dir));
+            }
+        }
+        RegDft<RAD, R>::run(x, dir);
+        if constexpr (S == 0 && !LAST) {
+            // the buffer may still be read by the group's previous use
+            if (c == 0) __syncthreads();
+        }
+        if constexpr (LAST) {
+            // output position b + t NB: the same register slot
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) v[c + C * t] = x[t];
+        } else {
+            const int base = (b - k) * RAD + k;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) lds[lds_pad(base + t * P)] = x[t];
+        }
+    }
+    if constexpr (!LAST) __syncthreads();
+}
+
+template <typename R, int LOG, int S>
+__device__ __forceinline__ void fft_stages_from(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw,
+                                                int tid, R dir) {
+    if constexpr (S < FftShape<LOG>::NSTAGE) {
+        fft_stage<R, LOG, S>(v, lds, tw, tid, dir);
+        fft_stages_from<R, LOG, S + 1>(v, lds, tw, tid, dir);
+    }
+}
+
+// The whole transform.  Every thread of the block must call it (it contains
+// block-wide barriers); `lds` is this group's buffer of lds_padded_size(F)
+// complex values.  The transform begins with a barrier before its first LDS
+// write, so it may follow any earlier reads of the buffer (including another
+// transform) directly; it ends without one, so a caller that writes the buffer
+// afterwards must synchronise first.
+template <typename R, int LOG>
+__device__ __forceinline__ void fft_reg(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw, int tid,
+                                        R dir) {
+    fft_stages_from<R, LOG, 0>(v, lds, tw, tid, dir);
+}
+
+}  // namespace phi

@@ -164,6 +164,7 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         Part p_gy = take(2 * f * 8);
         Part p_twlo = take(hp.tw_lo.size() * 8);
         Part p_twhi = take(hp.tw_hi.size() * 8);
+        Part p_twr = take(hp.twr.size() * es);
         Part p_ux = take(m * 8);
         Part p_uy = take(m * 8);
         Part p_q = take(m * 8);
@@ -195,6 +196,11 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         if (ce == hipSuccess) ce = up(p_gy, hp.gy.data());
         if (ce == hipSuccess) ce = up(p_twlo, hp.tw_lo.data());
         if (ce == hipSuccess) ce = up(p_twhi, hp.tw_hi.data());
+        // stage twiddles rounded once from FP64 to the data precision
+        std::vector<float> twr32;
+        if (p->dtype == PHI_F32) twr32.assign(hp.twr.begin(), hp.twr.end());
+        if (ce == hipSuccess) ce = up(p_twr, (p->dtype == PHI_F32) ? static_cast<const void*>(twr32.data())
+                                                                  : static_cast<const void*>(hp.twr.data()));
         if (ce == hipSuccess) ce = up(p_ux, hp.ux.data());
         if (ce == hipSuccess) ce = up(p_uy, hp.uy.data());
         if (ce == hipSuccess) ce = up(p_q, hp.q.data());
@@ -226,6 +232,8 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         d.gy = reinterpret_cast<const double*>(base + p_gy.off);
         d.tw_lo = reinterpret_cast<const double*>(base + p_twlo.off);
         d.tw_hi = reinterpret_cast<const double*>(base + p_twhi.off);
+        d.twr = base + p_twr.off;
+        d.twr_count = static_cast<int>(hp.twr.size() / 2);
         d.ux = reinterpret_cast<const double*>(base + p_ux.off);
         d.uy = reinterpret_cast<const double*>(base + p_uy.off);
         d.q = reinterpret_cast<const double*>(base + p_q.off);

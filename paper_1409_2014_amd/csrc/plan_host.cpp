@@ -120,6 +120,51 @@ double es_transform(double omega, double beta) {
     return 2.0 * s;
 }
 
+void unit_root(long long m, long long n, double* re, double* im) {
+    // angle 2 pi r / n with r = m mod n, written as octant * (pi/4) + frac * (pi/4)
+    // so that sin and cos only see arguments in [0, pi/4]
+    const long long r = ((m % n) + n) % n;
+    const long long e8 = 8 * r;
+    const long long oct = e8 / n;
+    const double frac = static_cast<double>(e8 - oct * n) / static_cast<double>(n);
+    const double th = frac * (kPi / 4.0);
+    const double c = std::cos(th), s = std::sin(th);
+    const double cq = std::cos(kPi / 4.0 - th), sq = std::sin(kPi / 4.0 - th);
+    double cr, sr;
+    switch (oct) {
+        case 0: cr = c; sr = s; break;
+        case 1: cr = sq; sr = cq; break;
+        case 2: cr = -s; sr = c; break;
+        case 3: cr = -cq; sr = sq; break;
+        case 4: cr = -c; sr = -s; break;
+        case 5: cr = -sq; sr = -cq; break;
+        case 6: cr = s; sr = -c; break;
+        default: cr = cq; sr = -sq; break;
+    }
+    *re = cr;
+    *im = -sr;
+}
+
+void fft_stage_twiddles(int log, std::vector<double>* out) {
+    const int s16 = log / 4, rem = log % 4, nst = s16 + (rem ? 1 : 0);
+    const long long f = 1LL << log;
+    out->clear();
+    long long p = 16;                       // span of stage 1
+    for (int s = 1; s < nst; ++s) {
+        const int r = (s < s16) ? 16 : (1 << rem);
+        const long long step = f / (p * r);  // W_{pR}^{tk} = W_F^{t k step}
+        for (int t = 1; t < r; ++t) {
+            for (long long k = 0; k < p; ++k) {
+                double re, im;
+                unit_root(t * k * step, f, &re, &im);
+                out->push_back(re);
+                out->push_back(im);
+            }
+        }
+        p *= r;
+    }
+}
+
 phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     if (!p || !hp) { *err = "NULL argument"; return PHI_ERR_INVALID_ARG; }
     if (p->nx != p->ny) { *err = "nx != ny: only square grids are implemented"; return PHI_ERR_UNSUPPORTED; }
@@ -320,32 +365,10 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
     const int s_hi = nf / s_lo;
     hp->tw_lo.resize(2 * s_lo);
     hp->tw_hi.resize(2 * s_hi);
-    auto expi = [&](long long mm, double* out) {
-        // e^{-2 pi i mm / nf} with the angle reduced to the first octant so that
-        // sin/cos see arguments in [0, pi/4]
-        const long long r = ((mm % nf) + nf) % nf;
-        const long long e8 = 8 * r;                 // angle in units of 2 pi / (8 nf)
-        const long long oct = e8 / nf;              // octant 0..7
-        const double frac = static_cast<double>(e8 - oct * nf) / nf;  // [0, 1)
-        const double th = frac * (kPi / 4.0);
-        double c = std::cos(th), s = std::sin(th);
-        double cr, sr;  // cos, sin of the full angle
-        const double cq = std::cos(kPi / 4.0 - th), sq = std::sin(kPi / 4.0 - th);
-        switch (oct) {
-            case 0: cr = c; sr = s; break;
-            case 1: cr = sq; sr = cq; break;
-            case 2: cr = -s; sr = c; break;
-            case 3: cr = -cq; sr = sq; break;
-            case 4: cr = -c; sr = -s; break;
-            case 5: cr = -sq; sr = -cq; break;
-            case 6: cr = s; sr = -c; break;
-            default: cr = cq; sr = -sq; break;
-        }
-        out[0] = cr;
-        out[1] = -sr;
-    };
+    auto expi = [&](long long mm, double* out) { unit_root(mm, nf, &out[0], &out[1]); };
     for (int i = 0; i < s_lo; ++i) expi(i, &hp->tw_lo[2 * i]);
     for (int k = 0; k < s_hi; ++k) expi(static_cast<long long>(k) * s_lo, &hp->tw_hi[2 * k]);
+    fft_stage_twiddles(lg, &hp->twr);
     return PHI_OK;
 }
 

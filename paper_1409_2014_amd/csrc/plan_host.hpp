@@ -47,6 +47,7 @@ struct HostPlan {
     std::vector<double> gy;             // [2 n_fine] (b, 1 - e^{-b}), signed frequency
     std::vector<double> tw_lo, tw_hi;   // (re, im) of e^{-2 pi i m / n_fine}: m < S and m = k S
     int tw_lo_log = 0;
+    std::vector<double> twr;            // (re, im) per-stage twiddles of the register FFT of length n_fine
 };
 
 phi_status fill_defaults(phi_params* p, int32_t n, double h, phi_dtype dtype);
@@ -56,6 +57,12 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err);
 phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err);
 
 void gauss_legendre(int n, double* x, double* w);
+// e^{-2 pi i m / n} with the angle reduced to the first octant (FP64).
+void unit_root(long long m, long long n, double* re, double* im);
+// Twiddles of the register-resident FFT of length 2^log (layout documented in
+// fft_reg.hpp): stage s >= 1 of radix R and span p holds W_{pR}^{t k},
+// t = 1..R-1, k = 0..p-1, at (t-1) p + k; stages back to back.
+void fft_stage_twiddles(int log, std::vector<double>* out);
 double es_kernel(double z, double beta);
 // int_{-1}^{1} phi(z) cos(omega z) dz
 double es_transform(double omega, double beta);

@@ -30,6 +30,7 @@
 
 #include "device_common.hpp"
 #include "fft_lds.hpp"
+#include "fft_reg.hpp"
 #include "solver_kernels.hpp"
 
 namespace phi {
@@ -70,82 +71,161 @@ constexpr int threads_for() {
 // ---------------------------------------------------------------------------
 // rows_forward
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int NT>
-__global__ __launch_bounds__(NT) void k_rows_forward(DevPlan P, const R* __restrict__ rho, R dir) {
-    constexpr int F = 1 << LOG;
+
+// Grid rows per block of the row kernels: as many as fit 1024 threads and about
+// 136 KB of LDS (one FFT buffer per row), so the column-major spectrum is
+// written and read in segments of G consecutive rows.
+template <typename R, int LOG>
+constexpr int rows_per_block() {
+    constexpr int nt = FftShape<LOG>::NT;
+    constexpr int by_threads = 1024 / nt;
+    constexpr int by_lds = static_cast<int>((136 * 1024) / (lds_padded_size(1 << LOG) * sizeof(cpx<R>)));
+    constexpr int g = by_threads < by_lds ? by_threads : by_lds;
+    constexpr int n = (1 << LOG) / 2;
+    return g < 1 ? 1 : (g > n ? n : g);
+}
+
+// Row `row` of the grid, at centred positions n' mod F: z = rho + i rho d(n1) d(n2)
+// (the type-2 deconvolution rides in the imaginary part), one F-point FFT; the
+// transform of the real part on m = 0..N is the I1 half spectrum, that of the
+// imaginary part on the Q window frequencies is the type-2 row window.
+template <typename R, int LOG>
+__global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_forward(
+    DevPlan P, const R* __restrict__ rho, R dir) {
+    using Sh = FftShape<LOG>;
+    constexpr int F = Sh::F;
     constexpr int N = F / 2;
-    __shared__ cpx<R> buf[lds_padded_size(F)];
-    __shared__ TwiddleLds<R, LOG> tw;
-    const int tid = threadIdx.x;
-    const int row = xcd_logical_block(blockIdx.x, gridDim.x);
-    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    constexpr int NT = Sh::NT;
+    constexpr int G = rows_per_block<R, LOG>();
+    constexpr int LP = lds_padded_size(F);
+    __shared__ cpx<R> lds_all[G * LP];
+    const int g = threadIdx.x / NT;
+    const int tid = threadIdx.x - g * NT;
+    cpx<R>* lds = lds_all + g * LP;
+    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
+    const int row0 = xcd_logical_block(blockIdx.x, gridDim.x) * G;
+    const int row = row0 + g;
     const double dy = P.deconv[row];
     const R* src = rho + static_cast<size_t>(row) * N;
-    for (int p = tid; p < F; p += NT) {
-        const int n1 = pos_to_grid<LOG>(p);
-        cpx<R> z = {R(0), R(0)};
-        if (n1 >= 0) {
+    const cpx<R> zero = {R(0), R(0)};
+    cpx<R> v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < 4 || i >= 12) {
+            const int n1 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
             const R r = src[n1];
-            z.x = r;
-            z.y = static_cast<R>(static_cast<double>(r) * P.deconv[n1] * dy);
+            v[i] = {r, static_cast<R>(static_cast<double>(r) * P.deconv[n1] * dy)};
+        } else {
+            v[i] = zero;
         }
-        buf[lds_pad(p)] = z;
     }
+    fft_reg<R, LOG>(v, lds, tw, tid, dir);
     __syncthreads();
-    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
-    // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2, m = 0..N
+#pragma unroll
+    for (int i = 0; i < 16; ++i) lds[lds_pad(tid + NT * i)] = v[i];
+    __syncthreads();
+    // outputs of the G rows, row index fastest: G-element runs of each column
     cpx<R>* xt = static_cast<cpx<R>*>(P.xt);
-    for (int m = tid; m <= N; m += NT) {
-        const cpx<R> a = buf[lds_pad(m)];
-        const cpx<R> b = buf[lds_pad((F - m) & (F - 1))];
-        xt[static_cast<size_t>(m) * N + row] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+    for (int idx = threadIdx.x; idx < (N + 1) * G; idx += NT * G) {
+        const int gg = idx % G;
+        const int m = idx / G;
+        const cpx<R>* l = lds_all + gg * LP;
+        const cpx<R> a = l[lds_pad(m)];
+        const cpx<R> b = l[lds_pad((F - m) & (F - 1))];
+        // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2
+        xt[static_cast<size_t>(m) * N + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
     }
-    // transform of the imaginary part on the window: (Z[l] - conj Z[-l]) / (2i)
     cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
-    for (int i = tid; i < P.patch; i += NT) {
-        const int l = P.patch_lo + i;
-        const cpx<R> a = buf[lds_pad(l & (F - 1))];
-        const cpx<R> b = buf[lds_pad((-l) & (F - 1))];
-        tt[static_cast<size_t>(i) * N + row] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
+    for (int idx = threadIdx.x; idx < P.patch * G; idx += NT * G) {
+        const int gg = idx % G;
+        const int i = idx / G;
+        const int lf = P.patch_lo + i;
+        const cpx<R>* l = lds_all + gg * LP;
+        const cpx<R> a = l[lds_pad(lf & (F - 1))];
+        const cpx<R> b = l[lds_pad((-lf) & (F - 1))];
+        // transform of the imaginary part: (Z[l] - conj Z[-l]) / (2i)
+        tt[static_cast<size_t>(i) * N + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
     }
 }
 
 // ---------------------------------------------------------------------------
 // cols_highfreq: FFT along y, multiplier, inverse FFT along y (in place in XT)
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int NT>
-__global__ __launch_bounds__(NT) void k_cols_highfreq(DevPlan P, R dir) {
-    constexpr int F = 1 << LOG;
-    constexpr int N = F / 2;
-    __shared__ cpx<R> buf[lds_padded_size(F)];
-    __shared__ TwiddleLds<R, LOG> tw;
-    const int tid = threadIdx.x;
-    const int m1 = xcd_logical_block(blockIdx.x, gridDim.x);   // 0..N
-    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
-    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(m1) * N;
-    for (int p = tid; p < F; p += NT) {
-        const int n2 = pos_to_grid<LOG>(p);
-        buf[lds_pad(p)] = (n2 >= 0) ? col[n2] : cpx<R>{R(0), R(0)};
+
+// Sequences per block of a register-FFT kernel: blocks of at least 256 threads.
+template <int LOG>
+constexpr int lines_per_block() {
+    constexpr int nt = FftShape<LOG>::NT;
+    return nt >= 256 ? 1 : 256 / nt;
+}
+
+template <typename R>
+__device__ __forceinline__ R recip(R x) {
+    if constexpr (sizeof(R) == 4) {
+        const float r = __builtin_amdgcn_rcpf(x);
+        return r * (2.0f - x * r);      // one Newton step: correctly rounded to within an ulp
+    } else {
+        return 1.0 / x;
     }
-    __syncthreads();
-    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+}
+
+// Column m1 of the half spectrum (contiguous in XT, N values at centred y
+// positions) is transformed along y with the zero padding implicit: in the
+// register layout position tid + NT i holds a grid row only for i < 4
+// (p < N/2) and i >= 12 (p >= F - N/2), so the other inputs are compile-time
+// zeros and the inverse transform's outputs there are never formed.
+template <typename R, int LOG>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P, R dir) {
+    using Sh = FftShape<LOG>;
+    constexpr int F = Sh::F;
+    constexpr int N = F / 2;
+    constexpr int NT = Sh::NT;
+    constexpr int G = lines_per_block<LOG>();
+    __shared__ cpx<R> lds_all[G * lds_padded_size(F)];
+    const int g = threadIdx.x / NT;
+    const int tid = threadIdx.x - g * NT;
+    cpx<R>* lds = lds_all + g * lds_padded_size(F);
+    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
+    const int m1 = xcd_logical_block(blockIdx.x, gridDim.x) * G + g;   // 0..N (+ idle lanes of the last block)
+    const bool active = m1 <= N;
+    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : 0) * N;
+    const cpx<R> zero = {R(0), R(0)};
+    cpx<R> v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < 4) {
+            v[i] = active ? col[tid + NT * i + N / 2] : zero;
+        } else if (i >= 12) {
+            v[i] = active ? col[tid + NT * (i - 12)] : zero;
+        } else {
+            v[i] = zero;
+        }
+    }
+    fft_reg<R, LOG>(v, lds, tw, tid, dir);
     // g1 = -(k_a^2/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with
     // 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a}, B = 1 - e^{-b} (all terms >= 0)
-    const R a = static_cast<R>(P.gx[2 * m1]);
-    const R A = static_cast<R>(P.gx[2 * m1 + 1]);
+    const int mc = active ? m1 : 0;
+    const R a = static_cast<R>(P.gx[2 * mc]);
+    const R A = static_cast<R>(P.gx[2 * mc + 1]);
     const R scale = static_cast<R>(P.inv_f2);
-    for (int m2 = tid; m2 < F; m2 += NT) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int m2 = tid + NT * i;
         const R b = static_cast<R>(P.gy[2 * m2]);
         const R B = static_cast<R>(P.gy[2 * m2 + 1]);
         const R num = P.component_y ? b : a;
         const R den = a + b;
-        const R g = (den > R(0)) ? -(num / den) * (A + B - A * B) * scale : R(0);
-        const int idx = lds_pad(m2);
-        buf[idx] = cscale(buf[idx], g);
+        const R gfac = (den > R(0)) ? -(num * recip(den)) * (A + B - A * B) * scale : R(0);
+        v[i] = cscale(v[i], gfac);
     }
-    __syncthreads();
-    fft_lds<R, LOG, NT>(buf, tw, tid, -dir);
-    for (int n2 = tid; n2 < N; n2 += NT) col[n2] = buf[lds_pad(centred_pos<LOG>(n2))];
+    fft_reg<R, LOG>(v, lds, tw, tid, -dir);
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < 4) col[tid + NT * i + N / 2] = v[i];
+            else if (i >= 12) col[tid + NT * (i - 12)] = v[i];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -258,50 +338,65 @@ __global__ __launch_bounds__(NT) void k_cols_type1(DevPlan P, R dir) {
 // ---------------------------------------------------------------------------
 // rows_inverse: Phi row = Re IFFT(S1 + i H) + Im IFFT(S1 + i H) d(n1)
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int NT>
-__global__ __launch_bounds__(NT) void k_rows_inverse(DevPlan P, R* __restrict__ out, R dir, int use_i1,
-                                                      int use_i2) {
-    constexpr int F = 1 << LOG;
+
+// For each of the block's G rows the full F-point row spectrum is assembled in
+// LDS: the Hermitian extension of the I1 half spectrum (column m of XT, conj at
+// F - m) plus i times the Hermitian part H[l] = (U[l] + conj U[-l]) / 2 of the
+// type-1 row on the window frequencies.  One inverse FFT then gives I1 in the
+// real part and Re(type-1 field) / d(n1) in the imaginary part.
+template <typename R, int LOG>
+__global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_inverse(
+    DevPlan P, R* __restrict__ out, R dir, int use_i1, int use_i2) {
+    using Sh = FftShape<LOG>;
+    constexpr int F = Sh::F;
     constexpr int N = F / 2;
-    __shared__ cpx<R> buf[lds_padded_size(F)];
-    __shared__ TwiddleLds<R, LOG> tw;
-    const int tid = threadIdx.x;
-    const int row = xcd_logical_block(blockIdx.x, gridDim.x);
-    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
+    constexpr int NT = Sh::NT;
+    constexpr int G = rows_per_block<R, LOG>();
+    constexpr int LP = lds_padded_size(F);
+    __shared__ cpx<R> lds_all[G * LP];
+    const int g = threadIdx.x / NT;
+    const int tid = threadIdx.x - g * NT;
+    cpx<R>* lds = lds_all + g * LP;
+    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
+    const int row0 = xcd_logical_block(blockIdx.x, gridDim.x) * G;
+    const int row = row0 + g;
     const cpx<R>* xt = static_cast<const cpx<R>*>(P.xt);
-    const cpx<R>* urow = static_cast<const cpx<R>*>(P.u) + static_cast<size_t>(row) * P.patch;
-    const int q = P.patch;
-    for (int p = tid; p < F; p += NT) {
-        cpx<R> v = {R(0), R(0)};
-        if (use_i1) {
-            // Hermitian extension of the real row's half spectrum
-            if (p <= N) {
-                v = xt[static_cast<size_t>(p) * N + row];
-            } else {
-                v = cconj(xt[static_cast<size_t>(F - p) * N + row]);
-            }
-        }
+    const cpx<R>* u = static_cast<const cpx<R>*>(P.u);
+    const int q = P.patch, lo = P.patch_lo;
+    for (int idx = threadIdx.x; idx < (N + 1) * G; idx += NT * G) {
+        const int gg = idx % G;
+        const int m = idx / G;
+        const int r = row0 + gg;
+        cpx<R> x = {R(0), R(0)};
+        if (use_i1) x = xt[static_cast<size_t>(m) * N + r];
+        cpx<R> hh = {R(0), R(0)};
         if (use_i2) {
-            const int l = (p < F / 2) ? p : p - F;          // signed fine-grid index
-            const int i = posmod_dev(l - P.patch_lo, F);
-            if (i < q) {
-                const cpx<R> ua = urow[i];
-                const int im = posmod_dev(-l - P.patch_lo, F);
-                const cpx<R> ub = (im < q) ? urow[im] : cpx<R>{R(0), R(0)};
-                // Hermitian part H = (U[l] + conj U[-l]) / 2; add i H
-                const cpx<R> hh = {R(0.5) * (ua.x + ub.x), R(0.5) * (ua.y - ub.y)};
-                v.x -= hh.y;
-                v.y += hh.x;
+            const int ia = posmod_dev(m - lo, F);
+            const int ib = posmod_dev(-m - lo, F);
+            if (ia < q || ib < q) {
+                const cpx<R>* urow = u + static_cast<size_t>(r) * q;
+                const cpx<R> ua = (ia < q) ? urow[ia] : cpx<R>{R(0), R(0)};
+                const cpx<R> ub = (ib < q) ? urow[ib] : cpx<R>{R(0), R(0)};
+                hh = {R(0.5) * (ua.x + ub.x), R(0.5) * (ua.y - ub.y)};
             }
         }
-        buf[lds_pad(p)] = v;
+        cpx<R>* l = lds_all + gg * LP;
+        // position m: X + i H;  position F - m: conj X + i conj H
+        l[lds_pad(m)] = {x.x - hh.y, x.y + hh.x};
+        if (m > 0 && m < N) l[lds_pad(F - m)] = {x.x + hh.y, -x.y + hh.x};
     }
     __syncthreads();
-    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
+    cpx<R> v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
+    fft_reg<R, LOG>(v, lds, tw, tid, dir);
     R* dst = out + static_cast<size_t>(row) * N;
-    for (int n1 = tid; n1 < N; n1 += NT) {
-        const cpx<R> z = buf[lds_pad(centred_pos<LOG>(n1))];
-        dst[n1] = static_cast<R>(static_cast<double>(z.x) + static_cast<double>(z.y) * P.deconv[n1]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < 4 || i >= 12) {
+            const int n1 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
+            dst[n1] = static_cast<R>(static_cast<double>(v[i].x) + static_cast<double>(v[i].y) * P.deconv[n1]);
+        }
     }
 }
 
@@ -460,16 +555,19 @@ namespace {
 
 template <typename R, int LOG>
 hipError_t launch_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
-    constexpr int NT = threads_for<LOG>();
-    hipLaunchKernelGGL((k_rows_forward<R, LOG, NT>), dim3(P.n), dim3(NT), 0, s, P,
+    if (P.twr_count != FftShape<LOG>::tw_size()) return hipErrorInvalidValue;
+    constexpr int G = rows_per_block<R, LOG>();
+    hipLaunchKernelGGL((k_rows_forward<R, LOG>), dim3(P.n / G), dim3(FftShape<LOG>::NT * G), 0, s, P,
                        static_cast<const R*>(rho), dir);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
 hipError_t launch_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
-    constexpr int NT = threads_for<LOG>();
-    hipLaunchKernelGGL((k_cols_highfreq<R, LOG, NT>), dim3(P.n + 1), dim3(NT), 0, s, P, dir);
+    if (P.twr_count != FftShape<LOG>::tw_size()) return hipErrorInvalidValue;
+    constexpr int G = lines_per_block<LOG>();
+    const int blocks = (P.n + 1 + G - 1) / G;
+    hipLaunchKernelGGL((k_cols_highfreq<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
     return hipGetLastError();
 }
 
@@ -489,9 +587,10 @@ hipError_t launch_cols_type1(const DevPlan& P, R dir, hipStream_t s) {
 
 template <typename R, int LOG>
 hipError_t launch_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int use_i2, hipStream_t s) {
-    constexpr int NT = threads_for<LOG>();
-    hipLaunchKernelGGL((k_rows_inverse<R, LOG, NT>), dim3(P.n), dim3(NT), 0, s, P, static_cast<R*>(out), dir,
-                       use_i1, use_i2);
+    if (P.twr_count != FftShape<LOG>::tw_size()) return hipErrorInvalidValue;
+    constexpr int G = rows_per_block<R, LOG>();
+    hipLaunchKernelGGL((k_rows_inverse<R, LOG>), dim3(P.n / G), dim3(FftShape<LOG>::NT * G), 0, s, P,
+                       static_cast<R*>(out), dir, use_i1, use_i2);
     return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@ struct DevPlan {
     const double* gy;       // [2 F]
     const double* tw_lo;    // [2 S]
     const double* tw_hi;    // [2 F/S]
+    const void* twr;        // register-FFT stage twiddles, data precision, twr_count complex
+    int twr_count;
     const double* ux;       // [M]
     const double* uy;       // [M]
     const double* q;        // [M] (without h^2)
