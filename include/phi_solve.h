@@ -82,8 +82,8 @@ typedef struct {
     int32_t kernel_width;  /* exponential-of-semicircle kernel width w (cells)   */
     int32_t patch;         /* side Q of the fine-grid window the nodes touch     */
     int32_t patch_lo;      /* lowest fine-grid index of that window (= -Q/2)     */
-    int32_t n_subproblems; /* bin-sorted node chunks used by interp / spread     */
-    int32_t bin_size;      /* bin side in fine-grid cells                        */
+    int32_t max_cell_nodes;/* most nodes whose first kernel tap is one cell      */
+    int32_t max_gather;    /* most nodes whose taps cover one window cell        */
     double h, half_width, sigma, cutoff, beta;
     size_t device_bytes;   /* tables + workspace allocated by phi_plan           */
 } phi_plan_info;

@@ -34,7 +34,7 @@ class PhiPlanInfo(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32), ("n_fine", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
         ("kernel_width", ctypes.c_int32), ("patch", ctypes.c_int32), ("patch_lo", ctypes.c_int32),
-        ("n_subproblems", ctypes.c_int32), ("bin_size", ctypes.c_int32),
+        ("max_cell_nodes", ctypes.c_int32), ("max_gather", ctypes.c_int32),
         ("h", ctypes.c_double), ("half_width", ctypes.c_double), ("sigma", ctypes.c_double),
         ("cutoff", ctypes.c_double), ("beta", ctypes.c_double),
         ("device_bytes", ctypes.c_size_t),

@@ -27,9 +27,53 @@
 #pragma once
 
 #include "device_common.hpp"
-#include "fft_lds.hpp"   // RegDft, root16
 
 namespace phi {
+
+// cos / sin of 2 pi a / 16, a = 0..7 (the 16th roots of unity, correctly rounded).
+template <typename R>
+__device__ __forceinline__ cpx<R> root16(int a, R dir) {
+    constexpr double C[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                             0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+    constexpr double S[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                             1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+    return {static_cast<R>(C[a]), dir * static_cast<R>(S[a])};
+}
+
+// In-register DFT of length RAD (1, 2, 4, 8, 16) by even/odd splitting:
+// v[k] <- sum_j v[j] e^{dir 2 pi i j k / RAD}.
+template <int RAD, typename R>
+struct RegDft {
+    __device__ __forceinline__ static void run(cpx<R>* v, R dir) {
+        constexpr int H = RAD / 2;
+        cpx<R> e[H], o[H];
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+            e[t] = v[2 * t];
+            o[t] = v[2 * t + 1];
+        }
+        RegDft<H, R>::run(e, dir);
+        RegDft<H, R>::run(o, dir);
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            cpx<R> t;
+            if (k == 0) {
+                t = o[k];
+            } else if (4 * k == RAD) {
+                t = cmul_si(o[k], dir);
+            } else {
+                t = cmul(o[k], root16<R>(k * (16 / RAD), dir));
+            }
+            v[k] = cadd(e[k], t);
+            v[k + H] = csub(e[k], t);
+        }
+    }
+};
+
+template <typename R>
+struct RegDft<1, R> {
+    __device__ __forceinline__ static void run(cpx<R>*, R) {}
+};
 
 template <int LOG>
 struct FftShape {

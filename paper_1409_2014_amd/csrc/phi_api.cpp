@@ -17,6 +17,7 @@
 struct phi_plan_s {
     phi::HostPlan host;
     phi::DevPlan dev;
+    phi::StreamSet streams;     // side stream + fork/join events of the node-side chain
     phi_params params;
     int device = 0;
     void* block = nullptr;      // one device allocation: tables + workspace
@@ -69,7 +70,7 @@ phi_status run(phi_plan_t plan, phi::Stage stage, const void* in, void* out, int
     if (cur != plan->device) {
         return fail(plan, PHI_ERR_INVALID_ARG, "current device differs from the plan's device");
     }
-    e = phi::enqueue(plan->dev, stage, in, out, adjoint, static_cast<hipStream_t>(stream));
+    e = phi::enqueue(plan->dev, plan->streams, stage, in, out, adjoint, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
     return PHI_OK;
 }
@@ -108,8 +109,8 @@ static void fill_info(const phi::HostPlan& hp, size_t bytes, phi_plan_info* info
     info->kernel_width = hp.width;
     info->patch = hp.patch;
     info->patch_lo = hp.patch_lo;
-    info->n_subproblems = hp.n_sub;
-    info->bin_size = hp.bin;
+    info->max_cell_nodes = hp.max_cell_nodes;
+    info->max_gather = hp.max_gather;
     info->h = hp.h;
     info->half_width = hp.half_width;
     info->sigma = hp.sigma;
@@ -162,20 +163,18 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         Part p_deconv = take(n * 8);
         Part p_gx = take(2 * (n + 1) * 8);
         Part p_gy = take(2 * f * 8);
-        Part p_twlo = take(hp.tw_lo.size() * 8);
-        Part p_twhi = take(hp.tw_hi.size() * 8);
-        Part p_twr = take(hp.twr.size() * es);
-        Part p_ux = take(m * 8);
-        Part p_uy = take(m * 8);
         Part p_q = take(m * 8);
+        Part p_cell = take(hp.cell.size() * 4);
         Part p_sub = take(hp.sub.size() * 4);
-        Part p_bins = take(hp.bin_start.size() * 4);
+        Part p_cst = take(hp.contrib_start.size() * 4);
+        Part p_con = take(hp.contrib.size() * 4);
+        Part p_taps = take(hp.taps.size() * es);
+        Part p_twr = take(hp.twr.size() * es);
         Part p_xt = take((n + 1) * n * 2 * es);
         Part p_tt = take(q * n * 2 * es);
         Part p_win = take(q * q * 2 * es);
         Part p_pts = take(m * 2 * es);
-        const size_t tile = static_cast<size_t>(hp.bin + hp.width - 1);
-        Part p_tiles = take(static_cast<size_t>(hp.n_sub) * tile * tile * 2 * es);
+        Part p_tiles = take(static_cast<size_t>(hp.n_sub) * hp.tile * hp.tile * 2 * es);
         Part p_u = take(n * q * 2 * es);
         plan->block_bytes = cursor;
         e = hipMalloc(&plan->block, cursor);
@@ -190,27 +189,38 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
             if (pt.bytes == 0) return hipSuccess;
             return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
         };
+        // kernel taps and FFT twiddles are rounded once from FP64 to the data precision
+        std::vector<float> taps32, twr32;
+        if (p->dtype == PHI_F32) {
+            taps32.assign(hp.taps.begin(), hp.taps.end());
+            twr32.assign(hp.twr.begin(), hp.twr.end());
+        }
+        const bool f32 = (p->dtype == PHI_F32);
         hipError_t ce = hipSuccess;
         if (ce == hipSuccess) ce = up(p_deconv, hp.deconv.data());
         if (ce == hipSuccess) ce = up(p_gx, hp.gx.data());
         if (ce == hipSuccess) ce = up(p_gy, hp.gy.data());
-        if (ce == hipSuccess) ce = up(p_twlo, hp.tw_lo.data());
-        if (ce == hipSuccess) ce = up(p_twhi, hp.tw_hi.data());
-        // stage twiddles rounded once from FP64 to the data precision
-        std::vector<float> twr32;
-        if (p->dtype == PHI_F32) twr32.assign(hp.twr.begin(), hp.twr.end());
-        if (ce == hipSuccess) ce = up(p_twr, (p->dtype == PHI_F32) ? static_cast<const void*>(twr32.data())
-                                                                  : static_cast<const void*>(hp.twr.data()));
-        if (ce == hipSuccess) ce = up(p_ux, hp.ux.data());
-        if (ce == hipSuccess) ce = up(p_uy, hp.uy.data());
         if (ce == hipSuccess) ce = up(p_q, hp.q.data());
+        if (ce == hipSuccess) ce = up(p_cell, hp.cell.data());
         if (ce == hipSuccess) ce = up(p_sub, hp.sub.data());
-        if (ce == hipSuccess) ce = up(p_bins, hp.bin_start.data());
+        if (ce == hipSuccess) ce = up(p_cst, hp.contrib_start.data());
+        if (ce == hipSuccess) ce = up(p_con, hp.contrib.data());
+        if (ce == hipSuccess) ce = up(p_taps, f32 ? static_cast<const void*>(taps32.data())
+                                                  : static_cast<const void*>(hp.taps.data()));
+        if (ce == hipSuccess) ce = up(p_twr, f32 ? static_cast<const void*>(twr32.data())
+                                                 : static_cast<const void*>(hp.twr.data()));
         if (ce == hipSuccess) ce = hipStreamSynchronize(s);
+        // the node-side chain runs on a second stream of the plan's device, default priority
+        if (ce == hipSuccess) ce = hipStreamCreateWithFlags(&plan->streams.side, hipStreamNonBlocking);
+        if (ce == hipSuccess) ce = hipEventCreateWithFlags(&plan->streams.fork, hipEventDisableTiming);
+        if (ce == hipSuccess) ce = hipEventCreateWithFlags(&plan->streams.join, hipEventDisableTiming);
         if (ce != hipSuccess) {
+            if (plan->streams.join) (void)hipEventDestroy(plan->streams.join);
+            if (plan->streams.fork) (void)hipEventDestroy(plan->streams.fork);
+            if (plan->streams.side) (void)hipStreamDestroy(plan->streams.side);
             (void)hipFree(plan->block);
             delete plan;
-            return device_fail(nullptr, ce, "table upload");
+            return device_fail(nullptr, ce, "plan setup");
         }
         phi::DevPlan& d = plan->dev;
         d.dtype = p->dtype;
@@ -220,27 +230,24 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         d.patch = hp.patch;
         d.patch_lo = hp.patch_lo;
         d.width = hp.width;
-        d.bin = hp.bin;
         d.n_nodes = hp.n_nodes;
-        d.n_sub = hp.n_sub;
         d.component_y = hp.component_y;
-        d.beta = hp.beta;
         d.h2 = hp.h * hp.h;
         d.inv_f2 = 1.0 / (static_cast<double>(f) * static_cast<double>(f));
         d.deconv = reinterpret_cast<const double*>(base + p_deconv.off);
         d.gx = reinterpret_cast<const double*>(base + p_gx.off);
         d.gy = reinterpret_cast<const double*>(base + p_gy.off);
-        d.tw_lo = reinterpret_cast<const double*>(base + p_twlo.off);
-        d.tw_hi = reinterpret_cast<const double*>(base + p_twhi.off);
+        d.q = reinterpret_cast<const double*>(base + p_q.off);
+        d.cell = reinterpret_cast<const int*>(base + p_cell.off);
+        d.sub = reinterpret_cast<const int*>(base + p_sub.off);
+        d.contrib_start = reinterpret_cast<const int*>(base + p_cst.off);
+        d.contrib = reinterpret_cast<const int*>(base + p_con.off);
+        d.n_sub = hp.n_sub;
+        d.bin = hp.bin;
+        d.tile = hp.tile;
+        d.taps = base + p_taps.off;
         d.twr = base + p_twr.off;
         d.twr_count = static_cast<int>(hp.twr.size() / 2);
-        d.ux = reinterpret_cast<const double*>(base + p_ux.off);
-        d.uy = reinterpret_cast<const double*>(base + p_uy.off);
-        d.q = reinterpret_cast<const double*>(base + p_q.off);
-        d.sub = reinterpret_cast<const int*>(base + p_sub.off);
-        d.bin_start = reinterpret_cast<const int*>(base + p_bins.off);
-        d.nb = hp.nb;
-        d.tile = static_cast<int>(tile);
         d.xt = base + p_xt.off;
         d.tt = base + p_tt.off;
         d.win = base + p_win.off;
@@ -280,7 +287,12 @@ phi_status phi_destroy(phi_plan_t plan) {
     if (prev != plan->device) (void)hipSetDevice(plan->device);
     hipError_t e = hipDeviceSynchronize();   // the plan's last stream work may still read its tables
     if (e == hipSuccess && plan->timer_ready) {
-        for (int i = 0; i < phi::KernelTimer::kMax; ++i) (void)hipEventDestroy(plan->timer.ev[i]);
+        for (int i = 0; i < 2 * phi::KernelTimer::kMax; ++i) (void)hipEventDestroy(plan->timer.ev[i]);
+    }
+    if (e == hipSuccess) {
+        (void)hipEventDestroy(plan->streams.join);
+        (void)hipEventDestroy(plan->streams.fork);
+        (void)hipStreamDestroy(plan->streams.side);
     }
     if (e == hipSuccess) e = hipFree(plan->block);
     if (e != hipSuccess) st = fail(nullptr, PHI_ERR_DEVICE, std::string("phi_destroy: ") + hipGetErrorString(e));
@@ -344,7 +356,7 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
     if (cur != plan->device) return fail(plan, PHI_ERR_INVALID_ARG, "current device differs from the plan's device");
     phi::KernelTimer& t = plan->timer;
     if (!plan->timer_ready) {
-        for (int i = 0; i < phi::KernelTimer::kMax; ++i) {
+        for (int i = 0; i < 2 * phi::KernelTimer::kMax; ++i) {
             e = hipEventCreate(&t.ev[i]);
             if (e != hipSuccess) {
                 for (int k = 0; k < i; ++k) (void)hipEventDestroy(t.ev[k]);
@@ -355,15 +367,14 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
     }
     t.count = 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    e = phi::enqueue(plan->dev, phi::Stage::Solve, in, out, adjoint ? 1 : 0, s, &t);
+    e = phi::enqueue(plan->dev, plan->streams, phi::Stage::Solve, in, out, adjoint ? 1 : 0, s, &t);
     if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(plan, e, "hipStreamSynchronize");
-    const int kernels = t.count - 1;
-    *count = kernels;
-    for (int i = 0; i < kernels && i < capacity; ++i) {
+    *count = t.count;
+    for (int i = 0; i < t.count && i < capacity; ++i) {
         float ms = 0.f;
-        e = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]);
+        e = hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]);
         if (e != hipSuccess) return device_fail(plan, e, "hipEventElapsedTime");
         kernel_ms[i] = ms;
         names[i] = t.names[i];

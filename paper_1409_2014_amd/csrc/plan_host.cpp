@@ -31,8 +31,7 @@ std::string fmt(const char* f, double a = 0, double b = 0) {
     return buf;
 }
 
-// Floor division / modulo for possibly negative numerators.
-int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+// Modulo for possibly negative numerators.
 int posmod(int a, int b) { int r = a % b; return r < 0 ? r + b : r; }
 
 }  // namespace
@@ -267,67 +266,114 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
     const int n = hp->n, nf = hp->n_fine, w = hp->width;
     const double half_w = 0.5 * w;
 
-    // ---- polar nodes, positions in fine-grid cells, bin sort -------------------
+    // ---- polar nodes, first kernel tap, sort by first-tap cell, taps ------------
     std::vector<double> kx, ky, q;
     polar_nodes(*hp, &kx, &ky, &q);
     const int m = hp->n_nodes;
-    std::vector<double> ux(m), uy(m);
-    std::vector<int> l0x(m), l0y(m);
     const int q_side = hp->patch, lo = hp->patch_lo;
+    std::vector<double> ux(m), uy(m);
+    std::vector<int> cx(m), cy(m);
     for (int j = 0; j < m; ++j) {
-        // t_j / Delta with t_j = 2 pi h k_j, Delta = 2 pi / n_fine
+        // t_j / Delta with t_j = 2 pi h k_j, Delta = 2 pi / n_fine: node position in cells
         ux[j] = nf * hp->h * kx[j];
         uy[j] = nf * hp->h * ky[j];
-        int ax = static_cast<int>(std::ceil(ux[j] - half_w));
-        int ay = static_cast<int>(std::ceil(uy[j] - half_w));
-        // first tap, wrapped into [lo, lo + n_fine) (only matters when the window
-        // is the whole periodic fine grid)
-        ax = lo + posmod(ax - lo, nf);
-        ay = lo + posmod(ay - lo, nf);
-        if (q_side < nf && (ax + w - 1 >= lo + q_side || ay + w - 1 >= lo + q_side)) {
+        // first tap l0 = ceil(u - w/2), as a window cell (wrapped when the window is
+        // the whole periodic fine grid)
+        const int ax = posmod(static_cast<int>(std::ceil(ux[j] - half_w)) - lo, nf);
+        const int ay = posmod(static_cast<int>(std::ceil(uy[j] - half_w)) - lo, nf);
+        if (q_side < nf && (ax + w > q_side || ay + w > q_side)) {
             *err = "internal: node taps outside the fine-grid window";
             return PHI_ERR_INTERNAL;
         }
-        l0x[j] = ax;
-        l0y[j] = ay;
+        cx[j] = ax;
+        cy[j] = ay;
     }
+    // bins of kBinSize x kBinSize window cells; nodes sorted by the bin of their first tap
     const int bin = kBinSize;
-    const int nb = (std::max(q_side, 1) + bin - 1) / bin;
+    const int nb = q_side / bin;        // the window side is a power of two >= 16
+    const bool whole = (q_side == nf);
     std::vector<int> key(m);
-    for (int j = 0; j < m; ++j) {
-        int bx = floordiv(l0x[j] - lo, bin);
-        int by = floordiv(l0y[j] - lo, bin);
-        key[j] = by * nb + bx;
-    }
+    for (int j = 0; j < m; ++j) key[j] = (cy[j] / bin) * nb + cx[j] / bin;
     std::vector<int> order(m);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-    hp->kx.resize(m); hp->ky.resize(m); hp->q.resize(m); hp->ux.resize(m); hp->uy.resize(m);
+    hp->kx.resize(m); hp->ky.resize(m); hp->q.resize(m);
+    hp->cell.resize(2 * static_cast<size_t>(m));
+    hp->taps.resize(static_cast<size_t>(m) * 2 * w);
     for (int i = 0; i < m; ++i) {
         const int j = order[i];
         hp->kx[i] = kx[j]; hp->ky[i] = ky[j]; hp->q[i] = q[j];
-        hp->ux[i] = ux[j]; hp->uy[i] = uy[j];
+        hp->cell[2 * i] = cx[j];
+        hp->cell[2 * i + 1] = cy[j];
+        // psi(u - l) for the w taps l = l0 .. l0 + w - 1
+        const double l0x = std::ceil(ux[j] - half_w), l0y = std::ceil(uy[j] - half_w);
+        for (int t = 0; t < w; ++t) {
+            hp->taps[(static_cast<size_t>(i) * 2 + 0) * w + t] = es_kernel((ux[j] - (l0x + t)) / half_w, hp->beta);
+            hp->taps[(static_cast<size_t>(i) * 2 + 1) * w + t] = es_kernel((uy[j] - (l0y + t)) / half_w, hp->beta);
+        }
     }
+    // subproblems: runs of at most kMaxNodesPerSub nodes of one bin
     hp->sub.clear();
-    hp->bin_start.assign(static_cast<size_t>(nb) * nb + 1, 0);
+    int max_bin = 0;
     for (int i = 0; i < m;) {
         const int k = key[order[i]];
         int e = i;
         while (e < m && key[order[e]] == k) ++e;
-        const int bx = k % nb, by = k / nb;
-        for (int s = i; s < e; s += kMaxNodesPerSub) {
-            hp->sub.push_back(lo + bx * bin);
-            hp->sub.push_back(lo + by * bin);
-            hp->sub.push_back(s);
-            hp->sub.push_back(std::min(kMaxNodesPerSub, e - s));
-            hp->bin_start[k + 1] += 1;
+        max_bin = std::max(max_bin, e - i);
+        for (int s0 = i; s0 < e; s0 += kMaxNodesPerSub) {
+            hp->sub.push_back(k % nb);
+            hp->sub.push_back(k / nb);
+            hp->sub.push_back(s0);
+            hp->sub.push_back(std::min(kMaxNodesPerSub, e - s0));
         }
         i = e;
     }
-    for (size_t b = 1; b < hp->bin_start.size(); ++b) hp->bin_start[b] += hp->bin_start[b - 1];
     hp->bin = bin;
     hp->nb = nb;
+    hp->tile = bin + w - 1;
     hp->n_sub = static_cast<int>(hp->sub.size() / 4);
+    hp->max_cell_nodes = max_bin;
+    // window cell <- tile entries: every tile cell inside the box its nodes' taps
+    // can reach, mapped to its window cell (wrapped when the window is periodic)
+    const int E = hp->tile;
+    std::vector<std::pair<int, int>> pairs;   // (window cell, flat tile index)
+    for (int sidx = 0; sidx < hp->n_sub; ++sidx) {
+        const int bx = hp->sub[4 * sidx], by = hp->sub[4 * sidx + 1];
+        const int first = hp->sub[4 * sidx + 2], count = hp->sub[4 * sidx + 3];
+        int ox0 = bin, ox1 = -1, oy0 = bin, oy1 = -1;
+        for (int i = first; i < first + count; ++i) {
+            ox0 = std::min(ox0, hp->cell[2 * i] - bx * bin);
+            ox1 = std::max(ox1, hp->cell[2 * i] - bx * bin);
+            oy0 = std::min(oy0, hp->cell[2 * i + 1] - by * bin);
+            oy1 = std::max(oy1, hp->cell[2 * i + 1] - by * bin);
+        }
+        for (int cb = oy0; cb <= oy1 + w - 1; ++cb) {
+            for (int ca = ox0; ca <= ox1 + w - 1; ++ca) {
+                int wx = bx * bin + ca, wy = by * bin + cb;
+                if (whole) {
+                    wx %= q_side;
+                    wy %= q_side;
+                } else if (wx >= q_side || wy >= q_side) {
+                    continue;
+                }
+                pairs.emplace_back(wx * q_side + wy, sidx * E * E + cb * E + ca);
+            }
+        }
+    }
+    std::stable_sort(pairs.begin(), pairs.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+    hp->contrib_start.assign(static_cast<size_t>(q_side) * q_side + 1, 0);
+    hp->contrib.resize(pairs.size());
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        hp->contrib_start[pairs[k].first + 1] += 1;
+        hp->contrib[k] = pairs[k].second;
+    }
+    int max_gather = 0;
+    for (size_t c = 1; c < hp->contrib_start.size(); ++c) {
+        max_gather = std::max(max_gather, hp->contrib_start[c]);
+        hp->contrib_start[c] += hp->contrib_start[c - 1];
+    }
+    hp->max_gather = max_gather;
 
     // ---- deconvolution factors 2 pi / (n_fine psi_hat(n')) ---------------------
     // psi(x) = phi(x / a) with a = (w/2) Delta the kernel half-width in radians:
@@ -358,16 +404,8 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
         hp->gy[2 * m2 + 1] = -std::expm1(-b);
     }
 
-    // ---- twiddles, two-level: e^{-2 pi i m / n_fine} for m < S and m = k S -----
+    // ---- register-FFT stage twiddles --------------------------------------------
     const int lg = hp->log_fine;
-    hp->tw_lo_log = (lg + 1) / 2;
-    const int s_lo = 1 << hp->tw_lo_log;
-    const int s_hi = nf / s_lo;
-    hp->tw_lo.resize(2 * s_lo);
-    hp->tw_hi.resize(2 * s_hi);
-    auto expi = [&](long long mm, double* out) { unit_root(mm, nf, &out[0], &out[1]); };
-    for (int i = 0; i < s_lo; ++i) expi(i, &hp->tw_lo[2 * i]);
-    for (int k = 0; k < s_hi; ++k) expi(static_cast<long long>(k) * s_lo, &hp->tw_hi[2 * k]);
     fft_stage_twiddles(lg, &hp->twr);
     return PHI_OK;
 }

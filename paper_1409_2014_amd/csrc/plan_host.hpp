@@ -15,9 +15,9 @@ namespace phi {
 
 constexpr int kMaxLogFine = 13;        // fine grid up to 8192 (N up to 4096)
 constexpr int kMinLogFine = 4;         // fine grid from 16 (N from 8)
+constexpr int kMaxKernelWidth = 16;
 constexpr int kBinSize = 8;            // bin side in fine-grid cells
 constexpr int kMaxNodesPerSub = 64;    // nodes per interp / spread subproblem
-constexpr int kMaxKernelWidth = 16;
 
 struct HostPlan {
     // problem
@@ -33,20 +33,24 @@ struct HostPlan {
     double beta = 0;
     // fine-grid window touched by the nodes' kernel taps: [patch_lo, patch_lo + patch)
     int patch = 0, patch_lo = 0;
-    // bin sort: bins of bin x bin cells tile the window, nb per side
-    int bin = kBinSize, n_sub = 0, nb = 0;
 
-    // node data in plan order (bin-sorted)
+    // node data in plan order: sorted by bin (bin x bin window cells) of the first kernel tap
     std::vector<double> kx, ky, q;      // k_j and q_j of eq. 12 (q without h^2)
-    std::vector<double> ux, uy;         // node positions in fine-grid cells: n_fine h k
-    std::vector<int32_t> sub;           // per subproblem: tile_lo1, tile_lo2, first node, count
-    std::vector<int32_t> bin_start;     // [nb*nb + 1] subproblems of bin b are bin_start[b] .. bin_start[b+1]-1
+    std::vector<int32_t> cell;          // [2 M] first-tap window cell (x, y), 0 <= c < patch
+    std::vector<double> taps;           // [M][2][w] psi(u_j - l0_j - t), x then y
+    int bin = 8, nb = 0;                // bin side in cells, bins per window side
+    int tile = 0;                       // spread tile side E = bin + w - 1
+    std::vector<int32_t> sub;           // [4 n_sub] bin x, bin y, first node, node count (<= 64)
+    int n_sub = 0;
+    // reduction of the subproblem tiles onto the window: for window cell c = x * patch + y,
+    // entries contrib_start[c] .. contrib_start[c+1]-1 of contrib hold flat tile indices
+    std::vector<int32_t> contrib_start, contrib;
+    int max_cell_nodes = 0;             // most nodes of one subproblem's bin
+    int max_gather = 0;                 // most tile entries summed into one window cell
     // tables
     std::vector<double> deconv;         // [N] 2 pi / (n_fine psi_hat(n')), n' = i - N/2
     std::vector<double> gx;             // [2 (N+1)] (a, 1 - e^{-a}),  a = kx^2 / sigma^2, kx = m/(n_fine h)
     std::vector<double> gy;             // [2 n_fine] (b, 1 - e^{-b}), signed frequency
-    std::vector<double> tw_lo, tw_hi;   // (re, im) of e^{-2 pi i m / n_fine}: m < S and m = k S
-    int tw_lo_log = 0;
     std::vector<double> twr;            // (re, im) per-stage twiddles of the register FFT of length n_fine
 };
 

@@ -1,35 +1,36 @@
 // HIP kernels of the split potential solve for gfx950 (see phi_solve.h).
 //
-// One solve runs seven stream-ordered kernels (N = grid side, F = 2N the side
-// of both the zero-padded I1 box and the NUFFT fine grid, Q = side of the
-// fine-grid window the polar nodes touch):
+// N = grid side, F = 2N the side of both the zero-padded I1 box and the NUFFT
+// fine grid, Q = side of the fine-grid window around frequency 0 that the
+// polar nodes' kernel taps touch, M = number of polar nodes, w = kernel width.
+// A solve runs six kernels; the node-side chain runs on a second stream
+// concurrently with the I1 column pass:
 //
 //   rows_forward   per grid row: z = rho + i rho d(n1) d(n2) at centred
-//                  positions, one F-point FFT, then split the two real
-//                  transforms: the I1 half spectrum (N+1 values) goes to the
-//                  column-major buffer XT, the type-2 window (Q values) to TT.
-//                  [Sec. 2.1, eq. 9 zero-padded FFT; Sec. 2.2 type 2: deconvolve + FFT]
+//                  positions, one F-point FFT; the transform of the real part
+//                  on m = 0..N (I1 half spectrum) goes to the column-major XT,
+//                  that of the imaginary part on the Q window frequencies (the
+//                  type-2 row window) to TT.   [Sec. 2.1 eq. (9); Sec. 2.2 eq. (16)]
 //   cols_highfreq  per spectrum column: F-point FFT, times g1(k)/F^2, inverse
-//                  FFT, keep the N centred rows, in place in XT.   [eq. 9]
-//   cols_type2     per window column of TT: F-point FFT, keep the Q window rows.
-//   interp         per bin-sorted subproblem: stage the fine-grid tile in LDS,
-//                  interpolate rho_hat(k_j) = h^2 sum_taps b psi psi with 16-lane
-//                  reductions, multiply by q_j.             [eq. 12, a_j = q_j rho_hat_j]
-//   spread         per subproblem: the transposed taps accumulate a_j psi psi
-//                  into an LDS tile (compensated sums in FP32); the tile goes
-//                  to the subproblem's own slot (no atomics).  [type 1 spreading]
-//   cols_type1     per window column: sum the tiles covering it in a fixed
-//                  order, F-point FFT (only Q non-zero inputs), keep the N
-//                  centred rows, times d(n2).
-//   rows_inverse   per grid row: rebuild the full Hermitian I1 row spectrum plus
-//                  i times the Hermitian part of the type-1 row, one F-point
-//                  FFT; Phi = Re + Im d(n1).       [eq. 8: Phi = I1 + Re I2]
+//                  FFT, the N centred rows back into XT.            [eq. (9)]
+//   side stream:
+//   cols_type2     per window column of TT: F-point FFT, the Q window rows -> WIN.
+//   nodes          per subproblem (<= 64 nodes of one bin): stage the window
+//                  tile and the nodes' precomputed kernel taps in LDS,
+//                  interpolate c_j, a_j = q_j h^2 c_j, spread the a_j into the
+//                  subproblem's own tile (no atomics).  [eq. (12), (15), (16)]
+//   cols_type1     per window column: sum the tile entries of each cell in a
+//                  fixed order, F-point FFT (only the Q window inputs are
+//                  non-zero), the N centred rows times d(n2) -> U.
+//   main stream, after both:
+//   rows_inverse   per grid row: the Hermitian I1 row spectrum plus i times the
+//                  Hermitian part of the type-1 row, one F-point FFT;
+//                  Phi = Re + Im d(n1).                 [eq. (8): Phi = I1 + Re I2]
 //
 // The transposed solve runs the same kernels with every FFT direction reversed.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
-#include "fft_lds.hpp"
 #include "fft_reg.hpp"
 #include "solver_kernels.hpp"
 
@@ -40,30 +41,6 @@ namespace {
 __device__ __forceinline__ int posmod_dev(int a, int b) {
     int r = a % b;
     return r < 0 ? r + b : r;
-}
-
-// Centred grid index n (0..N-1, n' = n - N/2) -> position n' mod F on the fine grid.
-template <int LOG>
-__device__ __forceinline__ int centred_pos(int n) {
-    constexpr int F = 1 << LOG;
-    constexpr int N = F / 2;
-    return (n - N / 2) & (F - 1);
-}
-
-// Inverse of centred_pos: position p -> grid index, or -1 for a padding position.
-template <int LOG>
-__device__ __forceinline__ int pos_to_grid(int p) {
-    constexpr int F = 1 << LOG;
-    constexpr int N = F / 2;
-    if (p < N / 2) return p + N / 2;
-    if (p >= F - N / 2) return p - (F - N / 2);
-    return -1;
-}
-
-template <int LOG>
-constexpr int threads_for() {
-    constexpr int F = 1 << LOG;
-    return (F / 16 < 64) ? 64 : (F / 16 > 256 ? 256 : F / 16);
 }
 
 }  // namespace
@@ -231,107 +208,250 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
 // ---------------------------------------------------------------------------
 // cols_type2: FFT along y of the type-2 row window, keep the Q window rows
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int NT>
-__global__ __launch_bounds__(NT) void k_cols_type2(DevPlan P, R dir) {
-    constexpr int F = 1 << LOG;
+template <typename R, int LOG>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type2(DevPlan P, R dir) {
+    using Sh = FftShape<LOG>;
+    constexpr int F = Sh::F;
     constexpr int N = F / 2;
-    __shared__ cpx<R> buf[lds_padded_size(F)];
-    __shared__ TwiddleLds<R, LOG> tw;
-    const int tid = threadIdx.x;
-    const int i1 = blockIdx.x;
-    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
-    const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(i1) * N;
-    for (int p = tid; p < F; p += NT) {
-        const int n2 = pos_to_grid<LOG>(p);
-        buf[lds_pad(p)] = (n2 >= 0) ? col[n2] : cpx<R>{R(0), R(0)};
+    constexpr int NT = Sh::NT;
+    constexpr int G = lines_per_block<LOG>();
+    __shared__ cpx<R> lds_all[G * lds_padded_size(F)];
+    const int g = threadIdx.x / NT;
+    const int tid = threadIdx.x - g * NT;
+    cpx<R>* lds = lds_all + g * lds_padded_size(F);
+    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
+    const int q = P.patch;
+    const int i1 = blockIdx.x * G + g;
+    const bool active = i1 < q;
+    const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(active ? i1 : 0) * N;
+    const cpx<R> zero = {R(0), R(0)};
+    cpx<R> v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < 4) {
+            v[i] = active ? col[tid + NT * i + N / 2] : zero;
+        } else if (i >= 12) {
+            v[i] = active ? col[tid + NT * (i - 12)] : zero;
+        } else {
+            v[i] = zero;
+        }
+    }
+    fft_reg<R, LOG>(v, lds, tw, tid, dir);
+    cpx<R>* win = static_cast<cpx<R>*>(P.win);
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int i2 = posmod_dev(tid + NT * i - P.patch_lo, F);   // window row of this position
+            if (i2 < q) win[static_cast<size_t>(i2) * q + i1] = v[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// nodes: interpolation, polar multiplier and spreading of one subproblem
+// ---------------------------------------------------------------------------
+// A subproblem is a run of at most 64 nodes whose first kernel taps lie in one
+// bin of bin x bin window cells, so all their taps fall in the E x E tile
+// (E = bin + w - 1) at the bin's corner.  The block stages that tile of the
+// type-2 window, the nodes' tap values and first-tap offsets in LDS, then
+//   interp:  c_j = sum_{t1,t2} tile[oy+t2][ox+t1] psi_x[t1] psi_y[t2]
+//            (16 lanes per node, fixed reduction tree)        [eq. (16), (12)]
+//   a_j = q_j h^2 c_j                                          [eq. (12)]
+//   spread:  T[cb][ca] = sum_j a_j psi_x[ca-ox_j] psi_y[cb-oy_j] (one thread per
+//            tile cell, nodes in order, compensated in FP32)   [eq. (15)]
+// and writes its whole tile T to its own slot: no atomics.  The tiles are
+// summed onto the window by cols_type1 through a precomputed index list.
+// MODE 0: all three steps; MODE 1: interp only, out[j] = h^2 c_j (type-2 stage);
+// MODE 2: spread only, of coef (type-1 stage).
+constexpr int kNodeThreads = 256;
+constexpr int kLanesPerNode = 16;
+constexpr int kTileMax = kBinSize + kMaxKernelWidth - 1;
+
+template <typename R>
+struct NodeLds {
+    cpx<R> tile[kTileMax * kTileMax];
+    R psx[kMaxNodesPerSub][kMaxKernelWidth];
+    R psy[kMaxNodesPerSub][kMaxKernelWidth];
+    int ox[kMaxNodesPerSub];
+    int oy[kMaxNodesPerSub];
+    cpx<R> val[kMaxNodesPerSub];
+};
+
+template <typename R>
+__device__ __forceinline__ void kahan_add(R& s, R& c, R v) {
+    if constexpr (sizeof(R) == 4) {
+        const R y = v - c;
+        const R t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += v;
+    }
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(kNodeThreads) void k_nodes(DevPlan P, const cpx<R>* __restrict__ coef,
+                                                        cpx<R>* __restrict__ out) {
+    __shared__ NodeLds<R> s;
+    const int* sub = P.sub + 4 * blockIdx.x;
+    const int bx = sub[0], by = sub[1], first = sub[2], count = sub[3];
+    const int w = P.width, E = P.tile, q = P.patch, bin = P.bin;
+    const int x0 = bx * bin, y0 = by * bin;   // tile corner in window cells
+    const R* taps = static_cast<const R*>(P.taps);
+    // node data
+    for (int e = threadIdx.x; e < count * w; e += kNodeThreads) {
+        const int jj = e / w, t = e - jj * w;
+        const R* tn = taps + static_cast<size_t>(first + jj) * 2 * w;
+        s.psx[jj][t] = tn[t];
+        s.psy[jj][t] = tn[w + t];
+    }
+    for (int jj = threadIdx.x; jj < count; jj += kNodeThreads) {
+        s.ox[jj] = P.cell[2 * (first + jj)] - x0;
+        s.oy[jj] = P.cell[2 * (first + jj) + 1] - y0;
+        if constexpr (MODE == 2) s.val[jj] = coef[first + jj];
+    }
+    if constexpr (MODE != 2) {
+        // the type-2 window tile; the window side is a power of two and tiles only
+        // wrap when the window is the whole periodic fine grid
+        const bool whole = (q == P.n_fine);
+        const cpx<R>* win = static_cast<const cpx<R>*>(P.win);
+        for (int c = threadIdx.x; c < E * E; c += kNodeThreads) {
+            const int cb = c / E, ca = c - cb * E;
+            int wx = x0 + ca, wy = y0 + cb;
+            bool inside = true;
+            if (whole) {
+                wx &= q - 1;
+                wy &= q - 1;
+            } else {
+                inside = wx < q && wy < q;
+            }
+            s.tile[c] = inside ? win[static_cast<size_t>(wy) * q + wx] : cpx<R>{R(0), R(0)};
+        }
     }
     __syncthreads();
-    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
-    cpx<R>* win = static_cast<cpx<R>*>(P.win);
-    for (int i2 = tid; i2 < P.patch; i2 += NT)
-        win[static_cast<size_t>(i2) * P.patch + i1] = buf[lds_pad((P.patch_lo + i2) & (F - 1))];
-}
-
-// ---------------------------------------------------------------------------
-// cols_type1: sum the spread tiles onto one column of the fine-grid window,
-// FFT along y (only the Q window rows are non-zero), keep the N centred rows,
-// times d(n2)
-// ---------------------------------------------------------------------------
-
-// Range of bins b (0 <= b < nb) whose tile starts at b * bin and covers window
-// index i (i - b * bin in [0, E)).
-__device__ __forceinline__ void covering_bins(int i, int bin, int E, int nb, int* lo, int* hi) {
-    const int a = i - E + 1;
-    int b0 = (a >= 0) ? (a + bin - 1) / bin : -((-a) / bin);   // ceil(a / bin)
-    *lo = b0 > 0 ? b0 : 0;
-    const int b1 = i / bin;
-    *hi = b1 < nb - 1 ? b1 : nb - 1;
-}
-
-// b[i1][i2] = sum of the tile values of every subproblem whose tile covers
-// window cell (i1, i2), in the fixed order (x period, x bin, y period, y bin,
-// subproblem).  When the window is the whole periodic fine grid (Q = F) a
-// tile may wrap around it, possibly more than once.
-template <typename R>
-__device__ __forceinline__ cpx<R> gather_tiles(const DevPlan& P, int i1, int i2) {
-    const int q = P.patch, E = P.tile, bin = P.bin, nb = P.nb;
-    const int periods = (q == P.n_fine) ? (q + E - 2) / q + 1 : 1;
-    const cpx<R>* tiles = static_cast<const cpx<R>*>(P.tiles);
-    R sx = 0, sy = 0, cx = 0, cy = 0;
-    for (int t1 = 0; t1 < periods; ++t1) {
-        const int x = i1 + t1 * q;
-        int bx0, bx1;
-        covering_bins(x, bin, E, nb, &bx0, &bx1);
-        for (int bx = bx0; bx <= bx1; ++bx) {
-            const int ox = x - bx * bin;
-            for (int t2 = 0; t2 < periods; ++t2) {
-                const int y = i2 + t2 * q;
-                int by0, by1;
-                covering_bins(y, bin, E, nb, &by0, &by1);
-                for (int by = by0; by <= by1; ++by) {
-                    const int oy = y - by * bin;
-                    const int b = by * nb + bx;
-                    for (int sidx = P.bin_start[b]; sidx < P.bin_start[b + 1]; ++sidx) {
-                        const cpx<R> v = tiles[static_cast<size_t>(sidx) * E * E + oy * E + ox];
-                        if constexpr (sizeof(R) == 4) {
-                            const R yx = v.x - cx, tx = sx + yx;
-                            cx = (tx - sx) - yx;
-                            sx = tx;
-                            const R yy = v.y - cy, ty = sy + yy;
-                            cy = (ty - sy) - yy;
-                            sy = ty;
-                        } else {
-                            sx += v.x;
-                            sy += v.y;
-                        }
-                    }
+    if constexpr (MODE != 2) {
+        const int lane = threadIdx.x % kLanesPerNode;
+        for (int jj0 = 0; jj0 < count; jj0 += kNodeThreads / kLanesPerNode) {
+            const int jj = jj0 + threadIdx.x / kLanesPerNode;
+            cpx<R> acc = {R(0), R(0)};
+            if (jj < count) {
+                const int ox = s.ox[jj], oy = s.oy[jj];
+                for (int t = lane; t < w * w; t += kLanesPerNode) {
+                    const int t2 = t / w;
+                    const int t1 = t - t2 * w;
+                    const R k = s.psx[jj][t1] * s.psy[jj][t2];
+                    const cpx<R> b = s.tile[(oy + t2) * E + ox + t1];
+                    acc.x += b.x * k;
+                    acc.y += b.y * k;
+                }
+            }
+#pragma unroll
+            for (int off = kLanesPerNode / 2; off > 0; off >>= 1) {
+                acc.x += __shfl_xor(acc.x, off, kLanesPerNode);
+                acc.y += __shfl_xor(acc.y, off, kLanesPerNode);
+            }
+            if (jj < count && lane == 0) {
+                const int j = first + jj;
+                if constexpr (MODE == 1) {
+                    out[j] = {static_cast<R>(acc.x * P.h2), static_cast<R>(acc.y * P.h2)};
+                } else {
+                    const double scale = P.q[j] * P.h2;
+                    s.val[jj] = {static_cast<R>(acc.x * scale), static_cast<R>(acc.y * scale)};
                 }
             }
         }
     }
-    return {sx - cx, sy - cy};
+    if constexpr (MODE == 1) return;
+    if constexpr (MODE == 0) __syncthreads();
+    cpx<R>* tile_out = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(blockIdx.x) * E * E;
+    for (int c = threadIdx.x; c < E * E; c += kNodeThreads) {
+        const int cb = c / E, ca = c - cb * E;
+        R sx = 0, sy = 0, kx = 0, ky = 0;
+        for (int jj = 0; jj < count; ++jj) {
+            const int t1 = ca - s.ox[jj];
+            const int t2 = cb - s.oy[jj];
+            if (static_cast<unsigned>(t1) < static_cast<unsigned>(w) &&
+                static_cast<unsigned>(t2) < static_cast<unsigned>(w)) {
+                const R k = s.psx[jj][t1] * s.psy[jj][t2];
+                kahan_add(sx, kx, s.val[jj].x * k);
+                kahan_add(sy, ky, s.val[jj].y * k);
+            }
+        }
+        tile_out[c] = {sx - kx, sy - ky};
+    }
 }
 
-template <typename R, int LOG, int NT>
-__global__ __launch_bounds__(NT) void k_cols_type1(DevPlan P, R dir) {
-    constexpr int F = 1 << LOG;
+// ---------------------------------------------------------------------------
+// cols_type1: sum the spread tiles onto one window column, FFT along y (only
+// the Q window inputs are non-zero), keep the N centred rows, times d(n2)
+// ---------------------------------------------------------------------------
+// Window cell (i1, i2) is the sum of the tile entries listed for it, in list
+// order: L = min(4, NT) lanes split the list, then a fixed shuffle tree.
+template <typename R, int LOG>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type1(DevPlan P, R dir) {
+    using Sh = FftShape<LOG>;
+    constexpr int F = Sh::F;
     constexpr int N = F / 2;
-    __shared__ cpx<R> buf[lds_padded_size(F)];
-    __shared__ TwiddleLds<R, LOG> tw;
-    const int tid = threadIdx.x;
-    const int i1 = blockIdx.x;
-    twiddle_fill<R, LOG>(tw, P.tw_lo, P.tw_hi, tid, NT);
-    for (int p = tid; p < F; p += NT) buf[lds_pad(p)] = {R(0), R(0)};
+    constexpr int NT = Sh::NT;
+    constexpr int G = lines_per_block<LOG>();
+    constexpr int L = NT < 4 ? NT : 4;
+    __shared__ cpx<R> lds_all[G * lds_padded_size(F)];
+    const int g = threadIdx.x / NT;
+    const int tid = threadIdx.x - g * NT;
+    cpx<R>* lds = lds_all + g * lds_padded_size(F);
+    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
+    const int q = P.patch;
+    const int i1 = blockIdx.x * G + g;
+    const bool active = i1 < q;
+    // reduced window column, staged at the start of this group's FFT buffer
+    // (q <= F entries); the FFT's first barrier orders these reads before its writes
+    const cpx<R>* tiles = static_cast<const cpx<R>*>(P.tiles);
+    for (int i2 = tid / L; i2 < q; i2 += NT / L) {
+        const int cell = (active ? i1 : 0) * q + i2;
+        const int k0 = P.contrib_start[cell], k1 = P.contrib_start[cell + 1];
+        R sx = 0, sy = 0, kx = 0, ky = 0;
+        // batches of U entries per lane: all index loads, then all value loads,
+        // then the sums in list order
+        constexpr int U = 8;
+        for (int base = k0 + tid % L; base < k1; base += L * U) {
+            int idx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) idx[u] = (base + u * L < k1) ? P.contrib[base + u * L] : -1;
+            cpx<R> t[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) t[u] = (idx[u] >= 0) ? tiles[idx[u]] : cpx<R>{R(0), R(0)};
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                kahan_add(sx, kx, t[u].x);
+                kahan_add(sy, ky, t[u].y);
+            }
+        }
+        R vx = sx - kx, vy = sy - ky;
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) {
+            vx += __shfl_xor(vx, off, L);
+            vy += __shfl_xor(vy, off, L);
+        }
+        if (tid % L == 0) lds[i2] = {vx, vy};
+    }
     __syncthreads();
-    for (int i2 = tid; i2 < P.patch; i2 += NT)
-        buf[lds_pad((P.patch_lo + i2) & (F - 1))] = gather_tiles<R>(P, i1, i2);
-    __syncthreads();
-    fft_lds<R, LOG, NT>(buf, tw, tid, dir);
-    cpx<R>* u = static_cast<cpx<R>*>(P.u);
-    for (int n2 = tid; n2 < N; n2 += NT) {
-        const cpx<R> v = buf[lds_pad(centred_pos<LOG>(n2))];
-        const double d = P.deconv[n2];
-        u[static_cast<size_t>(n2) * P.patch + i1] = {static_cast<R>(v.x * d), static_cast<R>(v.y * d)};
+    cpx<R> v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int i2 = posmod_dev(tid + NT * i - P.patch_lo, F);
+        v[i] = (active && i2 < q) ? lds[i2] : cpx<R>{R(0), R(0)};
+    }
+    fft_reg<R, LOG>(v, lds, tw, tid, dir);
+    if (active) {
+        cpx<R>* u = static_cast<cpx<R>*>(P.u);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < 4 || i >= 12) {
+                const int n2 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
+                const double d = P.deconv[n2];
+                u[static_cast<size_t>(n2) * q + i1] = {static_cast<R>(v[i].x * d), static_cast<R>(v[i].y * d)};
+            }
+        }
     }
 }
 
@@ -401,161 +521,12 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
 }
 
 // ---------------------------------------------------------------------------
-// Kernel taps of the bin-sorted subproblems
-// ---------------------------------------------------------------------------
-namespace {
-
-constexpr int kSubThreads = 256;
-constexpr int kTileMax = kBinSize + kMaxKernelWidth - 1;
-
-template <typename R>
-struct SubLds {
-    cpx<R> tile[kTileMax * kTileMax];
-    R psx[kMaxNodesPerSub][kMaxKernelWidth];
-    R psy[kMaxNodesPerSub][kMaxKernelWidth];
-    int offx[kMaxNodesPerSub];
-    int offy[kMaxNodesPerSub];
-    cpx<R> val[kMaxNodesPerSub];
-};
-
-__device__ __forceinline__ double es_kernel_dev(double z, double beta) {
-    return (fabs(z) < 1.0) ? exp(beta * (sqrt(1.0 - z * z) - 1.0)) : 0.0;
-}
-
-// Kernel values psi(u_j - l) for the w taps l = l0 .. l0+w-1 of every node of
-// the subproblem (separable in x and y), and each node's first-tap offset in
-// the tile.  FP64 evaluation, stored in the data precision.
-template <typename R>
-__device__ void subproblem_taps(const DevPlan& P, SubLds<R>& s, int tile_lo1, int tile_lo2, int first,
-                                int count) {
-    const int w = P.width;
-    const double half = 0.5 * w;
-    const int F = P.n_fine;
-    for (int e = threadIdx.x; e < count * w * 2; e += kSubThreads) {
-        const int axis = e / (count * w);
-        const int r = e - axis * count * w;
-        const int jj = r / w;
-        const int t = r - jj * w;
-        const int j = first + jj;
-        const double u = axis ? P.uy[j] : P.ux[j];
-        const int l0 = static_cast<int>(ceil(u - half));
-        const R v = static_cast<R>(es_kernel_dev((u - (l0 + t)) / half, P.beta));
-        if (axis == 0) {
-            s.psx[jj][t] = v;
-            if (t == 0) s.offx[jj] = P.patch_lo + posmod_dev(l0 - P.patch_lo, F) - tile_lo1;
-        } else {
-            s.psy[jj][t] = v;
-            if (t == 0) s.offy[jj] = P.patch_lo + posmod_dev(l0 - P.patch_lo, F) - tile_lo2;
-        }
-    }
-}
-
-}  // namespace
-
-// rho_hat_j = h^2 sum_taps b[l] psi(u_jx - l1) psi(u_jy - l2); a_j = q_j rho_hat_j
-// (mode 0: q_j h^2 from the plan; mode 1: h^2 only, for the type-2 entry point).
-template <typename R>
-__global__ __launch_bounds__(kSubThreads) void k_interp(DevPlan P, cpx<R>* __restrict__ out, int mode) {
-    __shared__ SubLds<R> s;
-    const int* sub = P.sub + 4 * blockIdx.x;
-    const int lo1 = sub[0], lo2 = sub[1], first = sub[2], count = sub[3];
-    const int w = P.width;
-    const int E = P.bin + w - 1;
-    const int F = P.n_fine;
-    const int q = P.patch;
-    const cpx<R>* win = static_cast<const cpx<R>*>(P.win);
-    for (int c = threadIdx.x; c < E * E; c += kSubThreads) {
-        const int ca = c % E, cb = c / E;
-        const int wi1 = posmod_dev(lo1 + ca - P.patch_lo, F);
-        const int wi2 = posmod_dev(lo2 + cb - P.patch_lo, F);
-        s.tile[c] = (wi1 < q && wi2 < q) ? win[static_cast<size_t>(wi2) * q + wi1] : cpx<R>{R(0), R(0)};
-    }
-    subproblem_taps<R>(P, s, lo1, lo2, first, count);
-    __syncthreads();
-    // 16 lanes per node, tree reduction over the lanes of the group
-    const int lane = threadIdx.x & 15;
-    const int group = threadIdx.x >> 4;
-    const int ntap = w * w;
-    for (int jj0 = 0; jj0 < count; jj0 += kSubThreads / 16) {
-        const int jj = jj0 + group;
-        cpx<R> acc = {R(0), R(0)};
-        if (jj < count) {
-            const int ox = s.offx[jj], oy = s.offy[jj];
-            for (int t = lane; t < ntap; t += 16) {
-                const int ay = t / w;
-                const int ax = t - ay * w;
-                const R k = s.psx[jj][ax] * s.psy[jj][ay];
-                const cpx<R> b = s.tile[(oy + ay) * E + ox + ax];
-                acc.x += b.x * k;
-                acc.y += b.y * k;
-            }
-        }
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            acc.x += __shfl_xor(acc.x, off, 16);
-            acc.y += __shfl_xor(acc.y, off, 16);
-        }
-        if (jj < count && lane == 0) {
-            const int j = first + jj;
-            const double scale = (mode == 0) ? P.q[j] * P.h2 : P.h2;
-            out[j] = {static_cast<R>(acc.x * scale), static_cast<R>(acc.y * scale)};
-        }
-    }
-}
-
-// Tile of subproblem s: T_s[l] = sum_j a_j psi(l1 - u_jx) psi(l2 - u_jy) over the
-// subproblem's nodes, for the E x E cells l of its bin's tile.  Each thread owns
-// tile cells and sums the taps that land on them in node order (compensated
-// summation in FP32), then writes the whole tile, zeros included, to the
-// subproblem's own slot: no atomics, so the result is bitwise reproducible.
-// The tiles are summed onto the fine-grid window by cols_type1.
-template <typename R>
-__global__ __launch_bounds__(kSubThreads) void k_spread(DevPlan P, const cpx<R>* __restrict__ coef) {
-    __shared__ SubLds<R> s;
-    const int* sub = P.sub + 4 * blockIdx.x;
-    const int lo1 = sub[0], lo2 = sub[1], first = sub[2], count = sub[3];
-    const int w = P.width;
-    const int E = P.tile;
-    subproblem_taps<R>(P, s, lo1, lo2, first, count);
-    for (int jj = threadIdx.x; jj < count; jj += kSubThreads) s.val[jj] = coef[first + jj];
-    __syncthreads();
-    cpx<R>* tile = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(blockIdx.x) * E * E;
-    for (int c = threadIdx.x; c < E * E; c += kSubThreads) {
-        const int ca = c % E, cb = c / E;
-        R sx = 0, sy = 0, cx = 0, cy = 0;   // sums and compensations
-        for (int jj = 0; jj < count; ++jj) {
-            const int ax = ca - s.offx[jj];
-            const int ay = cb - s.offy[jj];
-            if (static_cast<unsigned>(ax) < static_cast<unsigned>(w) &&
-                static_cast<unsigned>(ay) < static_cast<unsigned>(w)) {
-                const R k = s.psx[jj][ax] * s.psy[jj][ay];
-                const R vx = s.val[jj].x * k;
-                const R vy = s.val[jj].y * k;
-                if constexpr (sizeof(R) == 4) {
-                    const R yx = vx - cx, tx = sx + yx;
-                    cx = (tx - sx) - yx;
-                    sx = tx;
-                    const R yy = vy - cy, ty = sy + yy;
-                    cy = (ty - sy) - yy;
-                    sy = ty;
-                } else {
-                    sx += vx;
-                    sy += vy;
-                }
-            }
-        }
-        tile[c] = {sx - cx, sy - cy};
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 namespace {
 
 template <typename R, int LOG>
 hipError_t launch_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
-    if (P.twr_count != FftShape<LOG>::tw_size()) return hipErrorInvalidValue;
     constexpr int G = rows_per_block<R, LOG>();
     hipLaunchKernelGGL((k_rows_forward<R, LOG>), dim3(P.n / G), dim3(FftShape<LOG>::NT * G), 0, s, P,
                        static_cast<const R*>(rho), dir);
@@ -564,7 +535,6 @@ hipError_t launch_rows_forward(const DevPlan& P, const void* rho, R dir, hipStre
 
 template <typename R, int LOG>
 hipError_t launch_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
-    if (P.twr_count != FftShape<LOG>::tw_size()) return hipErrorInvalidValue;
     constexpr int G = lines_per_block<LOG>();
     const int blocks = (P.n + 1 + G - 1) / G;
     hipLaunchKernelGGL((k_cols_highfreq<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
@@ -573,29 +543,35 @@ hipError_t launch_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
 
 template <typename R, int LOG>
 hipError_t launch_cols_type2(const DevPlan& P, R dir, hipStream_t s) {
-    constexpr int NT = threads_for<LOG>();
-    hipLaunchKernelGGL((k_cols_type2<R, LOG, NT>), dim3(P.patch), dim3(NT), 0, s, P, dir);
+    constexpr int G = lines_per_block<LOG>();
+    const int blocks = (P.patch + G - 1) / G;
+    hipLaunchKernelGGL((k_cols_type2<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
 hipError_t launch_cols_type1(const DevPlan& P, R dir, hipStream_t s) {
-    constexpr int NT = threads_for<LOG>();
-    hipLaunchKernelGGL((k_cols_type1<R, LOG, NT>), dim3(P.patch), dim3(NT), 0, s, P, dir);
+    constexpr int G = lines_per_block<LOG>();
+    const int blocks = (P.patch + G - 1) / G;
+    hipLaunchKernelGGL((k_cols_type1<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
 hipError_t launch_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int use_i2, hipStream_t s) {
-    if (P.twr_count != FftShape<LOG>::tw_size()) return hipErrorInvalidValue;
     constexpr int G = rows_per_block<R, LOG>();
     hipLaunchKernelGGL((k_rows_inverse<R, LOG>), dim3(P.n / G), dim3(FftShape<LOG>::NT * G), 0, s, P,
                        static_cast<R*>(out), dir, use_i1, use_i2);
     return hipGetLastError();
 }
 
-#define PHI_DISPATCH_LOG(LOGV, CALL)        \
-    switch (LOGV) {                         \
+template <int LOG>
+bool twiddles_match(const DevPlan& P) {
+    return P.twr_count == FftShape<LOG>::tw_size();
+}
+
+#define PHI_DISPATCH_LOG(LOGV, CALL)                     \
+    switch (LOGV) {                                      \
         case 4: { constexpr int L_ = 4; return CALL; }   \
         case 5: { constexpr int L_ = 5; return CALL; }   \
         case 6: { constexpr int L_ = 6; return CALL; }   \
@@ -606,9 +582,12 @@ hipError_t launch_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, i
         case 11: { constexpr int L_ = 11; return CALL; } \
         case 12: { constexpr int L_ = 12; return CALL; } \
         case 13: { constexpr int L_ = 13; return CALL; } \
-        default: return hipErrorInvalidValue;           \
+        default: return hipErrorInvalidValue;            \
     }
 
+hipError_t check_twiddles(const DevPlan& P) {
+    PHI_DISPATCH_LOG(P.log_fine, (twiddles_match<L_>(P) ? hipSuccess : hipErrorInvalidValue));
+}
 template <typename R>
 hipError_t run_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_rows_forward<R, L_>(P, rho, dir, s)));
@@ -630,16 +609,10 @@ hipError_t run_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int 
     PHI_DISPATCH_LOG(P.log_fine, (launch_rows_inverse<R, L_>(P, out, dir, use_i1, use_i2, s)));
 }
 
-template <typename R>
-hipError_t run_interp(const DevPlan& P, void* out, int mode, hipStream_t s) {
-    hipLaunchKernelGGL((k_interp<R>), dim3(P.n_sub), dim3(kSubThreads), 0, s, P, static_cast<cpx<R>*>(out), mode);
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t run_spread(const DevPlan& P, const void* coef, hipStream_t s) {
-    hipLaunchKernelGGL((k_spread<R>), dim3(P.n_sub), dim3(kSubThreads), 0, s, P,
-                       static_cast<const cpx<R>*>(coef));
+template <typename R, int MODE>
+hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_nodes<R, MODE>), dim3(P.n_sub), dim3(kNodeThreads), 0, s, P,
+                       static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
     return hipGetLastError();
 }
 
@@ -649,71 +622,80 @@ hipError_t run_spread(const DevPlan& P, const void* coef, hipStream_t s) {
         if (e_ != hipSuccess) return e_; \
     } while (0)
 
-// Records an event on s before kernel `name` when a timer is attached.
-hipError_t mark(KernelTimer* t, const char* name, hipStream_t s) {
+// Records the start (end = false) or end (end = true) of kernel `name` on stream s.
+hipError_t mark(KernelTimer* t, const char* name, bool end, hipStream_t s) {
     if (!t) return hipSuccess;
     if (t->count >= KernelTimer::kMax) return hipErrorInvalidValue;
-    t->names[t->count] = name;
-    return hipEventRecord(t->ev[t->count++], s);
+    if (!end) {
+        t->names[t->count] = name;
+        return hipEventRecord(t->ev[2 * t->count], s);
+    }
+    return hipEventRecord(t->ev[2 * t->count++ + 1], s);
 }
 
-#define PHI_STEP(name, expr)                   \
-    do {                                       \
-        PHI_TRY(mark(timer, name, s));         \
-        PHI_TRY(expr);                         \
+#define PHI_STEP(name, stream, expr)                   \
+    do {                                               \
+        PHI_TRY(mark(timer, name, false, stream));     \
+        PHI_TRY(expr);                                 \
+        PHI_TRY(mark(timer, name, true, stream));      \
     } while (0)
 
 template <typename R>
-hipError_t enqueue_typed(const DevPlan& P, Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
-                         KernelTimer* timer) {
+hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
+                         hipStream_t s, KernelTimer* timer) {
+    PHI_TRY(check_twiddles(P));
     // forward solve: type-2 side and the first I1 transforms with e^{-...};
     // the transposed solve reverses every direction
     const R dir = adjoint ? R(1) : R(-1);
     switch (stage) {
-        case Stage::Solve:
-            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
-            PHI_STEP("cols_highfreq", (run_cols_highfreq<R>(P, dir, s)));
-            PHI_STEP("cols_type2", (run_cols_type2<R>(P, dir, s)));
-            PHI_STEP("interp", (run_interp<R>(P, P.pts, 0, s)));
-            PHI_STEP("spread", (run_spread<R>(P, P.pts, s)));
-            PHI_STEP("cols_type1", (run_cols_type1<R>(P, -dir, s)));
-            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
-            break;
+        case Stage::Solve: {
+            PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
+            hipStream_t side = ss.side ? ss.side : s;
+            if (ss.side) {
+                PHI_TRY(hipEventRecord(ss.fork, s));
+                PHI_TRY(hipStreamWaitEvent(side, ss.fork, 0));
+            }
+            PHI_STEP("cols_type2", side, (run_cols_type2<R>(P, dir, side)));
+            PHI_STEP("nodes", side, (run_nodes<R, 0>(P, nullptr, nullptr, side)));
+            PHI_STEP("cols_type1", side, (run_cols_type1<R>(P, -dir, side)));
+            if (ss.side) PHI_TRY(hipEventRecord(ss.join, side));
+            PHI_STEP("cols_highfreq", s, (run_cols_highfreq<R>(P, dir, s)));
+            if (ss.side) PHI_TRY(hipStreamWaitEvent(s, ss.join, 0));
+            PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
+            return hipSuccess;
+        }
         case Stage::HighFreq:
-            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
-            PHI_STEP("cols_highfreq", (run_cols_highfreq<R>(P, dir, s)));
-            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, -dir, 1, 0, s)));
-            break;
+            PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_highfreq", s, (run_cols_highfreq<R>(P, dir, s)));
+            PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 0, s)));
+            return hipSuccess;
         case Stage::LowFreq:
-            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
-            PHI_STEP("cols_type2", (run_cols_type2<R>(P, dir, s)));
-            PHI_STEP("interp", (run_interp<R>(P, P.pts, 0, s)));
-            PHI_STEP("spread", (run_spread<R>(P, P.pts, s)));
-            PHI_STEP("cols_type1", (run_cols_type1<R>(P, -dir, s)));
-            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, -dir, 0, 1, s)));
-            break;
+            PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_type2", s, (run_cols_type2<R>(P, dir, s)));
+            PHI_STEP("nodes", s, (run_nodes<R, 0>(P, nullptr, nullptr, s)));
+            PHI_STEP("cols_type1", s, (run_cols_type1<R>(P, -dir, s)));
+            PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 0, 1, s)));
+            return hipSuccess;
         case Stage::Type2:
-            PHI_STEP("rows_forward", (run_rows_forward<R>(P, in, dir, s)));
-            PHI_STEP("cols_type2", (run_cols_type2<R>(P, dir, s)));
-            PHI_STEP("interp", (run_interp<R>(P, out, 1, s)));
-            break;
+            PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
+            PHI_STEP("cols_type2", s, (run_cols_type2<R>(P, dir, s)));
+            PHI_STEP("nodes", s, (run_nodes<R, 1>(P, nullptr, out, s)));
+            return hipSuccess;
         case Stage::Type1:
-            PHI_STEP("spread", (run_spread<R>(P, in, s)));
-            PHI_STEP("cols_type1", (run_cols_type1<R>(P, R(1), s)));
-            PHI_STEP("rows_inverse", (run_rows_inverse<R>(P, out, R(1), 0, 1, s)));
-            break;
-        default:
-            return hipErrorInvalidValue;
+            PHI_STEP("nodes", s, (run_nodes<R, 2>(P, in, nullptr, s)));
+            PHI_STEP("cols_type1", s, (run_cols_type1<R>(P, R(1), s)));
+            PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, R(1), 0, 1, s)));
+            return hipSuccess;
     }
-    return mark(timer, nullptr, s);   // end of the last kernel
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t enqueue(const DevPlan& P, Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
-                   KernelTimer* timer) {
-    if (P.dtype == PHI_F32) return enqueue_typed<float>(P, stage, in, out, adjoint, s, timer);
-    return enqueue_typed<double>(P, stage, in, out, adjoint, s, timer);
+hipError_t enqueue(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
+                   hipStream_t s, KernelTimer* timer) {
+    if (P.dtype == PHI_F32) return enqueue_typed<float>(P, ss, stage, in, out, adjoint, s, timer);
+    return enqueue_typed<double>(P, ss, stage, in, out, adjoint, s, timer);
 }
 
 }  // namespace phi

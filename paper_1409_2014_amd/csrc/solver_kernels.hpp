@@ -13,47 +13,52 @@ namespace phi {
 struct DevPlan {
     phi_dtype dtype;
     int n, n_fine, log_fine;
-    int patch, patch_lo, width, bin, n_nodes, n_sub, component_y;
-    double beta, h2, inv_f2;
+    int patch, patch_lo, width, n_nodes, component_y;
+    double h2, inv_f2;
     // FP64 tables
-    const double* deconv;   // [N]
-    const double* gx;       // [2 (N+1)]
-    const double* gy;       // [2 F]
-    const double* tw_lo;    // [2 S]
-    const double* tw_hi;    // [2 F/S]
+    const double* deconv;   // [N] 2 pi / (n_fine psi_hat(n'))
+    const double* gx;       // [2 (N+1)] I1 multiplier factors along x
+    const double* gy;       // [2 F] I1 multiplier factors along y
+    const double* q;        // [M] I2 weights q_j (without h^2)
+    // node tables
+    const int* cell;        // [2 M] first-tap window cell (x, y)
+    const void* taps;       // [M][2][w] kernel tap values, data precision
+    const int* sub;         // [4 n_sub] bin x, bin y, first node, node count
+    const int* contrib_start;  // [Q^2 + 1] tile entries summed into window cell x*Q + y
+    const int* contrib;        // flat tile indices
+    int n_sub, bin, tile;      // subproblems, bin side, tile side E = bin + w - 1
     const void* twr;        // register-FFT stage twiddles, data precision, twr_count complex
     int twr_count;
-    const double* ux;       // [M]
-    const double* uy;       // [M]
-    const double* q;        // [M] (without h^2)
-    const int* sub;         // [4 n_sub]
-    const int* bin_start;   // [nb*nb + 1] subproblem range of each bin
-    int nb;                 // bins per window side (window side = nb * bin)
-    int tile;               // tile side E = bin + width - 1
     // workspace, element type = data precision
     void* xt;       // (N+1) x N complex: I1 half spectrum, column-major
     void* tt;       // Q x N complex: type-2 row window, column-major
-    void* win;      // Q x Q complex: type-2 fine-grid window
+    void* win;      // Q x Q complex: type-2 fine-grid window, [y][x]
     void* pts;      // M complex: a_j = q_j rho_hat_j
     void* tiles;    // n_sub x E x E complex: each subproblem's spread tile
-    void* u;        // N x Q complex: type-1 column transforms
+    void* u;        // N x Q complex: type-1 column transforms, [n2][x]
+};
+
+// Streams and events a plan uses to run the node-side chain concurrently with
+// the I1 column pass (all default priority).
+struct StreamSet {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 enum class Stage { Solve, HighFreq, LowFreq, Type2, Type1 };
 
-// Optional per-kernel timing: an event is recorded on the launch stream before
-// each kernel of the chain and one after the last.  The events are created by
-// the owner; names[i] names the kernel that starts at ev[i].
+// Optional per-kernel timing: events recorded on the kernel's launch stream
+// just before and just after each kernel.  The events are created by the owner.
 struct KernelTimer {
     static constexpr int kMax = 16;
-    hipEvent_t ev[kMax];
+    hipEvent_t ev[2 * kMax];
     const char* names[kMax];
     int count = 0;
 };
 
 // Enqueue a stage chain on stream s (no host synchronisation).  adjoint = 1
 // reverses every transform direction (the transposed operator).
-hipError_t enqueue(const DevPlan& P, Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
-                   KernelTimer* timer = nullptr);
+hipError_t enqueue(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
+                   hipStream_t s, KernelTimer* timer = nullptr);
 
 }  // namespace phi
