@@ -105,6 +105,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (and the error figures that need it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is not sharded "
@@ -148,6 +150,13 @@ def main() -> int:
     def pair64():
         plan64.solve(rho64_dev, out64)
         plan64.solve_adjoint(out64, back64)
+
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for fn in (fwd32, fwd64, pair32, pair64):

@@ -22,29 +22,38 @@
 // t = 1..R-1, k = 0..p-1 at index (t-1) p + k, and the stages are stored back
 // to back in order.  Forward tables; the inverse takes conjugates.
 //
-// dir = -1: X(k) = sum_j x(j) e^{-2 pi i k j / F} (forward DFT, Sec. 2.2,
-// eq. (13)); dir = +1: the same sum with e^{+...} (eq. (14) times F).
+// DIR = -1: X(k) = sum_j x(j) e^{-2 pi i k j / F} (forward DFT, Sec. 2.2,
+// eq. (13)); DIR = +1: the same sum with e^{+...} (eq. (14) times F).  The
+// direction is a template parameter so that every sign folds into the code.
 #pragma once
 
 #include "device_common.hpp"
 
 namespace phi {
 
-// cos / sin of 2 pi a / 16, a = 0..7 (the 16th roots of unity, correctly rounded).
-template <typename R>
-__device__ __forceinline__ cpx<R> root16(int a, R dir) {
+// The 16th roots of unity e^{DIR 2 pi i a / 16}, a = 0..7 (correctly rounded
+// constants; DIR = -1 forward, +1 inverse, fixed at compile time).
+template <typename R, int DIR>
+__device__ __forceinline__ cpx<R> root16(int a) {
     constexpr double C[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
     constexpr double S[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
                              1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
-    return {static_cast<R>(C[a]), dir * static_cast<R>(S[a])};
+    return {static_cast<R>(C[a]), static_cast<R>(DIR * S[a])};
+}
+
+// x times DIR i
+template <typename R, int DIR>
+__device__ __forceinline__ cpx<R> mul_i(cpx<R> a) {
+    if constexpr (DIR > 0) return {-a.y, a.x};
+    else return {a.y, -a.x};
 }
 
 // In-register DFT of length RAD (1, 2, 4, 8, 16) by even/odd splitting:
-// v[k] <- sum_j v[j] e^{dir 2 pi i j k / RAD}.
-template <int RAD, typename R>
+// v[k] <- sum_j v[j] e^{DIR 2 pi i j k / RAD}.
+template <int RAD, typename R, int DIR>
 struct RegDft {
-    __device__ __forceinline__ static void run(cpx<R>* v, R dir) {
+    __device__ __forceinline__ static void run(cpx<R>* v) {
         constexpr int H = RAD / 2;
         cpx<R> e[H], o[H];
 #pragma unroll
@@ -52,17 +61,17 @@ struct RegDft {
             e[t] = v[2 * t];
             o[t] = v[2 * t + 1];
         }
-        RegDft<H, R>::run(e, dir);
-        RegDft<H, R>::run(o, dir);
+        RegDft<H, R, DIR>::run(e);
+        RegDft<H, R, DIR>::run(o);
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             cpx<R> t;
             if (k == 0) {
                 t = o[k];
             } else if (4 * k == RAD) {
-                t = cmul_si(o[k], dir);
+                t = mul_i<R, DIR>(o[k]);
             } else {
-                t = cmul(o[k], root16<R>(k * (16 / RAD), dir));
+                t = cmul(o[k], root16<R, DIR>(k * (16 / RAD)));
             }
             v[k] = cadd(e[k], t);
             v[k + H] = csub(e[k], t);
@@ -70,9 +79,9 @@ struct RegDft {
     }
 };
 
-template <typename R>
-struct RegDft<1, R> {
-    __device__ __forceinline__ static void run(cpx<R>*, R) {}
+template <typename R, int DIR>
+struct RegDft<1, R, DIR> {
+    __device__ __forceinline__ static void run(cpx<R>*) {}
 };
 
 template <int LOG>
@@ -98,18 +107,38 @@ struct FftShape {
     static constexpr int tw_size() { return tw_offset(NSTAGE); }
 };
 
-template <typename R>
-__device__ __forceinline__ cpx<R> tw_load(const cpx<R>* __restrict__ tw, int idx, R dir) {
-    cpx<R> w = tw[idx];
-    w.y = -dir * w.y;   // table holds e^{-i theta}
-    return w;
+// x times the twiddle w (DIR = -1) or its conjugate (DIR = +1); the table holds e^{-i theta}.
+template <typename R, int DIR>
+__device__ __forceinline__ cpx<R> tw_mul(cpx<R> x, cpx<R> w) {
+    if constexpr (DIR < 0) return {x.x * w.x - x.y * w.y, x.x * w.y + x.y * w.x};
+    else return {x.x * w.x + x.y * w.y, x.y * w.x - x.x * w.y};
+}
+
+// Twiddles of stage S (S >= 1) for this thread: w[c (RAD-1) + t - 1] multiplies
+// input t of butterfly c.  At most 15 per stage.
+template <typename R, int LOG, int S>
+__device__ __forceinline__ void stage_twiddles(cpx<R> (&w)[16], const cpx<R>* __restrict__ tw, int tid) {
+    using Sh = FftShape<LOG>;
+    if constexpr (S > 0 && S < Sh::NSTAGE) {
+        constexpr int RAD = Sh::radix(S);
+        constexpr int P = Sh::span(S);
+        constexpr int C = 16 / RAD;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int k = (tid + Sh::NT * c) & (P - 1);
+#pragma unroll
+            for (int t = 1; t < RAD; ++t) w[c * (RAD - 1) + t - 1] = tw[Sh::tw_offset(S) + (t - 1) * P + k];
+        }
+    }
 }
 
 // Stage S of the transform.  v holds the thread's 16 points in the register
-// layout; stages after the first read their inputs from LDS.
-template <typename R, int LOG, int S>
-__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw,
-                                          int tid, R dir) {
+// layout; stages after the first read their inputs from LDS.  w holds this
+// stage's twiddles on entry and the next stage's on exit: they are fetched
+// before the exchange so that their latency overlaps the barrier and LDS traffic.
+template <typename R, int LOG, int S, int DIR>
+__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R> (&w)[16], cpx<R>* lds,
+                                          const cpx<R>* __restrict__ tw, int tid) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int NT = Sh::NT;
@@ -124,42 +153,47 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, const cp
         for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
         if constexpr (!LAST) __syncthreads();   // all reads done before this stage overwrites
     }
+    cpx<R> x[C][RAD];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int b = tid + NT * c;
-        const int k = b & (P - 1);
-        cpx<R> x[RAD];
 #pragma unroll
         for (int t = 0; t < RAD; ++t) {
-            x[t] = v[c + C * t];
+            x[c][t] = v[c + C * t];
             if constexpr (S > 0) {
-                if (t > 0) x[t] = cmul(x[t], tw_load<R>(tw, Sh::tw_offset(S) + (t - 1) * P + k, dir));
+                if (t > 0) x[c][t] = tw_mul<R, DIR>(x[c][t], w[c * (RAD - 1) + t - 1]);
             }
         }
-        RegDft<RAD, R>::run(x, dir);
-        if constexpr (S == 0 && !LAST) {
-            // the buffer may still be read by the group's previous use
-            if (c == 0) __syncthreads();
-        }
-        if constexpr (LAST) {
-            // output position b + t NB: the same register slot
+    }
+    if constexpr (!LAST) stage_twiddles<R, LOG, S + 1>(w, tw, tid);
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) v[c + C * t] = x[t];
-        } else {
+    for (int c = 0; c < C; ++c) RegDft<RAD, R, DIR>::run(x[c]);
+    if constexpr (LAST) {
+        // output position b + t NB: the same register slot
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) v[c + C * t] = x[c][t];
+    } else {
+        // the buffer may still be read by the group's previous use (stage 0)
+        if constexpr (S == 0) __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int b = tid + NT * c;
+            const int k = b & (P - 1);
             const int base = (b - k) * RAD + k;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) lds[lds_pad(base + t * P)] = x[t];
+            for (int t = 0; t < RAD; ++t) lds[lds_pad(base + t * P)] = x[c][t];
         }
+        __syncthreads();
     }
-    if constexpr (!LAST) __syncthreads();
 }
 
-template <typename R, int LOG, int S>
-__device__ __forceinline__ void fft_stages_from(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw,
-                                                int tid, R dir) {
+template <typename R, int LOG, int S, int DIR>
+__device__ __forceinline__ void fft_stages_from(cpx<R> (&v)[16], cpx<R> (&w)[16], cpx<R>* lds,
+                                                const cpx<R>* __restrict__ tw, int tid) {
     if constexpr (S < FftShape<LOG>::NSTAGE) {
-        fft_stage<R, LOG, S>(v, lds, tw, tid, dir);
-        fft_stages_from<R, LOG, S + 1>(v, lds, tw, tid, dir);
+        fft_stage<R, LOG, S, DIR>(v, w, lds, tw, tid);
+        fft_stages_from<R, LOG, S + 1, DIR>(v, w, lds, tw, tid);
     }
 }
 
@@ -169,10 +203,10 @@ __device__ __forceinline__ void fft_stages_from(cpx<R> (&v)[16], cpx<R>* lds, co
 // write, so it may follow any earlier reads of the buffer (including another
 // transform) directly; it ends without one, so a caller that writes the buffer
 // afterwards must synchronise first.
-template <typename R, int LOG>
-__device__ __forceinline__ void fft_reg(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw, int tid,
-                                        R dir) {
-    fft_stages_from<R, LOG, 0>(v, lds, tw, tid, dir);
+template <typename R, int LOG, int DIR>
+__device__ __forceinline__ void fft_reg(cpx<R> (&v)[16], cpx<R>* lds, const cpx<R>* __restrict__ tw, int tid) {
+    cpx<R> w[16];
+    fft_stages_from<R, LOG, 0, DIR>(v, w, lds, tw, tid);
 }
 
 }  // namespace phi

@@ -163,6 +163,7 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         Part p_deconv = take(n * 8);
         Part p_gx = take(2 * (n + 1) * 8);
         Part p_gy = take(2 * f * 8);
+        Part p_gyr = take(2 * f * es);
         Part p_q = take(m * 8);
         Part p_cell = take(hp.cell.size() * 4);
         Part p_sub = take(hp.sub.size() * 4);
@@ -190,8 +191,9 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
             return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
         };
         // kernel taps and FFT twiddles are rounded once from FP64 to the data precision
-        std::vector<float> taps32, twr32;
+        std::vector<float> taps32, twr32, gy32;
         if (p->dtype == PHI_F32) {
+            gy32.assign(hp.gy.begin(), hp.gy.end());
             taps32.assign(hp.taps.begin(), hp.taps.end());
             twr32.assign(hp.twr.begin(), hp.twr.end());
         }
@@ -200,6 +202,8 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         if (ce == hipSuccess) ce = up(p_deconv, hp.deconv.data());
         if (ce == hipSuccess) ce = up(p_gx, hp.gx.data());
         if (ce == hipSuccess) ce = up(p_gy, hp.gy.data());
+        if (ce == hipSuccess) ce = up(p_gyr, f32 ? static_cast<const void*>(gy32.data())
+                                                 : static_cast<const void*>(hp.gy.data()));
         if (ce == hipSuccess) ce = up(p_q, hp.q.data());
         if (ce == hipSuccess) ce = up(p_cell, hp.cell.data());
         if (ce == hipSuccess) ce = up(p_sub, hp.sub.data());
@@ -232,11 +236,16 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
         d.width = hp.width;
         d.n_nodes = hp.n_nodes;
         d.component_y = hp.component_y;
+        d.n_cu = 0;
+        if (hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, plan->device) != hipSuccess ||
+            d.n_cu < 1)
+            d.n_cu = 1;
         d.h2 = hp.h * hp.h;
         d.inv_f2 = 1.0 / (static_cast<double>(f) * static_cast<double>(f));
         d.deconv = reinterpret_cast<const double*>(base + p_deconv.off);
         d.gx = reinterpret_cast<const double*>(base + p_gx.off);
         d.gy = reinterpret_cast<const double*>(base + p_gy.off);
+        d.gyr = base + p_gyr.off;
         d.q = reinterpret_cast<const double*>(base + p_q.off);
         d.cell = reinterpret_cast<const int*>(base + p_cell.off);
         d.sub = reinterpret_cast<const int*>(base + p_sub.off);

@@ -49,68 +49,92 @@ __device__ __forceinline__ int posmod_dev(int a, int b) {
 // rows_forward
 // ---------------------------------------------------------------------------
 
+// Distance between the LDS buffers of the sequences of one block: the padded
+// length plus 8 entries, so that lanes working on the same position of
+// different sequences fall into different banks.
+__host__ __device__ constexpr int lds_group_stride(int f) { return lds_padded_size(f) + 8; }
+
 // Grid rows per block of the row kernels: as many as fit 1024 threads and about
-// 136 KB of LDS (one FFT buffer per row), so the column-major spectrum is
-// written and read in segments of G consecutive rows.
+// 70 KB of LDS (one FFT buffer per row, two blocks per CU), so the column-major
+// spectrum is written and read in segments of G consecutive rows (two rows in
+// FP32, one in FP64 at the long transforms: measured best among 1, 2 and 4).
 template <typename R, int LOG>
 constexpr int rows_per_block() {
     constexpr int nt = FftShape<LOG>::NT;
     constexpr int by_threads = 1024 / nt;
-    constexpr int by_lds = static_cast<int>((136 * 1024) / (lds_padded_size(1 << LOG) * sizeof(cpx<R>)));
-    constexpr int g = by_threads < by_lds ? by_threads : by_lds;
+    constexpr int by_lds = static_cast<int>((70 * 1024) / (lds_group_stride(1 << LOG) * sizeof(cpx<R>)));
     constexpr int n = (1 << LOG) / 2;
-    return g < 1 ? 1 : (g > n ? n : g);
+    int lim = by_threads < by_lds ? by_threads : by_lds;
+    lim = lim < n ? lim : n;
+    int g = 1;                      // largest power of two <= lim: divides N
+    while (2 * g <= lim) g *= 2;
+    return g;
 }
 
-// Row `row` of the grid, at centred positions n' mod F: z = rho + i rho d(n1) d(n2)
-// (the type-2 deconvolution rides in the imaginary part), one F-point FFT; the
-// transform of the real part on m = 0..N is the I1 half spectrum, that of the
-// imaginary part on the Q window frequencies is the type-2 row window.
-template <typename R, int LOG>
+// Grid column of register slot i of thread tid (centred positions: slots 0..3
+// hold n' >= 0, slots 12..15 hold n' < 0, the other slots are zero padding).
+template <int LOG>
+__device__ __forceinline__ int slot_col(int tid, int i) {
+    constexpr int NT = FftShape<LOG>::NT;
+    constexpr int N = (1 << LOG) / 2;
+    return (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
+}
+
+// Rows of the grid, G per block, at centred positions n' mod F:
+// z = rho + i rho d(n1) d(n2) (the type-2 deconvolution rides in the imaginary
+// part), one F-point FFT; the transform of the real part on m = 0..N is the I1
+// half spectrum, that of the imaginary part on the Q window frequencies is the
+// type-2 row window.
+template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_forward(
-    DevPlan P, const R* __restrict__ rho, R dir) {
+    DevPlan P, const R* __restrict__ rho) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int G = rows_per_block<R, LOG>();
-    constexpr int LP = lds_padded_size(F);
+    static_assert(N % G == 0, "the rows of a block must tile the grid");
+    constexpr int LP = lds_group_stride(F);
     __shared__ cpx<R> lds_all[G * LP];
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
     const int row0 = xcd_logical_block(blockIdx.x, gridDim.x) * G;
-    const int row = row0 + g;
-    const double dy = P.deconv[row];
-    const R* src = rho + static_cast<size_t>(row) * N;
-    const cpx<R> zero = {R(0), R(0)};
+    const double dy = P.deconv[row0 + g];
+    const R* src = rho + static_cast<size_t>(row0 + g) * N;
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i < 4 || i >= 12) {
-            const int n1 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
+            const int n1 = slot_col<LOG>(tid, i);
             const R r = src[n1];
             v[i] = {r, static_cast<R>(static_cast<double>(r) * P.deconv[n1] * dy)};
         } else {
-            v[i] = zero;
+            v[i] = {R(0), R(0)};
         }
     }
-    fft_reg<R, LOG>(v, lds, tw, tid, dir);
+    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) lds[lds_pad(tid + NT * i)] = v[i];
     __syncthreads();
-    // outputs of the G rows, row index fastest: G-element runs of each column
+    // outputs of the G rows, row index fastest: G-element runs of each column;
+    // a compile-time number of passes with clamped indices
     cpx<R>* xt = static_cast<cpx<R>*>(P.xt);
-    for (int idx = threadIdx.x; idx < (N + 1) * G; idx += NT * G) {
-        const int gg = idx % G;
-        const int m = idx / G;
+    constexpr int ITEMS = (N + 1) * G;
+    constexpr int PASSES = (ITEMS + NT * G - 1) / (NT * G);
+#pragma unroll
+    for (int k = 0; k < PASSES; ++k) {
+        const int idx = threadIdx.x + k * NT * G;
+        const int idc = idx < ITEMS ? idx : ITEMS - 1;
+        const int gg = idc % G;
+        const int m = idc / G;
         const cpx<R>* l = lds_all + gg * LP;
         const cpx<R> a = l[lds_pad(m)];
         const cpx<R> b = l[lds_pad((F - m) & (F - 1))];
         // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2
-        xt[static_cast<size_t>(m) * N + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+        if (idx < ITEMS) xt[static_cast<size_t>(m) * N + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
     }
     cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
     for (int idx = threadIdx.x; idx < P.patch * G; idx += NT * G) {
@@ -151,74 +175,83 @@ __device__ __forceinline__ R recip(R x) {
 // register layout position tid + NT i holds a grid row only for i < 4
 // (p < N/2) and i >= 12 (p >= F - N/2), so the other inputs are compile-time
 // zeros and the inverse transform's outputs there are never formed.
-template <typename R, int LOG>
-__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P, R dir) {
+template <typename R, int LOG, int DIR>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int G = lines_per_block<LOG>();
-    __shared__ cpx<R> lds_all[G * lds_padded_size(F)];
+    __shared__ cpx<R> lds_all[G * lds_group_stride(F)];
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_padded_size(F);
+    cpx<R>* lds = lds_all + g * lds_group_stride(F);
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
     const int m1 = xcd_logical_block(blockIdx.x, gridDim.x) * G + g;   // 0..N (+ idle lanes of the last block)
     const bool active = m1 <= N;
-    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : 0) * N;
-    const cpx<R> zero = {R(0), R(0)};
+    // idle lanes load column N and never store: no branch around the loads
+    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : N) * N;
+    // (b, 1 - e^{-b}) of the 16 rows this thread multiplies; in FP32 fetched
+    // before the transform so that their latency is hidden by it (in FP64 the
+    // registers are needed by the transform itself)
+    const cpx<R>* gyr = static_cast<const cpx<R>*>(P.gyr);
+    cpx<R> gb[16];
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
+    }
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        if (i < 4) {
-            v[i] = active ? col[tid + NT * i + N / 2] : zero;
-        } else if (i >= 12) {
-            v[i] = active ? col[tid + NT * (i - 12)] : zero;
-        } else {
-            v[i] = zero;
-        }
+        if (i < 4 || i >= 12) v[i] = col[slot_col<LOG>(tid, i)];
+        else v[i] = {R(0), R(0)};
     }
-    fft_reg<R, LOG>(v, lds, tw, tid, dir);
+    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
+    if constexpr (sizeof(R) != 4) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
+    }
     // g1 = -(k_a^2/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with
-    // 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a}, B = 1 - e^{-b} (all terms >= 0)
-    const int mc = active ? m1 : 0;
+    // 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a}, B = 1 - e^{-b} (all terms >= 0);
+    // branch-free, g1(0) = 0
+    const int mc = active ? m1 : N;
     const R a = static_cast<R>(P.gx[2 * mc]);
     const R A = static_cast<R>(P.gx[2 * mc + 1]);
     const R scale = static_cast<R>(P.inv_f2);
+    const bool ycomp = P.component_y != 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const int m2 = tid + NT * i;
-        const R b = static_cast<R>(P.gy[2 * m2]);
-        const R B = static_cast<R>(P.gy[2 * m2 + 1]);
-        const R num = P.component_y ? b : a;
+        const R b = gb[i].x;
+        const R B = gb[i].y;
+        const R num = ycomp ? b : a;
         const R den = a + b;
-        const R gfac = (den > R(0)) ? -(num * recip(den)) * (A + B - A * B) * scale : R(0);
+        const bool pos = den > R(0);
+        R gfac = -(num * recip(pos ? den : R(1))) * (A + B - A * B) * scale;
+        gfac = pos ? gfac : R(0);
         v[i] = cscale(v[i], gfac);
     }
-    fft_reg<R, LOG>(v, lds, tw, tid, -dir);
+    fft_reg<R, LOG, -DIR>(v, lds, tw, tid);
     if (active) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i < 4) col[tid + NT * i + N / 2] = v[i];
-            else if (i >= 12) col[tid + NT * (i - 12)] = v[i];
-        }
+        for (int i = 0; i < 16; ++i)
+            if (i < 4 || i >= 12) col[slot_col<LOG>(tid, i)] = v[i];
     }
 }
 
 // ---------------------------------------------------------------------------
 // cols_type2: FFT along y of the type-2 row window, keep the Q window rows
 // ---------------------------------------------------------------------------
-template <typename R, int LOG>
-__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type2(DevPlan P, R dir) {
+template <typename R, int LOG, int DIR>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type2(DevPlan P) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int G = lines_per_block<LOG>();
-    __shared__ cpx<R> lds_all[G * lds_padded_size(F)];
+    __shared__ cpx<R> lds_all[G * lds_group_stride(F)];
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_padded_size(F);
+    cpx<R>* lds = lds_all + g * lds_group_stride(F);
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
     const int q = P.patch;
     const int i1 = blockIdx.x * G + g;
@@ -236,7 +269,7 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
             v[i] = zero;
         }
     }
-    fft_reg<R, LOG>(v, lds, tw, tid, dir);
+    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     cpx<R>* win = static_cast<cpx<R>*>(P.win);
     if (active) {
 #pragma unroll
@@ -363,21 +396,44 @@ __global__ __launch_bounds__(kNodeThreads) void k_nodes(DevPlan P, const cpx<R>*
     }
     if constexpr (MODE == 1) return;
     if constexpr (MODE == 0) __syncthreads();
+    // two threads per tile cell, each summing half of the nodes (in order), then
+    // one fixed shuffle step; the node loop is unrolled and branch-free so the
+    // LDS reads of several nodes are in flight together
     cpx<R>* tile_out = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(blockIdx.x) * E * E;
-    for (int c = threadIdx.x; c < E * E; c += kNodeThreads) {
+    constexpr int HALF = kMaxNodesPerSub / 2;
+    constexpr int U = 8;
+    const int part = threadIdx.x & 1;
+    for (int c = threadIdx.x >> 1; c < E * E; c += kNodeThreads / 2) {
         const int cb = c / E, ca = c - cb * E;
         R sx = 0, sy = 0, kx = 0, ky = 0;
-        for (int jj = 0; jj < count; ++jj) {
-            const int t1 = ca - s.ox[jj];
-            const int t2 = cb - s.oy[jj];
-            if (static_cast<unsigned>(t1) < static_cast<unsigned>(w) &&
-                static_cast<unsigned>(t2) < static_cast<unsigned>(w)) {
-                const R k = s.psx[jj][t1] * s.psy[jj][t2];
-                kahan_add(sx, kx, s.val[jj].x * k);
-                kahan_add(sy, ky, s.val[jj].y * k);
+        const int j_lo = part * HALF;
+        const int j_hi = (j_lo + HALF < count) ? j_lo + HALF : count;
+        for (int j0 = j_lo; j0 < j_hi; j0 += U) {
+            R kk[U];
+            cpx<R> vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int jj = j0 + u;
+                const bool valid = jj < j_hi;
+                const int jc = valid ? jj : j_lo;
+                const int t1 = ca - s.ox[jc];
+                const int t2 = cb - s.oy[jc];
+                const bool in = valid && static_cast<unsigned>(t1) < static_cast<unsigned>(w) &&
+                                static_cast<unsigned>(t2) < static_cast<unsigned>(w);
+                const R k = s.psx[jc][in ? t1 : 0] * s.psy[jc][in ? t2 : 0];
+                kk[u] = in ? k : R(0);
+                vv[u] = s.val[jc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                kahan_add(sx, kx, vv[u].x * kk[u]);
+                kahan_add(sy, ky, vv[u].y * kk[u]);
             }
         }
-        tile_out[c] = {sx - kx, sy - ky};
+        R vx = sx - kx, vy = sy - ky;
+        vx += __shfl_xor(vx, 1, 2);
+        vy += __shfl_xor(vy, 1, 2);
+        if (part == 0) tile_out[c] = {vx, vy};
     }
 }
 
@@ -387,18 +443,18 @@ __global__ __launch_bounds__(kNodeThreads) void k_nodes(DevPlan P, const cpx<R>*
 // ---------------------------------------------------------------------------
 // Window cell (i1, i2) is the sum of the tile entries listed for it, in list
 // order: L = min(4, NT) lanes split the list, then a fixed shuffle tree.
-template <typename R, int LOG>
-__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type1(DevPlan P, R dir) {
+template <typename R, int LOG, int DIR>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type1(DevPlan P) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int G = lines_per_block<LOG>();
     constexpr int L = NT < 4 ? NT : 4;
-    __shared__ cpx<R> lds_all[G * lds_padded_size(F)];
+    __shared__ cpx<R> lds_all[G * lds_group_stride(F)];
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_padded_size(F);
+    cpx<R>* lds = lds_all + g * lds_group_stride(F);
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
     const int q = P.patch;
     const int i1 = blockIdx.x * G + g;
@@ -441,7 +497,7 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
         const int i2 = posmod_dev(tid + NT * i - P.patch_lo, F);
         v[i] = (active && i2 < q) ? lds[i2] : cpx<R>{R(0), R(0)};
     }
-    fft_reg<R, LOG>(v, lds, tw, tid, dir);
+    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     if (active) {
         cpx<R>* u = static_cast<cpx<R>*>(P.u);
 #pragma unroll
@@ -464,44 +520,52 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
 // F - m) plus i times the Hermitian part H[l] = (U[l] + conj U[-l]) / 2 of the
 // type-1 row on the window frequencies.  One inverse FFT then gives I1 in the
 // real part and Re(type-1 field) / d(n1) in the imaginary part.
-template <typename R, int LOG>
+template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2>
 __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_inverse(
-    DevPlan P, R* __restrict__ out, R dir, int use_i1, int use_i2) {
+    DevPlan P, R* __restrict__ out) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int G = rows_per_block<R, LOG>();
-    constexpr int LP = lds_padded_size(F);
+    static_assert(N % G == 0, "the rows of a block must tile the grid");
+    constexpr int LP = lds_group_stride(F);
     __shared__ cpx<R> lds_all[G * LP];
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
     const int row0 = xcd_logical_block(blockIdx.x, gridDim.x) * G;
-    const int row = row0 + g;
     const cpx<R>* xt = static_cast<const cpx<R>*>(P.xt);
     const cpx<R>* u = static_cast<const cpx<R>*>(P.u);
     const int q = P.patch, lo = P.patch_lo;
-    for (int idx = threadIdx.x; idx < (N + 1) * G; idx += NT * G) {
-        const int gg = idx % G;
-        const int m = idx / G;
+    // (N+1) G entries (column m, row gg), row index fastest; every load is issued
+    // unconditionally (clamped index) so that all of them are in flight at once
+    constexpr int ITEMS = (N + 1) * G;
+    constexpr int PASSES = (ITEMS + NT * G - 1) / (NT * G);
+#pragma unroll
+    for (int k = 0; k < PASSES; ++k) {
+        const int idx = threadIdx.x + k * NT * G;
+        const int idc = idx < ITEMS ? idx : ITEMS - 1;
+        const int gg = idc % G;
+        const int m = idc / G;
         const int r = row0 + gg;
         cpx<R> x = {R(0), R(0)};
-        if (use_i1) x = xt[static_cast<size_t>(m) * N + r];
+        if constexpr (USE_I1) x = xt[static_cast<size_t>(m) * N + r];
         cpx<R> hh = {R(0), R(0)};
-        if (use_i2) {
+        if constexpr (USE_I2) {
             const int ia = posmod_dev(m - lo, F);
             const int ib = posmod_dev(-m - lo, F);
-            if (ia < q || ib < q) {
-                const cpx<R>* urow = u + static_cast<size_t>(r) * q;
-                const cpx<R> ua = (ia < q) ? urow[ia] : cpx<R>{R(0), R(0)};
-                const cpx<R> ub = (ib < q) ? urow[ib] : cpx<R>{R(0), R(0)};
-                hh = {R(0.5) * (ua.x + ub.x), R(0.5) * (ua.y - ub.y)};
-            }
+            const cpx<R>* urow = u + static_cast<size_t>(r) * q;
+            const cpx<R> ua0 = urow[ia < q ? ia : q - 1];
+            const cpx<R> ub0 = urow[ib < q ? ib : q - 1];
+            const cpx<R> ua = (ia < q) ? ua0 : cpx<R>{R(0), R(0)};
+            const cpx<R> ub = (ib < q) ? ub0 : cpx<R>{R(0), R(0)};
+            hh = {R(0.5) * (ua.x + ub.x), R(0.5) * (ua.y - ub.y)};
         }
+        // position m: X + i H;  position F - m: conj X + i conj H (the clamped
+        // duplicate of the last entry rewrites the same values)
         cpx<R>* l = lds_all + gg * LP;
-        // position m: X + i H;  position F - m: conj X + i conj H
         l[lds_pad(m)] = {x.x - hh.y, x.y + hh.x};
         if (m > 0 && m < N) l[lds_pad(F - m)] = {x.x + hh.y, -x.y + hh.x};
     }
@@ -509,12 +573,12 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
-    fft_reg<R, LOG>(v, lds, tw, tid, dir);
-    R* dst = out + static_cast<size_t>(row) * N;
+    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
+    R* dst = out + static_cast<size_t>(row0 + g) * N;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         if (i < 4 || i >= 12) {
-            const int n1 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
+            const int n1 = slot_col<LOG>(tid, i);
             dst[n1] = static_cast<R>(static_cast<double>(v[i].x) + static_cast<double>(v[i].y) * P.deconv[n1]);
         }
     }
@@ -525,44 +589,78 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename R, int LOG>
-hipError_t launch_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
+template <typename R, int LOG, int DIR>
+hipError_t launch_rows_forward_dir(const DevPlan& P, const R* src, hipStream_t s) {
     constexpr int G = rows_per_block<R, LOG>();
-    hipLaunchKernelGGL((k_rows_forward<R, LOG>), dim3(P.n / G), dim3(FftShape<LOG>::NT * G), 0, s, P,
-                       static_cast<const R*>(rho), dir);
+    constexpr int block = FftShape<LOG>::NT * G;
+    const int items = P.n / G;
+    const int grid = items;   // one work item per block
+    hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR>), dim3(grid), dim3(block), 0, s, P, src);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
-hipError_t launch_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
+hipError_t launch_rows_forward(const DevPlan& P, const void* rho, int dir, hipStream_t s) {
+    const R* src = static_cast<const R*>(rho);
+    return dir < 0 ? launch_rows_forward_dir<R, LOG, -1>(P, src, s) : launch_rows_forward_dir<R, LOG, 1>(P, src, s);
+}
+
+template <typename R, int LOG, int DIR>
+hipError_t launch_cols_highfreq_dir(const DevPlan& P, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
-    const int blocks = (P.n + 1 + G - 1) / G;
-    hipLaunchKernelGGL((k_cols_highfreq<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
+    constexpr int block = FftShape<LOG>::NT * G;
+    const int items = (P.n + 1 + G - 1) / G;
+    const int grid = items;   // one work item per block
+    hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR>), dim3(grid), dim3(block), 0, s, P);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
-hipError_t launch_cols_type2(const DevPlan& P, R dir, hipStream_t s) {
+hipError_t launch_cols_highfreq(const DevPlan& P, int dir, hipStream_t s) {
+    return dir < 0 ? launch_cols_highfreq_dir<R, LOG, -1>(P, s) : launch_cols_highfreq_dir<R, LOG, 1>(P, s);
+}
+
+template <typename R, int LOG>
+hipError_t launch_cols_type2(const DevPlan& P, int dir, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
     const int blocks = (P.patch + G - 1) / G;
-    hipLaunchKernelGGL((k_cols_type2<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
+    if (dir < 0) hipLaunchKernelGGL((k_cols_type2<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
+    else hipLaunchKernelGGL((k_cols_type2<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
-hipError_t launch_cols_type1(const DevPlan& P, R dir, hipStream_t s) {
+hipError_t launch_cols_type1(const DevPlan& P, int dir, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
     const int blocks = (P.patch + G - 1) / G;
-    hipLaunchKernelGGL((k_cols_type1<R, LOG>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P, dir);
+    if (dir < 0) hipLaunchKernelGGL((k_cols_type1<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
+    else hipLaunchKernelGGL((k_cols_type1<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
     return hipGetLastError();
 }
 
-template <typename R, int LOG>
-hipError_t launch_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int use_i2, hipStream_t s) {
+template <typename R, int LOG, int DIR, bool I1, bool I2>
+hipError_t launch_rows_inverse_parts(const DevPlan& P, R* dst, hipStream_t s) {
     constexpr int G = rows_per_block<R, LOG>();
-    hipLaunchKernelGGL((k_rows_inverse<R, LOG>), dim3(P.n / G), dim3(FftShape<LOG>::NT * G), 0, s, P,
-                       static_cast<R*>(out), dir, use_i1, use_i2);
+    constexpr int block = FftShape<LOG>::NT * G;
+    const int items = P.n / G;
+    const int grid = items;   // one work item per block
+    hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2>), dim3(grid), dim3(block), 0, s, P, dst);
     return hipGetLastError();
+}
+
+template <typename R, int LOG, int DIR>
+hipError_t launch_rows_inverse_dir(const DevPlan& P, R* dst, int use_i1, int use_i2, hipStream_t s) {
+    if (use_i1 && use_i2) return launch_rows_inverse_parts<R, LOG, DIR, true, true>(P, dst, s);
+    if (use_i1) return launch_rows_inverse_parts<R, LOG, DIR, true, false>(P, dst, s);
+    if (use_i2) return launch_rows_inverse_parts<R, LOG, DIR, false, true>(P, dst, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename R, int LOG>
+hipError_t launch_rows_inverse(const DevPlan& P, void* out, int dir, int use_i1, int use_i2, hipStream_t s) {
+    R* dst = static_cast<R*>(out);
+    if (dir < 0) return launch_rows_inverse_dir<R, LOG, -1>(P, dst, use_i1, use_i2, s);
+    return launch_rows_inverse_dir<R, LOG, 1>(P, dst, use_i1, use_i2, s);
 }
 
 template <int LOG>
@@ -589,23 +687,23 @@ hipError_t check_twiddles(const DevPlan& P) {
     PHI_DISPATCH_LOG(P.log_fine, (twiddles_match<L_>(P) ? hipSuccess : hipErrorInvalidValue));
 }
 template <typename R>
-hipError_t run_rows_forward(const DevPlan& P, const void* rho, R dir, hipStream_t s) {
+hipError_t run_rows_forward(const DevPlan& P, const void* rho, int dir, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_rows_forward<R, L_>(P, rho, dir, s)));
 }
 template <typename R>
-hipError_t run_cols_highfreq(const DevPlan& P, R dir, hipStream_t s) {
+hipError_t run_cols_highfreq(const DevPlan& P, int dir, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_cols_highfreq<R, L_>(P, dir, s)));
 }
 template <typename R>
-hipError_t run_cols_type2(const DevPlan& P, R dir, hipStream_t s) {
+hipError_t run_cols_type2(const DevPlan& P, int dir, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_cols_type2<R, L_>(P, dir, s)));
 }
 template <typename R>
-hipError_t run_cols_type1(const DevPlan& P, R dir, hipStream_t s) {
+hipError_t run_cols_type1(const DevPlan& P, int dir, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_cols_type1<R, L_>(P, dir, s)));
 }
 template <typename R>
-hipError_t run_rows_inverse(const DevPlan& P, void* out, R dir, int use_i1, int use_i2, hipStream_t s) {
+hipError_t run_rows_inverse(const DevPlan& P, void* out, int dir, int use_i1, int use_i2, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_rows_inverse<R, L_>(P, out, dir, use_i1, use_i2, s)));
 }
 
@@ -646,7 +744,7 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
     PHI_TRY(check_twiddles(P));
     // forward solve: type-2 side and the first I1 transforms with e^{-...};
     // the transposed solve reverses every direction
-    const R dir = adjoint ? R(1) : R(-1);
+    const int dir = adjoint ? 1 : -1;
     switch (stage) {
         case Stage::Solve: {
             PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
@@ -683,8 +781,8 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
             return hipSuccess;
         case Stage::Type1:
             PHI_STEP("nodes", s, (run_nodes<R, 2>(P, in, nullptr, s)));
-            PHI_STEP("cols_type1", s, (run_cols_type1<R>(P, R(1), s)));
-            PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, R(1), 0, 1, s)));
+            PHI_STEP("cols_type1", s, (run_cols_type1<R>(P, 1, s)));
+            PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, 1, 0, 1, s)));
             return hipSuccess;
     }
     return hipErrorInvalidValue;

@@ -14,11 +14,13 @@ struct DevPlan {
     phi_dtype dtype;
     int n, n_fine, log_fine;
     int patch, patch_lo, width, n_nodes, component_y;
+    int n_cu;               // compute units of the plan's device (persistent grids)
     double h2, inv_f2;
     // FP64 tables
     const double* deconv;   // [N] 2 pi / (n_fine psi_hat(n'))
     const double* gx;       // [2 (N+1)] I1 multiplier factors along x
     const double* gy;       // [2 F] I1 multiplier factors along y
+    const void* gyr;        // [F] (b, 1 - e^{-b}) pairs of gy in the data precision
     const double* q;        // [M] I2 weights q_j (without h^2)
     // node tables
     const int* cell;        // [2 M] first-tap window cell (x, y)
