@@ -105,6 +105,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (and the error figures that need it)")
+    ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
+                    help="replay each solve from a captured HIP graph (default) or launch it eagerly")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -164,6 +166,25 @@ def main() -> int:
             fn()
     torch.cuda.synchronize()
 
+    if args.launch == "graph":
+        # one captured graph per step kind; a timed step is one replay (the
+        # graph holds exactly the kernels of one solve, or of one solve pair)
+        def capture(fn):
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                fn()
+            return graph.replay
+        fwd32, fwd64, pair32, pair64 = (capture(f) for f in (fwd32, fwd64, pair32, pair64))
+        for fn in (fwd32, fwd64, pair32, pair64):
+            for _ in range(args.warmup):
+                fn()
+        torch.cuda.synchronize()
+
     k = args.steps
     print(f"[bench] timing {k} steps per leg", file=sys.stderr, flush=True)
     t32 = timed_rate(fwd32, k, torch)
@@ -204,7 +225,7 @@ def main() -> int:
         "config": {"workload": "single potential solve, 2048x2048 grid over [-16,16)^2, 8-Gaussian mixture "
                                "density (seed 0), 64x128 polar nodes, NUFFT tol 1e-7 (f32) / 1e-12 (f64)",
                    "grid": N, "half_width": HALF, "n_r": N_R, "n_theta": N_THETA,
-                   "tol_f32": TOL32, "tol_f64": TOL64},
+                   "tol_f32": TOL32, "tol_f64": TOL64, "launch": args.launch},
         "fp64_solves_per_s": k / t64,
         "fp32_over_fp64": t64 / t32,
         "fwd_bwd_solves_per_s": {"f32": k / tp32, "f64": k / tp64},

@@ -242,3 +242,34 @@ def test_autograd_backward_is_the_adjoint(ps):
     g = 2 * (phi.detach() - target)
     ref = plan.solve_adjoint(g)
     assert torch.allclose(r.grad, ref, rtol=0, atol=1e-14 * ref.abs().max().item())
+
+
+def test_graph_replay_matches_eager(ps):
+    """A solve captured into a HIP graph (through torch's capture stream; the
+    node-side chain joins the capture through the plan's fork/join events)
+    gives the eager result on every replay, with other eager work between."""
+    print("case: graph replay 512^2 FP32", flush=True)
+    n = 512
+    rho = W.mixture_density(n, 8.0, W.draw_mixture(12, 8, 3.0, (0.5, 1.5)))
+    other = W.mixture_density(n, 8.0, W.draw_mixture(13, 8, 3.0, (0.5, 1.5)))
+    plan = ps.Plan(n, 16.0 / n, dtype=torch.float32)
+    r = to_dev(rho, torch.float32)
+    o = to_dev(other, torch.float32)
+    eager = plan.solve(r).cpu().numpy()
+    out = torch.empty_like(r)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.solve(r, out)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.solve(r, out)
+    for rep in range(4):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), f"replay {rep}"
+        # unrelated eager work on the same plan between replays
+        plan.solve(o)
+        torch.cuda.synchronize()
