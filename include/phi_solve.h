@@ -101,6 +101,23 @@ phi_status phi_describe(const phi_params* p, phi_plan_info* info);
  * This is the only host-to-device transfer; the copy is complete on return. */
 phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out);
 
+/* Batch of independent solves (Sec. 2.1 applied to each member on its own box):
+ * one plan for `count` members, each with its own parameters (grid side
+ * 128..2048, spacing, node counts, tolerance); all members share one dtype.
+ * Members with equal parameters (field by field) share their device tables; every
+ * member has its own workspace.  phi_solve / phi_solve_adjoint on a batch plan
+ * take packed buffers: member i's N_i x N_i array starts at element offset
+ * offsets[i] (phi_batch_layout).  Each stage of the chain is one launch over
+ * all members.  The stage entry points (phi_solve_highfreq, phi_nodes_type2,
+ * ...) and phi_plan_nodes return PHI_ERR_UNSUPPORTED on batch plans;
+ * phi_plan_get_info describes member 0 and the plan's total device bytes. */
+phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream, phi_plan_t* out);
+
+/* Packed layout of a plan's input and output: *count = members (1 for a single
+ * plan); offsets (may be NULL) receives count + 1 element offsets, member i
+ * occupying [offsets[i], offsets[i+1]). */
+phi_status phi_batch_layout(phi_plan_t plan, int32_t* count, int64_t* offsets);
+
 /* Phi = A rho (Sec. 2.1, eq. 8: I1 + I2).  rho, phi: N x N device arrays. */
 phi_status phi_solve(phi_plan_t plan, const void* rho, void* phi, void* stream);
 

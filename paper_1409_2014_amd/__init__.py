@@ -9,6 +9,7 @@ Python binding.
 """
 from .solver import (  # noqa: F401
     Plan,
+    BatchPlan,
     PhiSolve,
     phi_solve,
     describe,

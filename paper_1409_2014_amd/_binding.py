@@ -60,6 +60,8 @@ def _declare(lib):
         "phi_params_default": (st, [ctypes.POINTER(PhiParams), ctypes.c_int32, ctypes.c_double, ctypes.c_int]),
         "phi_describe": (st, [ctypes.POINTER(PhiParams), ctypes.POINTER(PhiPlanInfo)]),
         "phi_plan": (st, [ctypes.POINTER(PhiParams), _P, ctypes.POINTER(_P)]),
+        "phi_plan_batch": (st, [ctypes.POINTER(PhiParams), ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+        "phi_batch_layout": (st, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
         "phi_solve": (st, [_P, _P, _P, _P]),
         "phi_solve_adjoint": (st, [_P, _P, _P, _P]),
         "phi_solve_highfreq": (st, [_P, _P, _P, _P]),
@@ -107,7 +109,8 @@ def check(status: int, plan=None) -> None:
 def exported_symbols():
     """Names declared by include/phi_solve.h that the binding uses."""
     return [
-        "phi_params_default", "phi_describe", "phi_plan", "phi_solve", "phi_solve_adjoint",
+        "phi_params_default", "phi_describe", "phi_plan", "phi_plan_batch", "phi_batch_layout",
+        "phi_solve", "phi_solve_adjoint",
         "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1",
         "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",

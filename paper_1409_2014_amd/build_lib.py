@@ -26,8 +26,6 @@ HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 arithmetic in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # hardware float atomics for the spread tiles
-    "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function",
 ]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__"]
@@ -48,7 +46,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     incs = [f"-I{INCLUDE}", f"-I{CSRC}", f"-I{ROCM}/include"]
     jobs = []
-    for src, compiler in (("plan_host.cpp", "gxx"), ("phi_api.cpp", "gxx"), ("solver_kernels.hip", "hipcc")):
+    for src, compiler in (("plan_host.cpp", "gxx"), ("phi_api.cpp", "gxx"), ("solver_kernels.hip", "hipcc"),
+                          ("batch_kernels.hip", "hipcc")):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         path = os.path.join(CSRC, src)
         if compiler == "gxx":

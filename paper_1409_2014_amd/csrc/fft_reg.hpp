@@ -144,8 +144,7 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R> (&w)[16], cpx<
     constexpr int NT = Sh::NT;
     constexpr int RAD = Sh::radix(S);
     constexpr int P = Sh::span(S);
-    constexpr int NB = F / RAD;
-    constexpr int C = 16 / RAD;          // butterflies per thread
+    constexpr int C = 16 / RAD;          // butterflies per thread (butterfly b reads b + t F/RAD)
     constexpr bool LAST = (S == Sh::NSTAGE - 1);
     if constexpr (S > 0) {
         // inputs of this stage: positions tid + NT i

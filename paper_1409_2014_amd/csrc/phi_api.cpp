@@ -3,9 +3,11 @@
 // points.  No C++ exception crosses this boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <set>
 #include <string>
 #include <vector>
@@ -15,10 +17,18 @@
 #include "solver_kernels.hpp"
 
 struct phi_plan_s {
+    // single plan: host tables and the device view
     phi::HostPlan host;
     phi::DevPlan dev;
     phi::StreamSet streams;     // side stream + fork/join events of the node-side chain
     phi_params params;
+    // batched plan (n_members > 0): members share a table set when their
+    // parameters are equal; each member has its own workspace
+    int n_members = 0;
+    std::vector<phi::HostPlan> sets;        // distinct table sets
+    std::vector<int> member_set;            // table set of each member
+    std::vector<int64_t> offsets;           // packed element offsets, n_members + 1
+    phi::BatchDev batch;
     int device = 0;
     void* block = nullptr;      // one device allocation: tables + workspace
     size_t block_bytes = 0;
@@ -59,20 +69,196 @@ phi_status check_plan(phi_plan_t plan) {
     return PHI_OK;
 }
 
+phi_status check_device(phi_plan_t plan) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return device_fail(plan, e, "hipGetDevice");
+    if (cur != plan->device) return fail(plan, PHI_ERR_INVALID_ARG, "current device differs from the plan's device");
+    return PHI_OK;
+}
+
+// ---- device layout of tables and workspaces ---------------------------------
+struct Part {
+    size_t off = 0, bytes = 0;
+};
+struct Layout {
+    size_t cursor = 0;
+    Part take(size_t bytes) {
+        Part p{cursor, bytes};
+        cursor = align256(cursor + bytes);
+        return p;
+    }
+};
+// everything a plan reads and never writes
+struct TableParts {
+    Part deconv, gx, gy, gyr, q, cell, sub, cst, con, taps, twr;
+};
+// everything a solve writes
+struct WorkParts {
+    Part xt, tt, win, pts, tiles, u;
+};
+
+TableParts layout_tables(const phi::HostPlan& hp, size_t es, Layout& L) {
+    TableParts t;
+    const size_t n = hp.n, f = hp.n_fine, m = hp.n_nodes;
+    t.deconv = L.take(n * 8);
+    t.gx = L.take(2 * (n + 1) * 8);
+    t.gy = L.take(2 * f * 8);
+    t.gyr = L.take(2 * f * es);
+    t.q = L.take(m * 8);
+    t.cell = L.take(hp.cell.size() * 4);
+    t.sub = L.take(hp.sub.size() * 4);
+    t.cst = L.take(hp.contrib_start.size() * 4);
+    t.con = L.take(hp.contrib.size() * 4);
+    t.taps = L.take(hp.taps.size() * es);
+    t.twr = L.take(hp.twr.size() * es);
+    return t;
+}
+
+WorkParts layout_work(const phi::HostPlan& hp, size_t es, Layout& L) {
+    WorkParts w;
+    const size_t n = hp.n, q = hp.patch, m = hp.n_nodes;
+    w.xt = L.take((n + 1) * n * 2 * es);
+    w.tt = L.take(q * n * 2 * es);
+    w.win = L.take(q * q * 2 * es);
+    w.pts = L.take(m * 2 * es);
+    w.tiles = L.take(static_cast<size_t>(hp.n_sub) * hp.tile * hp.tile * 2 * es);
+    w.u = L.take(n * q * 2 * es);
+    return w;
+}
+
+// Enqueues the copies of one table set; `keep` holds the rounded FP32 copies
+// until the caller has synchronised the stream.
+hipError_t upload_tables(const phi::HostPlan& hp, const TableParts& t, char* base, bool f32, hipStream_t s,
+                         std::vector<std::vector<float>>& keep) {
+    auto up = [&](const Part& pt, const void* src) -> hipError_t {
+        if (pt.bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
+    };
+    // kernel taps, FFT twiddles and the y factors of g1 are rounded once from FP64
+    // to the data precision
+    auto narrow = [&](const std::vector<double>& v) -> const void* {
+        if (!f32) return v.data();
+        keep.emplace_back(v.begin(), v.end());
+        return keep.back().data();
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(t.deconv, hp.deconv.data());
+    if (e == hipSuccess) e = up(t.gx, hp.gx.data());
+    if (e == hipSuccess) e = up(t.gy, hp.gy.data());
+    if (e == hipSuccess) e = up(t.gyr, narrow(hp.gy));
+    if (e == hipSuccess) e = up(t.q, hp.q.data());
+    if (e == hipSuccess) e = up(t.cell, hp.cell.data());
+    if (e == hipSuccess) e = up(t.sub, hp.sub.data());
+    if (e == hipSuccess) e = up(t.cst, hp.contrib_start.data());
+    if (e == hipSuccess) e = up(t.con, hp.contrib.data());
+    if (e == hipSuccess) e = up(t.taps, narrow(hp.taps));
+    if (e == hipSuccess) e = up(t.twr, narrow(hp.twr));
+    return e;
+}
+
+void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, int n_cu, char* base, const TableParts& t,
+              const WorkParts& w, phi::DevPlan* d) {
+    const double f = hp.n_fine;
+    d->dtype = dtype;
+    d->n = hp.n;
+    d->n_fine = hp.n_fine;
+    d->log_fine = hp.log_fine;
+    d->patch = hp.patch;
+    d->patch_lo = hp.patch_lo;
+    d->width = hp.width;
+    d->n_nodes = hp.n_nodes;
+    d->component_y = hp.component_y;
+    d->n_cu = n_cu;
+    d->h2 = hp.h * hp.h;
+    d->inv_f2 = 1.0 / (f * f);
+    d->deconv = reinterpret_cast<const double*>(base + t.deconv.off);
+    d->gx = reinterpret_cast<const double*>(base + t.gx.off);
+    d->gy = reinterpret_cast<const double*>(base + t.gy.off);
+    d->gyr = base + t.gyr.off;
+    d->q = reinterpret_cast<const double*>(base + t.q.off);
+    d->cell = reinterpret_cast<const int*>(base + t.cell.off);
+    d->taps = base + t.taps.off;
+    d->sub = reinterpret_cast<const int*>(base + t.sub.off);
+    d->contrib_start = reinterpret_cast<const int*>(base + t.cst.off);
+    d->contrib = reinterpret_cast<const int*>(base + t.con.off);
+    d->n_sub = hp.n_sub;
+    d->bin = hp.bin;
+    d->tile = hp.tile;
+    d->twr = base + t.twr.off;
+    d->twr_count = static_cast<int>(hp.twr.size() / 2);
+    d->xt = base + w.xt.off;
+    d->tt = base + w.tt.off;
+    d->win = base + w.win.off;
+    d->pts = base + w.pts.off;
+    d->tiles = base + w.tiles.off;
+    d->u = base + w.u.off;
+}
+
+int device_cu_count(int device) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+phi_status create_streams(phi_plan_t plan) {
+    // the node-side chain runs on a second stream of the plan's device, default priority
+    hipError_t e = hipStreamCreateWithFlags(&plan->streams.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->streams.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->streams.join, hipEventDisableTiming);
+    if (e != hipSuccess) return device_fail(nullptr, e, "plan streams");
+    return PHI_OK;
+}
+
+void release(phi_plan_t plan) {
+    if (plan->timer_ready) {
+        for (int i = 0; i < 2 * phi::KernelTimer::kMax; ++i) (void)hipEventDestroy(plan->timer.ev[i]);
+    }
+    if (plan->streams.join) (void)hipEventDestroy(plan->streams.join);
+    if (plan->streams.fork) (void)hipEventDestroy(plan->streams.fork);
+    if (plan->streams.side) (void)hipStreamDestroy(plan->streams.side);
+    if (plan->block) (void)hipFree(plan->block);
+    plan->block = nullptr;
+}
+
+phi_status register_plan(phi_plan_t plan, phi_plan_t* out) {
+    std::lock_guard<std::mutex> lock(g_registry_mutex);
+    registry().insert(plan);
+    *out = plan;
+    return PHI_OK;
+}
+
+hipError_t enqueue_any(phi_plan_t plan, phi::Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
+                       phi::KernelTimer* timer) {
+    if (plan->n_members > 0) return phi::enqueue_batch(plan->batch, in, out, adjoint, s, timer);
+    return phi::enqueue(plan->dev, plan->streams, stage, in, out, adjoint, s, timer);
+}
+
 phi_status run(phi_plan_t plan, phi::Stage stage, const void* in, void* out, int adjoint, void* stream) {
     phi_status st = check_plan(plan);
     if (st != PHI_OK) return st;
     if (!in || !out) return fail(plan, PHI_ERR_INVALID_ARG, "NULL data pointer");
     if (in == out) return fail(plan, PHI_ERR_INVALID_ARG, "input and output must not alias");
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return device_fail(plan, e, "hipGetDevice");
-    if (cur != plan->device) {
-        return fail(plan, PHI_ERR_INVALID_ARG, "current device differs from the plan's device");
-    }
-    e = phi::enqueue(plan->dev, plan->streams, stage, in, out, adjoint, static_cast<hipStream_t>(stream));
+    if (plan->n_members > 0 && stage != phi::Stage::Solve)
+        return fail(plan, PHI_ERR_UNSUPPORTED, "stage entry points take single plans only");
+    st = check_device(plan);
+    if (st != PHI_OK) return st;
+    hipError_t e = enqueue_any(plan, stage, in, out, adjoint, static_cast<hipStream_t>(stream), nullptr);
     if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
     return PHI_OK;
+}
+
+// Field-wise equality (the struct's padding bytes are not compared).
+bool same_params(const phi_params& a, const phi_params& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.hx == b.hx && a.hy == b.hy && a.n_r == b.n_r &&
+           a.n_theta == b.n_theta && a.tol == b.tol && a.pad == b.pad && a.sigma == b.sigma &&
+           a.cutoff == b.cutoff && a.dtype == b.dtype && a.flags == b.flags;
+}
+
+// Work items of one member and stage: first row / column / subproblem of each
+// block.  Members are listed largest first, so the last blocks to start are short.
+void push_items(std::vector<phi::WorkItem>* v, int member, int kind, int count, int step) {
+    for (int i = 0; i < count; i += step) v->push_back({member, i, kind, 0});
 }
 
 }  // namespace
@@ -154,134 +340,210 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
             delete plan;
             return device_fail(nullptr, e, "hipGetDevice");
         }
-        const size_t es = (p->dtype == PHI_F32) ? 4 : 8;   // real element size
-        const size_t n = hp.n, f = hp.n_fine, q = hp.patch, m = hp.n_nodes;
-        // layout of the single allocation
-        struct Part { size_t off, bytes; };
-        size_t cursor = 0;
-        auto take = [&](size_t bytes) { Part pt{cursor, bytes}; cursor = align256(cursor + bytes); return pt; };
-        Part p_deconv = take(n * 8);
-        Part p_gx = take(2 * (n + 1) * 8);
-        Part p_gy = take(2 * f * 8);
-        Part p_gyr = take(2 * f * es);
-        Part p_q = take(m * 8);
-        Part p_cell = take(hp.cell.size() * 4);
-        Part p_sub = take(hp.sub.size() * 4);
-        Part p_cst = take(hp.contrib_start.size() * 4);
-        Part p_con = take(hp.contrib.size() * 4);
-        Part p_taps = take(hp.taps.size() * es);
-        Part p_twr = take(hp.twr.size() * es);
-        Part p_xt = take((n + 1) * n * 2 * es);
-        Part p_tt = take(q * n * 2 * es);
-        Part p_win = take(q * q * 2 * es);
-        Part p_pts = take(m * 2 * es);
-        Part p_tiles = take(static_cast<size_t>(hp.n_sub) * hp.tile * hp.tile * 2 * es);
-        Part p_u = take(n * q * 2 * es);
-        plan->block_bytes = cursor;
-        e = hipMalloc(&plan->block, cursor);
+        const bool f32 = (p->dtype == PHI_F32);
+        const size_t es = f32 ? 4 : 8;
+        Layout L;
+        const TableParts tp = layout_tables(hp, es, L);
+        const WorkParts wp = layout_work(hp, es, L);
+        plan->block_bytes = L.cursor;
+        e = hipMalloc(&plan->block, L.cursor);
         if (e != hipSuccess) {
             (void)hipGetLastError();
+            plan->block = nullptr;
             delete plan;
             return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
         }
         char* base = static_cast<char*>(plan->block);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        auto up = [&](const Part& pt, const void* src) -> hipError_t {
-            if (pt.bytes == 0) return hipSuccess;
-            return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
-        };
-        // kernel taps and FFT twiddles are rounded once from FP64 to the data precision
-        std::vector<float> taps32, twr32, gy32;
-        if (p->dtype == PHI_F32) {
-            gy32.assign(hp.gy.begin(), hp.gy.end());
-            taps32.assign(hp.taps.begin(), hp.taps.end());
-            twr32.assign(hp.twr.begin(), hp.twr.end());
-        }
-        const bool f32 = (p->dtype == PHI_F32);
-        hipError_t ce = hipSuccess;
-        if (ce == hipSuccess) ce = up(p_deconv, hp.deconv.data());
-        if (ce == hipSuccess) ce = up(p_gx, hp.gx.data());
-        if (ce == hipSuccess) ce = up(p_gy, hp.gy.data());
-        if (ce == hipSuccess) ce = up(p_gyr, f32 ? static_cast<const void*>(gy32.data())
-                                                 : static_cast<const void*>(hp.gy.data()));
-        if (ce == hipSuccess) ce = up(p_q, hp.q.data());
-        if (ce == hipSuccess) ce = up(p_cell, hp.cell.data());
-        if (ce == hipSuccess) ce = up(p_sub, hp.sub.data());
-        if (ce == hipSuccess) ce = up(p_cst, hp.contrib_start.data());
-        if (ce == hipSuccess) ce = up(p_con, hp.contrib.data());
-        if (ce == hipSuccess) ce = up(p_taps, f32 ? static_cast<const void*>(taps32.data())
-                                                  : static_cast<const void*>(hp.taps.data()));
-        if (ce == hipSuccess) ce = up(p_twr, f32 ? static_cast<const void*>(twr32.data())
-                                                 : static_cast<const void*>(hp.twr.data()));
-        if (ce == hipSuccess) ce = hipStreamSynchronize(s);
-        // the node-side chain runs on a second stream of the plan's device, default priority
-        if (ce == hipSuccess) ce = hipStreamCreateWithFlags(&plan->streams.side, hipStreamNonBlocking);
-        if (ce == hipSuccess) ce = hipEventCreateWithFlags(&plan->streams.fork, hipEventDisableTiming);
-        if (ce == hipSuccess) ce = hipEventCreateWithFlags(&plan->streams.join, hipEventDisableTiming);
-        if (ce != hipSuccess) {
-            if (plan->streams.join) (void)hipEventDestroy(plan->streams.join);
-            if (plan->streams.fork) (void)hipEventDestroy(plan->streams.fork);
-            if (plan->streams.side) (void)hipStreamDestroy(plan->streams.side);
-            (void)hipFree(plan->block);
+        std::vector<std::vector<float>> keep;
+        e = upload_tables(hp, tp, base, f32, s, keep);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            release(plan);
             delete plan;
-            return device_fail(nullptr, ce, "plan setup");
+            return device_fail(nullptr, e, "table upload");
         }
-        phi::DevPlan& d = plan->dev;
-        d.dtype = p->dtype;
-        d.n = hp.n;
-        d.n_fine = hp.n_fine;
-        d.log_fine = hp.log_fine;
-        d.patch = hp.patch;
-        d.patch_lo = hp.patch_lo;
-        d.width = hp.width;
-        d.n_nodes = hp.n_nodes;
-        d.component_y = hp.component_y;
-        d.n_cu = 0;
-        if (hipDeviceGetAttribute(&d.n_cu, hipDeviceAttributeMultiprocessorCount, plan->device) != hipSuccess ||
-            d.n_cu < 1)
-            d.n_cu = 1;
-        d.h2 = hp.h * hp.h;
-        d.inv_f2 = 1.0 / (static_cast<double>(f) * static_cast<double>(f));
-        d.deconv = reinterpret_cast<const double*>(base + p_deconv.off);
-        d.gx = reinterpret_cast<const double*>(base + p_gx.off);
-        d.gy = reinterpret_cast<const double*>(base + p_gy.off);
-        d.gyr = base + p_gyr.off;
-        d.q = reinterpret_cast<const double*>(base + p_q.off);
-        d.cell = reinterpret_cast<const int*>(base + p_cell.off);
-        d.sub = reinterpret_cast<const int*>(base + p_sub.off);
-        d.contrib_start = reinterpret_cast<const int*>(base + p_cst.off);
-        d.contrib = reinterpret_cast<const int*>(base + p_con.off);
-        d.n_sub = hp.n_sub;
-        d.bin = hp.bin;
-        d.tile = hp.tile;
-        d.taps = base + p_taps.off;
-        d.twr = base + p_twr.off;
-        d.twr_count = static_cast<int>(hp.twr.size() / 2);
-        d.xt = base + p_xt.off;
-        d.tt = base + p_tt.off;
-        d.win = base + p_win.off;
-        d.pts = base + p_pts.off;
-        d.tiles = base + p_tiles.off;
-        d.u = base + p_u.off;
-        {
-            std::lock_guard<std::mutex> lock(g_registry_mutex);
-            registry().insert(plan);
+        st = create_streams(plan);
+        if (st != PHI_OK) {
+            release(plan);
+            delete plan;
+            return st;
         }
-        *out = plan;
-        return PHI_OK;
+        fill_dev(hp, p->dtype, device_cu_count(plan->device), base, tp, wp, &plan->dev);
+        return register_plan(plan, out);
     } catch (const std::bad_alloc&) {
         if (plan) {
-            if (plan->block) (void)hipFree(plan->block);
+            release(plan);
             delete plan;
         }
         return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
         if (plan) {
-            if (plan->block) (void)hipFree(plan->block);
+            release(plan);
             delete plan;
         }
         return fail(nullptr, PHI_ERR_INTERNAL, "unexpected exception");
     }
+}
+
+phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream, phi_plan_t* out) {
+    if (!members || !out || count < 1) return fail(nullptr, PHI_ERR_INVALID_ARG, "NULL argument or empty batch");
+    *out = nullptr;
+    phi_plan_s* plan = nullptr;
+    try {
+        plan = new phi_plan_s();
+        plan->n_members = count;
+        plan->member_set.resize(count);
+        const phi_dtype dtype = members[0].dtype;
+        std::vector<phi_params> set_params;
+        for (int i = 0; i < count; ++i) {
+            const phi_params& p = members[i];
+            if (p.dtype != dtype) {
+                delete plan;
+                return fail(nullptr, PHI_ERR_INVALID_ARG, "all members of a batch must have the same dtype");
+            }
+            int found = -1;
+            for (size_t k = 0; k < set_params.size(); ++k)
+                if (same_params(set_params[k], p)) found = static_cast<int>(k);
+            if (found < 0) {
+                phi::HostPlan hp;
+                std::string err;
+                phi_status st = phi::build_host_plan(&p, &hp, &err);
+                if (st != PHI_OK) {
+                    delete plan;
+                    return fail(nullptr, st, "member " + std::to_string(i) + ": " + err);
+                }
+                if (hp.log_fine < phi::kBatchMinLogFine || hp.log_fine > phi::kBatchMaxLogFine) {
+                    delete plan;
+                    return fail(nullptr, PHI_ERR_UNSUPPORTED,
+                                "member " + std::to_string(i) + ": batched grid sides are 128 .. 2048");
+                }
+                set_params.push_back(p);
+                plan->sets.push_back(std::move(hp));
+                found = static_cast<int>(plan->sets.size()) - 1;
+            }
+            plan->member_set[i] = found;
+        }
+        plan->params = members[0];
+        hipError_t e = hipGetDevice(&plan->device);
+        if (e != hipSuccess) {
+            delete plan;
+            return device_fail(nullptr, e, "hipGetDevice");
+        }
+        const bool f32 = (dtype == PHI_F32);
+        const size_t es = f32 ? 4 : 8;
+        // packed element offsets
+        plan->offsets.assign(count + 1, 0);
+        for (int i = 0; i < count; ++i) {
+            const int64_t n = plan->sets[plan->member_set[i]].n;
+            plan->offsets[i + 1] = plan->offsets[i] + n * n;
+        }
+        // work tables, members in decreasing size order
+        std::vector<int> order(count);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return plan->sets[plan->member_set[a]].n > plan->sets[plan->member_set[b]].n;
+        });
+        std::vector<phi::WorkItem> rows, cols, nodes, cols1;
+        for (int i : order) {
+            const phi::HostPlan& hp = plan->sets[plan->member_set[i]];
+            const int g = phi::batch_lines(hp.log_fine);
+            push_items(&rows, i, 0, hp.n, g);
+            push_items(&cols, i, 0, hp.n + 1, g);
+            push_items(&cols, i, 1, hp.patch, g);
+            push_items(&nodes, i, 0, hp.n_sub, 1);
+            push_items(&cols1, i, 0, hp.patch, g);
+        }
+        // one allocation: table sets, member workspaces, device views, work tables
+        Layout L;
+        std::vector<TableParts> tparts;
+        for (const phi::HostPlan& hp : plan->sets) tparts.push_back(layout_tables(hp, es, L));
+        std::vector<WorkParts> wparts;
+        for (int i = 0; i < count; ++i) wparts.push_back(layout_work(plan->sets[plan->member_set[i]], es, L));
+        const Part p_dev = L.take(sizeof(phi::DevPlan) * count);
+        const Part p_off = L.take(sizeof(int64_t) * (count + 1));
+        const Part p_rows = L.take(sizeof(phi::WorkItem) * rows.size());
+        const Part p_cols = L.take(sizeof(phi::WorkItem) * cols.size());
+        const Part p_nodes = L.take(sizeof(phi::WorkItem) * nodes.size());
+        const Part p_cols1 = L.take(sizeof(phi::WorkItem) * cols1.size());
+        plan->block_bytes = L.cursor;
+        e = hipMalloc(&plan->block, L.cursor);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            plan->block = nullptr;
+            delete plan;
+            return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        char* base = static_cast<char*>(plan->block);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        std::vector<std::vector<float>> keep;
+        for (size_t k = 0; k < plan->sets.size() && e == hipSuccess; ++k)
+            e = upload_tables(plan->sets[k], tparts[k], base, f32, s, keep);
+        const int n_cu = device_cu_count(plan->device);
+        std::vector<phi::DevPlan> devs(count);
+        for (int i = 0; i < count; ++i)
+            fill_dev(plan->sets[plan->member_set[i]], dtype, n_cu, base, tparts[plan->member_set[i]], wparts[i],
+                     &devs[i]);
+        auto up = [&](const Part& pt, const void* src) -> hipError_t {
+            if (pt.bytes == 0) return hipSuccess;
+            return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
+        };
+        if (e == hipSuccess) e = up(p_dev, devs.data());
+        if (e == hipSuccess) e = up(p_off, plan->offsets.data());
+        if (e == hipSuccess) e = up(p_rows, rows.data());
+        if (e == hipSuccess) e = up(p_cols, cols.data());
+        if (e == hipSuccess) e = up(p_nodes, nodes.data());
+        if (e == hipSuccess) e = up(p_cols1, cols1.data());
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            release(plan);
+            delete plan;
+            return device_fail(nullptr, e, "table upload");
+        }
+        phi::BatchDev& b = plan->batch;
+        b.dtype = dtype;
+        b.members = reinterpret_cast<const phi::DevPlan*>(base + p_dev.off);
+        b.offsets = reinterpret_cast<const int64_t*>(base + p_off.off);
+        b.rows = reinterpret_cast<const phi::WorkItem*>(base + p_rows.off);
+        b.cols = reinterpret_cast<const phi::WorkItem*>(base + p_cols.off);
+        b.nodes = reinterpret_cast<const phi::WorkItem*>(base + p_nodes.off);
+        b.cols1 = reinterpret_cast<const phi::WorkItem*>(base + p_cols1.off);
+        b.n_rows = static_cast<int>(rows.size());
+        b.n_cols = static_cast<int>(cols.size());
+        b.n_nodes = static_cast<int>(nodes.size());
+        b.n_cols1 = static_cast<int>(cols1.size());
+        plan->host = plan->sets[plan->member_set[0]];
+        return register_plan(plan, out);
+    } catch (const std::bad_alloc&) {
+        if (plan) {
+            release(plan);
+            delete plan;
+        }
+        return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        if (plan) {
+            release(plan);
+            delete plan;
+        }
+        return fail(nullptr, PHI_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+phi_status phi_batch_layout(phi_plan_t plan, int32_t* count, int64_t* offsets) {
+    phi_status st = check_plan(plan);
+    if (st != PHI_OK) return st;
+    if (!count) return fail(plan, PHI_ERR_INVALID_ARG, "NULL count");
+    if (plan->n_members == 0) {
+        *count = 1;
+        if (offsets) {
+            offsets[0] = 0;
+            offsets[1] = static_cast<int64_t>(plan->host.n) * plan->host.n;
+        }
+        return PHI_OK;
+    }
+    *count = plan->n_members;
+    if (offsets) std::memcpy(offsets, plan->offsets.data(), sizeof(int64_t) * (plan->n_members + 1));
+    return PHI_OK;
 }
 
 phi_status phi_destroy(phi_plan_t plan) {
@@ -295,16 +557,11 @@ phi_status phi_destroy(phi_plan_t plan) {
     (void)hipGetDevice(&prev);
     if (prev != plan->device) (void)hipSetDevice(plan->device);
     hipError_t e = hipDeviceSynchronize();   // the plan's last stream work may still read its tables
-    if (e == hipSuccess && plan->timer_ready) {
-        for (int i = 0; i < 2 * phi::KernelTimer::kMax; ++i) (void)hipEventDestroy(plan->timer.ev[i]);
-    }
     if (e == hipSuccess) {
-        (void)hipEventDestroy(plan->streams.join);
-        (void)hipEventDestroy(plan->streams.fork);
-        (void)hipStreamDestroy(plan->streams.side);
+        release(plan);
+    } else {
+        st = fail(nullptr, PHI_ERR_DEVICE, std::string("phi_destroy: ") + hipGetErrorString(e));
     }
-    if (e == hipSuccess) e = hipFree(plan->block);
-    if (e != hipSuccess) st = fail(nullptr, PHI_ERR_DEVICE, std::string("phi_destroy: ") + hipGetErrorString(e));
     if (prev >= 0 && prev != plan->device) (void)hipSetDevice(prev);
     delete plan;
     return st;
@@ -321,6 +578,7 @@ phi_status phi_plan_get_info(phi_plan_t plan, phi_plan_info* info) {
 phi_status phi_plan_nodes(phi_plan_t plan, double* kx, double* ky, double* q) {
     phi_status st = check_plan(plan);
     if (st != PHI_OK) return st;
+    if (plan->n_members > 0) return fail(plan, PHI_ERR_UNSUPPORTED, "node tables of batched plans are per member");
     const size_t m = plan->host.n_nodes;
     if (kx) std::memcpy(kx, plan->host.kx.data(), m * sizeof(double));
     if (ky) std::memcpy(ky, plan->host.ky.data(), m * sizeof(double));
@@ -359,10 +617,9 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
     if (!in || !out || !count || (capacity > 0 && (!kernel_ms || !names)) || capacity < 0)
         return fail(plan, PHI_ERR_INVALID_ARG, "NULL or invalid argument");
     if (in == out) return fail(plan, PHI_ERR_INVALID_ARG, "input and output must not alias");
-    int cur = -1;
-    hipError_t e = hipGetDevice(&cur);
-    if (e != hipSuccess) return device_fail(plan, e, "hipGetDevice");
-    if (cur != plan->device) return fail(plan, PHI_ERR_INVALID_ARG, "current device differs from the plan's device");
+    st = check_device(plan);
+    if (st != PHI_OK) return st;
+    hipError_t e = hipSuccess;
     phi::KernelTimer& t = plan->timer;
     if (!plan->timer_ready) {
         for (int i = 0; i < 2 * phi::KernelTimer::kMax; ++i) {
@@ -376,7 +633,7 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
     }
     t.count = 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    e = phi::enqueue(plan->dev, plan->streams, phi::Stage::Solve, in, out, adjoint ? 1 : 0, s, &t);
+    e = enqueue_any(plan, phi::Stage::Solve, in, out, adjoint ? 1 : 0, s, &t);
     if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(plan, e, "hipStreamSynchronize");

@@ -30,558 +30,56 @@
 // The transposed solve runs the same kernels with every FFT direction reversed.
 #include <hip/hip_runtime.h>
 
-#include "device_common.hpp"
-#include "fft_reg.hpp"
-#include "solver_kernels.hpp"
+#include "solver_device.hpp"
 
 namespace phi {
 
-namespace {
-
-__device__ __forceinline__ int posmod_dev(int a, int b) {
-    int r = a % b;
-    return r < 0 ? r + b : r;
-}
-
-}  // namespace
-
 // ---------------------------------------------------------------------------
-// rows_forward
+// Single-solve kernels: one work item per block
 // ---------------------------------------------------------------------------
-
-// Distance between the LDS buffers of the sequences of one block: the padded
-// length plus 8 entries, so that lanes working on the same position of
-// different sequences fall into different banks.
-__host__ __device__ constexpr int lds_group_stride(int f) { return lds_padded_size(f) + 8; }
-
-// Grid rows per block of the row kernels: as many as fit 1024 threads and about
-// 70 KB of LDS (one FFT buffer per row, two blocks per CU), so the column-major
-// spectrum is written and read in segments of G consecutive rows (two rows in
-// FP32, one in FP64 at the long transforms: measured best among 1, 2 and 4).
-template <typename R, int LOG>
-constexpr int rows_per_block() {
-    constexpr int nt = FftShape<LOG>::NT;
-    constexpr int by_threads = 1024 / nt;
-    constexpr int by_lds = static_cast<int>((70 * 1024) / (lds_group_stride(1 << LOG) * sizeof(cpx<R>)));
-    constexpr int n = (1 << LOG) / 2;
-    int lim = by_threads < by_lds ? by_threads : by_lds;
-    lim = lim < n ? lim : n;
-    int g = 1;                      // largest power of two <= lim: divides N
-    while (2 * g <= lim) g *= 2;
-    return g;
-}
-
-// Grid column of register slot i of thread tid (centred positions: slots 0..3
-// hold n' >= 0, slots 12..15 hold n' < 0, the other slots are zero padding).
-template <int LOG>
-__device__ __forceinline__ int slot_col(int tid, int i) {
-    constexpr int NT = FftShape<LOG>::NT;
-    constexpr int N = (1 << LOG) / 2;
-    return (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
-}
-
-// Rows of the grid, G per block, at centred positions n' mod F:
-// z = rho + i rho d(n1) d(n2) (the type-2 deconvolution rides in the imaginary
-// part), one F-point FFT; the transform of the real part on m = 0..N is the I1
-// half spectrum, that of the imaginary part on the Q window frequencies is the
-// type-2 row window.
 template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_forward(
     DevPlan P, const R* __restrict__ rho) {
-    using Sh = FftShape<LOG>;
-    constexpr int F = Sh::F;
-    constexpr int N = F / 2;
-    constexpr int NT = Sh::NT;
     constexpr int G = rows_per_block<R, LOG>();
-    static_assert(N % G == 0, "the rows of a block must tile the grid");
-    constexpr int LP = lds_group_stride(F);
-    __shared__ cpx<R> lds_all[G * LP];
-    const int g = threadIdx.x / NT;
-    const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * LP;
-    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const int row0 = xcd_logical_block(blockIdx.x, gridDim.x) * G;
-    const double dy = P.deconv[row0 + g];
-    const R* src = rho + static_cast<size_t>(row0 + g) * N;
-    cpx<R> v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (i < 4 || i >= 12) {
-            const int n1 = slot_col<LOG>(tid, i);
-            const R r = src[n1];
-            v[i] = {r, static_cast<R>(static_cast<double>(r) * P.deconv[n1] * dy)};
-        } else {
-            v[i] = {R(0), R(0)};
-        }
-    }
-    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) lds[lds_pad(tid + NT * i)] = v[i];
-    __syncthreads();
-    // outputs of the G rows, row index fastest: G-element runs of each column;
-    // a compile-time number of passes with clamped indices
-    cpx<R>* xt = static_cast<cpx<R>*>(P.xt);
-    constexpr int ITEMS = (N + 1) * G;
-    constexpr int PASSES = (ITEMS + NT * G - 1) / (NT * G);
-#pragma unroll
-    for (int k = 0; k < PASSES; ++k) {
-        const int idx = threadIdx.x + k * NT * G;
-        const int idc = idx < ITEMS ? idx : ITEMS - 1;
-        const int gg = idc % G;
-        const int m = idc / G;
-        const cpx<R>* l = lds_all + gg * LP;
-        const cpx<R> a = l[lds_pad(m)];
-        const cpx<R> b = l[lds_pad((F - m) & (F - 1))];
-        // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2
-        if (idx < ITEMS) xt[static_cast<size_t>(m) * N + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
-    }
-    cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
-    for (int idx = threadIdx.x; idx < P.patch * G; idx += NT * G) {
-        const int gg = idx % G;
-        const int i = idx / G;
-        const int lf = P.patch_lo + i;
-        const cpx<R>* l = lds_all + gg * LP;
-        const cpx<R> a = l[lds_pad(lf & (F - 1))];
-        const cpx<R> b = l[lds_pad((-lf) & (F - 1))];
-        // transform of the imaginary part: (Z[l] - conj Z[-l]) / (2i)
-        tt[static_cast<size_t>(i) * N + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
-    }
+    __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
+    rows_forward_body<R, LOG, DIR, G>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
-// ---------------------------------------------------------------------------
-// cols_highfreq: FFT along y, multiplier, inverse FFT along y (in place in XT)
-// ---------------------------------------------------------------------------
-
-// Sequences per block of a register-FFT kernel: blocks of at least 256 threads.
-template <int LOG>
-constexpr int lines_per_block() {
-    constexpr int nt = FftShape<LOG>::NT;
-    return nt >= 256 ? 1 : 256 / nt;
-}
-
-template <typename R>
-__device__ __forceinline__ R recip(R x) {
-    if constexpr (sizeof(R) == 4) {
-        const float r = __builtin_amdgcn_rcpf(x);
-        return r * (2.0f - x * r);      // one Newton step: correctly rounded to within an ulp
-    } else {
-        return 1.0 / x;
-    }
-}
-
-// Column m1 of the half spectrum (contiguous in XT, N values at centred y
-// positions) is transformed along y with the zero padding implicit: in the
-// register layout position tid + NT i holds a grid row only for i < 4
-// (p < N/2) and i >= 12 (p >= F - N/2), so the other inputs are compile-time
-// zeros and the inverse transform's outputs there are never formed.
 template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P) {
-    using Sh = FftShape<LOG>;
-    constexpr int F = Sh::F;
-    constexpr int N = F / 2;
-    constexpr int NT = Sh::NT;
     constexpr int G = lines_per_block<LOG>();
-    __shared__ cpx<R> lds_all[G * lds_group_stride(F)];
-    const int g = threadIdx.x / NT;
-    const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_group_stride(F);
-    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const int m1 = xcd_logical_block(blockIdx.x, gridDim.x) * G + g;   // 0..N (+ idle lanes of the last block)
-    const bool active = m1 <= N;
-    // idle lanes load column N and never store: no branch around the loads
-    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : N) * N;
-    // (b, 1 - e^{-b}) of the 16 rows this thread multiplies; in FP32 fetched
-    // before the transform so that their latency is hidden by it (in FP64 the
-    // registers are needed by the transform itself)
-    const cpx<R>* gyr = static_cast<const cpx<R>*>(P.gyr);
-    cpx<R> gb[16];
-    if constexpr (sizeof(R) == 4) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
-    }
-    cpx<R> v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (i < 4 || i >= 12) v[i] = col[slot_col<LOG>(tid, i)];
-        else v[i] = {R(0), R(0)};
-    }
-    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    if constexpr (sizeof(R) != 4) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
-    }
-    // g1 = -(k_a^2/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with
-    // 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a}, B = 1 - e^{-b} (all terms >= 0);
-    // branch-free, g1(0) = 0
-    const int mc = active ? m1 : N;
-    const R a = static_cast<R>(P.gx[2 * mc]);
-    const R A = static_cast<R>(P.gx[2 * mc + 1]);
-    const R scale = static_cast<R>(P.inv_f2);
-    const bool ycomp = P.component_y != 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const R b = gb[i].x;
-        const R B = gb[i].y;
-        const R num = ycomp ? b : a;
-        const R den = a + b;
-        const bool pos = den > R(0);
-        R gfac = -(num * recip(pos ? den : R(1))) * (A + B - A * B) * scale;
-        gfac = pos ? gfac : R(0);
-        v[i] = cscale(v[i], gfac);
-    }
-    fft_reg<R, LOG, -DIR>(v, lds, tw, tid);
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < 4 || i >= 12) col[slot_col<LOG>(tid, i)] = v[i];
-    }
+    __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
+    cols_highfreq_body<R, LOG, DIR, G>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
-// ---------------------------------------------------------------------------
-// cols_type2: FFT along y of the type-2 row window, keep the Q window rows
-// ---------------------------------------------------------------------------
 template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type2(DevPlan P) {
-    using Sh = FftShape<LOG>;
-    constexpr int F = Sh::F;
-    constexpr int N = F / 2;
-    constexpr int NT = Sh::NT;
     constexpr int G = lines_per_block<LOG>();
-    __shared__ cpx<R> lds_all[G * lds_group_stride(F)];
-    const int g = threadIdx.x / NT;
-    const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_group_stride(F);
-    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const int q = P.patch;
-    const int i1 = blockIdx.x * G + g;
-    const bool active = i1 < q;
-    const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(active ? i1 : 0) * N;
-    const cpx<R> zero = {R(0), R(0)};
-    cpx<R> v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (i < 4) {
-            v[i] = active ? col[tid + NT * i + N / 2] : zero;
-        } else if (i >= 12) {
-            v[i] = active ? col[tid + NT * (i - 12)] : zero;
-        } else {
-            v[i] = zero;
-        }
-    }
-    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    cpx<R>* win = static_cast<cpx<R>*>(P.win);
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int i2 = posmod_dev(tid + NT * i - P.patch_lo, F);   // window row of this position
-            if (i2 < q) win[static_cast<size_t>(i2) * q + i1] = v[i];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// nodes: interpolation, polar multiplier and spreading of one subproblem
-// ---------------------------------------------------------------------------
-// A subproblem is a run of at most 64 nodes whose first kernel taps lie in one
-// bin of bin x bin window cells, so all their taps fall in the E x E tile
-// (E = bin + w - 1) at the bin's corner.  The block stages that tile of the
-// type-2 window, the nodes' tap values and first-tap offsets in LDS, then
-//   interp:  c_j = sum_{t1,t2} tile[oy+t2][ox+t1] psi_x[t1] psi_y[t2]
-//            (16 lanes per node, fixed reduction tree)        [eq. (16), (12)]
-//   a_j = q_j h^2 c_j                                          [eq. (12)]
-//   spread:  T[cb][ca] = sum_j a_j psi_x[ca-ox_j] psi_y[cb-oy_j] (one thread per
-//            tile cell, nodes in order, compensated in FP32)   [eq. (15)]
-// and writes its whole tile T to its own slot: no atomics.  The tiles are
-// summed onto the window by cols_type1 through a precomputed index list.
-// MODE 0: all three steps; MODE 1: interp only, out[j] = h^2 c_j (type-2 stage);
-// MODE 2: spread only, of coef (type-1 stage).
-constexpr int kNodeThreads = 256;
-constexpr int kLanesPerNode = 16;
-constexpr int kTileMax = kBinSize + kMaxKernelWidth - 1;
-
-template <typename R>
-struct NodeLds {
-    cpx<R> tile[kTileMax * kTileMax];
-    R psx[kMaxNodesPerSub][kMaxKernelWidth];
-    R psy[kMaxNodesPerSub][kMaxKernelWidth];
-    int ox[kMaxNodesPerSub];
-    int oy[kMaxNodesPerSub];
-    cpx<R> val[kMaxNodesPerSub];
-};
-
-template <typename R>
-__device__ __forceinline__ void kahan_add(R& s, R& c, R v) {
-    if constexpr (sizeof(R) == 4) {
-        const R y = v - c;
-        const R t = s + y;
-        c = (t - s) - y;
-        s = t;
-    } else {
-        s += v;
-    }
+    __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
+    cols_type2_body<R, LOG, DIR, G>(P, blockIdx.x * G, lds_all);
 }
 
 template <typename R, int MODE>
 __global__ __launch_bounds__(kNodeThreads) void k_nodes(DevPlan P, const cpx<R>* __restrict__ coef,
                                                         cpx<R>* __restrict__ out) {
     __shared__ NodeLds<R> s;
-    const int* sub = P.sub + 4 * blockIdx.x;
-    const int bx = sub[0], by = sub[1], first = sub[2], count = sub[3];
-    const int w = P.width, E = P.tile, q = P.patch, bin = P.bin;
-    const int x0 = bx * bin, y0 = by * bin;   // tile corner in window cells
-    const R* taps = static_cast<const R*>(P.taps);
-    // node data
-    for (int e = threadIdx.x; e < count * w; e += kNodeThreads) {
-        const int jj = e / w, t = e - jj * w;
-        const R* tn = taps + static_cast<size_t>(first + jj) * 2 * w;
-        s.psx[jj][t] = tn[t];
-        s.psy[jj][t] = tn[w + t];
-    }
-    for (int jj = threadIdx.x; jj < count; jj += kNodeThreads) {
-        s.ox[jj] = P.cell[2 * (first + jj)] - x0;
-        s.oy[jj] = P.cell[2 * (first + jj) + 1] - y0;
-        if constexpr (MODE == 2) s.val[jj] = coef[first + jj];
-    }
-    if constexpr (MODE != 2) {
-        // the type-2 window tile; the window side is a power of two and tiles only
-        // wrap when the window is the whole periodic fine grid
-        const bool whole = (q == P.n_fine);
-        const cpx<R>* win = static_cast<const cpx<R>*>(P.win);
-        for (int c = threadIdx.x; c < E * E; c += kNodeThreads) {
-            const int cb = c / E, ca = c - cb * E;
-            int wx = x0 + ca, wy = y0 + cb;
-            bool inside = true;
-            if (whole) {
-                wx &= q - 1;
-                wy &= q - 1;
-            } else {
-                inside = wx < q && wy < q;
-            }
-            s.tile[c] = inside ? win[static_cast<size_t>(wy) * q + wx] : cpx<R>{R(0), R(0)};
-        }
-    }
-    __syncthreads();
-    if constexpr (MODE != 2) {
-        const int lane = threadIdx.x % kLanesPerNode;
-        for (int jj0 = 0; jj0 < count; jj0 += kNodeThreads / kLanesPerNode) {
-            const int jj = jj0 + threadIdx.x / kLanesPerNode;
-            cpx<R> acc = {R(0), R(0)};
-            if (jj < count) {
-                const int ox = s.ox[jj], oy = s.oy[jj];
-                for (int t = lane; t < w * w; t += kLanesPerNode) {
-                    const int t2 = t / w;
-                    const int t1 = t - t2 * w;
-                    const R k = s.psx[jj][t1] * s.psy[jj][t2];
-                    const cpx<R> b = s.tile[(oy + t2) * E + ox + t1];
-                    acc.x += b.x * k;
-                    acc.y += b.y * k;
-                }
-            }
-#pragma unroll
-            for (int off = kLanesPerNode / 2; off > 0; off >>= 1) {
-                acc.x += __shfl_xor(acc.x, off, kLanesPerNode);
-                acc.y += __shfl_xor(acc.y, off, kLanesPerNode);
-            }
-            if (jj < count && lane == 0) {
-                const int j = first + jj;
-                if constexpr (MODE == 1) {
-                    out[j] = {static_cast<R>(acc.x * P.h2), static_cast<R>(acc.y * P.h2)};
-                } else {
-                    const double scale = P.q[j] * P.h2;
-                    s.val[jj] = {static_cast<R>(acc.x * scale), static_cast<R>(acc.y * scale)};
-                }
-            }
-        }
-    }
-    if constexpr (MODE == 1) return;
-    if constexpr (MODE == 0) __syncthreads();
-    // two threads per tile cell, each summing half of the nodes (in order), then
-    // one fixed shuffle step; the node loop is unrolled and branch-free so the
-    // LDS reads of several nodes are in flight together
-    cpx<R>* tile_out = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(blockIdx.x) * E * E;
-    constexpr int HALF = kMaxNodesPerSub / 2;
-    constexpr int U = 8;
-    const int part = threadIdx.x & 1;
-    for (int c = threadIdx.x >> 1; c < E * E; c += kNodeThreads / 2) {
-        const int cb = c / E, ca = c - cb * E;
-        R sx = 0, sy = 0, kx = 0, ky = 0;
-        const int j_lo = part * HALF;
-        const int j_hi = (j_lo + HALF < count) ? j_lo + HALF : count;
-        for (int j0 = j_lo; j0 < j_hi; j0 += U) {
-            R kk[U];
-            cpx<R> vv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int jj = j0 + u;
-                const bool valid = jj < j_hi;
-                const int jc = valid ? jj : j_lo;
-                const int t1 = ca - s.ox[jc];
-                const int t2 = cb - s.oy[jc];
-                const bool in = valid && static_cast<unsigned>(t1) < static_cast<unsigned>(w) &&
-                                static_cast<unsigned>(t2) < static_cast<unsigned>(w);
-                const R k = s.psx[jc][in ? t1 : 0] * s.psy[jc][in ? t2 : 0];
-                kk[u] = in ? k : R(0);
-                vv[u] = s.val[jc];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                kahan_add(sx, kx, vv[u].x * kk[u]);
-                kahan_add(sy, ky, vv[u].y * kk[u]);
-            }
-        }
-        R vx = sx - kx, vy = sy - ky;
-        vx += __shfl_xor(vx, 1, 2);
-        vy += __shfl_xor(vy, 1, 2);
-        if (part == 0) tile_out[c] = {vx, vy};
-    }
+    nodes_body<R, MODE>(P, blockIdx.x, coef, out, s);
 }
 
-// ---------------------------------------------------------------------------
-// cols_type1: sum the spread tiles onto one window column, FFT along y (only
-// the Q window inputs are non-zero), keep the N centred rows, times d(n2)
-// ---------------------------------------------------------------------------
-// Window cell (i1, i2) is the sum of the tile entries listed for it, in list
-// order: L = min(4, NT) lanes split the list, then a fixed shuffle tree.
 template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type1(DevPlan P) {
-    using Sh = FftShape<LOG>;
-    constexpr int F = Sh::F;
-    constexpr int N = F / 2;
-    constexpr int NT = Sh::NT;
     constexpr int G = lines_per_block<LOG>();
-    constexpr int L = NT < 4 ? NT : 4;
-    __shared__ cpx<R> lds_all[G * lds_group_stride(F)];
-    const int g = threadIdx.x / NT;
-    const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_group_stride(F);
-    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const int q = P.patch;
-    const int i1 = blockIdx.x * G + g;
-    const bool active = i1 < q;
-    // reduced window column, staged at the start of this group's FFT buffer
-    // (q <= F entries); the FFT's first barrier orders these reads before its writes
-    const cpx<R>* tiles = static_cast<const cpx<R>*>(P.tiles);
-    for (int i2 = tid / L; i2 < q; i2 += NT / L) {
-        const int cell = (active ? i1 : 0) * q + i2;
-        const int k0 = P.contrib_start[cell], k1 = P.contrib_start[cell + 1];
-        R sx = 0, sy = 0, kx = 0, ky = 0;
-        // batches of U entries per lane: all index loads, then all value loads,
-        // then the sums in list order
-        constexpr int U = 8;
-        for (int base = k0 + tid % L; base < k1; base += L * U) {
-            int idx[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) idx[u] = (base + u * L < k1) ? P.contrib[base + u * L] : -1;
-            cpx<R> t[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) t[u] = (idx[u] >= 0) ? tiles[idx[u]] : cpx<R>{R(0), R(0)};
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                kahan_add(sx, kx, t[u].x);
-                kahan_add(sy, ky, t[u].y);
-            }
-        }
-        R vx = sx - kx, vy = sy - ky;
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) {
-            vx += __shfl_xor(vx, off, L);
-            vy += __shfl_xor(vy, off, L);
-        }
-        if (tid % L == 0) lds[i2] = {vx, vy};
-    }
-    __syncthreads();
-    cpx<R> v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int i2 = posmod_dev(tid + NT * i - P.patch_lo, F);
-        v[i] = (active && i2 < q) ? lds[i2] : cpx<R>{R(0), R(0)};
-    }
-    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    if (active) {
-        cpx<R>* u = static_cast<cpx<R>*>(P.u);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i < 4 || i >= 12) {
-                const int n2 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
-                const double d = P.deconv[n2];
-                u[static_cast<size_t>(n2) * q + i1] = {static_cast<R>(v[i].x * d), static_cast<R>(v[i].y * d)};
-            }
-        }
-    }
+    __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
+    cols_type1_body<R, LOG, DIR, G>(P, blockIdx.x * G, lds_all);
 }
 
-// ---------------------------------------------------------------------------
-// rows_inverse: Phi row = Re IFFT(S1 + i H) + Im IFFT(S1 + i H) d(n1)
-// ---------------------------------------------------------------------------
-
-// For each of the block's G rows the full F-point row spectrum is assembled in
-// LDS: the Hermitian extension of the I1 half spectrum (column m of XT, conj at
-// F - m) plus i times the Hermitian part H[l] = (U[l] + conj U[-l]) / 2 of the
-// type-1 row on the window frequencies.  One inverse FFT then gives I1 in the
-// real part and Re(type-1 field) / d(n1) in the imaginary part.
 template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2>
 __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_inverse(
     DevPlan P, R* __restrict__ out) {
-    using Sh = FftShape<LOG>;
-    constexpr int F = Sh::F;
-    constexpr int N = F / 2;
-    constexpr int NT = Sh::NT;
     constexpr int G = rows_per_block<R, LOG>();
-    static_assert(N % G == 0, "the rows of a block must tile the grid");
-    constexpr int LP = lds_group_stride(F);
-    __shared__ cpx<R> lds_all[G * LP];
-    const int g = threadIdx.x / NT;
-    const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * LP;
-    const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const int row0 = xcd_logical_block(blockIdx.x, gridDim.x) * G;
-    const cpx<R>* xt = static_cast<const cpx<R>*>(P.xt);
-    const cpx<R>* u = static_cast<const cpx<R>*>(P.u);
-    const int q = P.patch, lo = P.patch_lo;
-    // (N+1) G entries (column m, row gg), row index fastest; every load is issued
-    // unconditionally (clamped index) so that all of them are in flight at once
-    constexpr int ITEMS = (N + 1) * G;
-    constexpr int PASSES = (ITEMS + NT * G - 1) / (NT * G);
-#pragma unroll
-    for (int k = 0; k < PASSES; ++k) {
-        const int idx = threadIdx.x + k * NT * G;
-        const int idc = idx < ITEMS ? idx : ITEMS - 1;
-        const int gg = idc % G;
-        const int m = idc / G;
-        const int r = row0 + gg;
-        cpx<R> x = {R(0), R(0)};
-        if constexpr (USE_I1) x = xt[static_cast<size_t>(m) * N + r];
-        cpx<R> hh = {R(0), R(0)};
-        if constexpr (USE_I2) {
-            const int ia = posmod_dev(m - lo, F);
-            const int ib = posmod_dev(-m - lo, F);
-            const cpx<R>* urow = u + static_cast<size_t>(r) * q;
-            const cpx<R> ua0 = urow[ia < q ? ia : q - 1];
-            const cpx<R> ub0 = urow[ib < q ? ib : q - 1];
-            const cpx<R> ua = (ia < q) ? ua0 : cpx<R>{R(0), R(0)};
-            const cpx<R> ub = (ib < q) ? ub0 : cpx<R>{R(0), R(0)};
-            hh = {R(0.5) * (ua.x + ub.x), R(0.5) * (ua.y - ub.y)};
-        }
-        // position m: X + i H;  position F - m: conj X + i conj H (the clamped
-        // duplicate of the last entry rewrites the same values)
-        cpx<R>* l = lds_all + gg * LP;
-        l[lds_pad(m)] = {x.x - hh.y, x.y + hh.x};
-        if (m > 0 && m < N) l[lds_pad(F - m)] = {x.x + hh.y, -x.y + hh.x};
-    }
-    __syncthreads();
-    cpx<R> v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
-    fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    R* dst = out + static_cast<size_t>(row0 + g) * N;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (i < 4 || i >= 12) {
-            const int n1 = slot_col<LOG>(tid, i);
-            dst[n1] = static_cast<R>(static_cast<double>(v[i].x) + static_cast<double>(v[i].y) * P.deconv[n1]);
-        }
-    }
+    __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
+    rows_inverse_body<R, LOG, DIR, USE_I1, USE_I2, G>(P, out, xcd_logical_block(blockIdx.x, gridDim.x) * G,
+                                                      lds_all);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,22 +218,11 @@ hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t 
         if (e_ != hipSuccess) return e_; \
     } while (0)
 
-// Records the start (end = false) or end (end = true) of kernel `name` on stream s.
-hipError_t mark(KernelTimer* t, const char* name, bool end, hipStream_t s) {
-    if (!t) return hipSuccess;
-    if (t->count >= KernelTimer::kMax) return hipErrorInvalidValue;
-    if (!end) {
-        t->names[t->count] = name;
-        return hipEventRecord(t->ev[2 * t->count], s);
-    }
-    return hipEventRecord(t->ev[2 * t->count++ + 1], s);
-}
-
-#define PHI_STEP(name, stream, expr)                   \
-    do {                                               \
-        PHI_TRY(mark(timer, name, false, stream));     \
-        PHI_TRY(expr);                                 \
-        PHI_TRY(mark(timer, name, true, stream));      \
+#define PHI_STEP(name, stream, expr)                         \
+    do {                                                     \
+        PHI_TRY(mark_kernel(timer, name, false, stream));    \
+        PHI_TRY(expr);                                       \
+        PHI_TRY(mark_kernel(timer, name, true, stream));     \
     } while (0)
 
 template <typename R>
@@ -789,6 +276,16 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
 }
 
 }  // namespace
+
+hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s) {
+    if (!t) return hipSuccess;
+    if (t->count >= KernelTimer::kMax) return hipErrorInvalidValue;
+    if (!end) {
+        t->names[t->count] = name;
+        return hipEventRecord(t->ev[2 * t->count], s);
+    }
+    return hipEventRecord(t->ev[2 * t->count++ + 1], s);
+}
 
 hipError_t enqueue(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
                    hipStream_t s, KernelTimer* timer) {

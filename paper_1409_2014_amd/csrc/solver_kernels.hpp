@@ -58,9 +58,53 @@ struct KernelTimer {
     int count = 0;
 };
 
+// Records the start (end = false) or the end (end = true) of kernel `name` on
+// stream s; no-op without a timer.
+hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s);
+
 // Enqueue a stage chain on stream s (no host synchronisation).  adjoint = 1
 // reverses every transform direction (the transposed operator).
 hipError_t enqueue(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
                    hipStream_t s, KernelTimer* timer = nullptr);
+
+// ---- batches of independent solves of different sizes -----------------------
+// Batched kernels run 256-thread blocks; a block takes one entry of a work table
+// (member, first row / column / subproblem, kind) and dispatches on the
+// member's transform length, so one launch per stage covers every member.
+constexpr int kBatchThreads = 256;
+constexpr int kBatchMinLogFine = 8;    // N = 128
+constexpr int kBatchMaxLogFine = 12;   // N = 2048
+
+// rows or columns per batched block at fine-grid side 2^log_fine (F/16 threads
+// per transform)
+constexpr int batch_lines(int log_fine) {
+    const int nt = (1 << log_fine) / 16;
+    return nt >= kBatchThreads ? 1 : kBatchThreads / nt;
+}
+
+struct WorkItem {
+    int member;   // index into BatchDev::members
+    int item;     // first grid row, spectrum / window column, or subproblem
+    int kind;     // column pass: 0 = I1 spectrum column, 1 = type-2 window column
+    int pad;
+};
+
+// Device tables of a batch (all device pointers).  Member i reads its input at
+// in + offsets[i] and writes its output at out + offsets[i] (elements).
+struct BatchDev {
+    phi_dtype dtype = PHI_F32;
+    const DevPlan* members = nullptr;
+    const int64_t* offsets = nullptr;
+    const WorkItem* rows = nullptr;    // rows_forward and rows_inverse
+    const WorkItem* cols = nullptr;    // I1 columns and type-2 window columns
+    const WorkItem* nodes = nullptr;   // subproblems
+    const WorkItem* cols1 = nullptr;   // type-1 window columns
+    int n_rows = 0, n_cols = 0, n_nodes = 0, n_cols1 = 0;
+};
+
+// Enqueue one solve (adjoint = 0) or transposed solve (adjoint = 1) of every
+// member on stream s: five launches in stream order.
+hipError_t enqueue_batch(const BatchDev& B, const void* in, void* out, int adjoint, hipStream_t s,
+                         KernelTimer* timer = nullptr);
 
 }  // namespace phi

@@ -13,7 +13,7 @@ import torch
 
 from . import _binding as B
 
-__all__ = ["Plan", "PhiSolve", "phi_solve", "describe", "host_gauss_legendre",
+__all__ = ["Plan", "BatchPlan", "PhiSolve", "phi_solve", "describe", "host_gauss_legendre",
            "host_es_kernel", "host_es_transform", "host_polar_nodes", "make_params"]
 
 _DTYPES = {torch.float64: B.PHI_F64, torch.float32: B.PHI_F32}
@@ -202,6 +202,102 @@ class Plan:
         kx, ky, q = np.empty(m), np.empty(m), np.empty(m)
         B.check(B.lib().phi_plan_nodes(self._handle, _dptr(kx), _dptr(ky), _dptr(q)), self._handle)
         return kx, ky, q
+
+
+class BatchPlan:
+    """Independent solves of several densities, possibly of different sizes, as
+    one chain of launches (one per stage over all members).
+
+    BatchPlan(members, dtype=torch.float32) where members is a list of dicts of
+    make_params keyword arguments (n, h, n_r, n_theta, tol, ...).  Inputs and
+    outputs are packed 1-D tensors: member i occupies
+    [offsets[i], offsets[i+1]) as an n_i x n_i row-major grid."""
+
+    def __init__(self, members, *, dtype=torch.float32, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("phisolve needs a ROCm GPU (torch.cuda is not available)")
+        if len(members) == 0:
+            raise ValueError("a batch needs at least one member")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.dtype = dtype
+        self.sizes = [int(m["n"]) for m in members]
+        arr = (B.PhiParams * len(members))()
+        for i, m in enumerate(members):
+            kw = dict(m)
+            kw["dtype"] = dtype
+            arr[i] = make_params(**kw)
+        self._handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            B.check(B.lib().phi_plan_batch(arr, len(members), _stream_handle(self.device),
+                                           ctypes.byref(self._handle)))
+        count = ctypes.c_int32(0)
+        offs = (ctypes.c_int64 * (len(members) + 1))()
+        B.check(B.lib().phi_batch_layout(self._handle, ctypes.byref(count), offs), self._handle)
+        self.offsets = [int(offs[i]) for i in range(count.value + 1)]
+        self.total = self.offsets[-1]
+        info = B.PhiPlanInfo()
+        B.check(B.lib().phi_plan_get_info(self._handle, ctypes.byref(info)), self._handle)
+        self.device_bytes = int(info.device_bytes)
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) and self._handle.value:
+            with torch.cuda.device(self.device):
+                B.check(B.lib().phi_destroy(self._handle))
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, grids) -> torch.Tensor:
+        """One packed device tensor from a list of n_i x n_i tensors or arrays."""
+        out = torch.empty(self.total, dtype=self.dtype, device=self.device)
+        for i, g in enumerate(grids):
+            t = torch.as_tensor(g, dtype=self.dtype, device=self.device)
+            out[self.offsets[i]:self.offsets[i + 1]].copy_(t.reshape(-1))
+        return out
+
+    def unpack(self, packed: torch.Tensor):
+        """Views of the members' n_i x n_i grids in a packed tensor."""
+        return [packed[self.offsets[i]:self.offsets[i + 1]].view(n, n) for i, n in enumerate(self.sizes)]
+
+    def _check_packed(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        if t.device != self.device or t.dtype != self.dtype or t.numel() != self.total:
+            raise ValueError(f"{name} must be a packed {self.dtype} tensor of {self.total} elements on "
+                             f"{self.device}, got {tuple(t.shape)} {t.dtype} on {t.device}")
+        return t.contiguous()
+
+    def _call(self, fn, src, out):
+        src = self._check_packed(src, "input")
+        out = (torch.empty(self.total, dtype=self.dtype, device=self.device) if out is None
+               else self._check_packed(out, "out"))
+        with torch.cuda.device(self.device):
+            B.check(fn(self._handle, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                       _stream_handle(self.device)), self._handle)
+        return out
+
+    def solve(self, rho: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._call(B.lib().phi_solve, rho, out)
+
+    def solve_adjoint(self, g_phi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._call(B.lib().phi_solve_adjoint, g_phi, out)
+
+    def solve_timed(self, src: torch.Tensor, out: torch.Tensor, adjoint: bool = False):
+        cap = 16
+        ms = (ctypes.c_float * cap)()
+        names = (ctypes.c_char_p * cap)()
+        count = ctypes.c_int32(0)
+        src = self._check_packed(src, "input")
+        out = self._check_packed(out, "out")
+        with torch.cuda.device(self.device):
+            B.check(B.lib().phi_solve_timed(self._handle, ctypes.c_void_p(src.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), int(bool(adjoint)),
+                                            _stream_handle(self.device), ms, names, cap,
+                                            ctypes.byref(count)), self._handle)
+        return [(names[i].decode(), float(ms[i])) for i in range(min(count.value, cap))]
 
 
 class PhiSolve(torch.autograd.Function):
