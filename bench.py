@@ -13,7 +13,10 @@ steps; the same line carries the FP64 rate, the FP32/FP64 ratio, the rate of
 forward + transposed solve pairs, the relative errors of both data paths
 against the FP64 oracle, the dominant kernel's HBM roofline figure (HIP events
 recorded around every kernel on its launch stream) and the oracle's own rate
-on the host cores.
+on the host cores.  Two further legs (skipped with --no-extra-legs): a batch
+of 256 densities with sides drawn from {128, 256, 512, 1024} at h = 1/32
+(seed 1; autotuned node sorts), and forward + transposed solve pairs at
+1024^2 over [-16, 16)^2 (mixture seed 2).
 """
 from __future__ import annotations
 
@@ -43,18 +46,27 @@ SEED = 0
 def kernel_bytes(info: dict, real_bytes: int) -> dict:
     """Algorithmic HBM bytes of one launch of each kernel: what the kernel must
     read and write at least (inputs once, outputs once), from the plan's sizes."""
-    n, q, m = info["n"], info["patch"], info["n_nodes"]
+    n, q, m, w = info["n"], info["patch"], info["n_nodes"], info["kernel_width"]
     sr, sc = real_bytes, 2 * real_bytes
     spec = (n + 1) * n * sc            # I1 half spectrum, N+1 columns of N values
+    tiles = info["n_sub"] * info["tile"] ** 2 * sc
     return {
         "rows_forward": n * n * sr + spec + q * n * sc,
         "cols_highfreq": 2 * spec,
         "cols_type2": q * n * sc + q * q * sc,
-        "interp": q * q * sc + m * sc + 3 * m * 8,
-        "spread": m * sc + q * q * sc + 2 * m * 8,
-        "cols_type1": q * q * sc + n * q * sc,
+        # window, per-node taps (2w), first-tap cell (2 int32) and q_j (FP64); tiles out
+        "nodes": q * q * sc + m * (2 * w * sr + 8 + 8) + tiles,
+        # tiles and their index lists in, type-1 column transforms out
+        "cols_type1": tiles + info["n_contrib"] * 4 + (q * q + 1) * 4 + n * q * sc,
         "rows_inverse": spec + n * q * sc + n * n * sr,
     }
+
+
+def solve_alg_bytes(n: int, real_bytes: int) -> int:
+    """Bytes a solve must move at least: rho in, Phi out, and two passes over the
+    half spectrum of the padded transform (N (n_f/2 + 1) complex values) that a
+    row-column realisation cannot keep on chip."""
+    return 2 * n * n * real_bytes + 4 * n * (n + 1) * 2 * real_bytes
 
 
 def timed_rate(fn, steps: int, torch) -> float:
@@ -98,6 +110,110 @@ def cpu_baseline(rho_used: np.ndarray):
                            f"{len(os.sched_getaffinity(0))} host cores visible)"}
 
 
+def capture_graph(fn, torch):
+    """One captured graph per step kind; a timed step is one replay (the graph
+    holds exactly the kernels of one call of fn)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    return graph.replay
+
+
+def event_kernels(timed_call, steps: int, nbytes: dict) -> dict:
+    """Average duration of each kernel over `steps` runs of timed_call (HIP
+    events recorded on each kernel's launch stream) and its algorithmic GB/s."""
+    acc: dict[str, float] = {}
+    for _ in range(steps):
+        for name, ms in timed_call():
+            acc[name] = acc.get(name, 0.0) + ms
+    out = {}
+    for name, tot in acc.items():
+        ms = tot / steps
+        b = nbytes.get(name)
+        out[name] = {"avg_us": round(ms * 1e3, 2), "alg_bytes": b,
+                     "gbs": round(b / (ms * 1e-3) / 1e9, 1) if b else None}
+    return out
+
+
+def batch_leg(args, torch, ps, W) -> dict:
+    """256 independent densities with sides drawn from {128, 256, 512, 1024} at
+    h = 1/32 (seed 1), FP32, autotuned node sorts, one launch per stage over all
+    members, replayed from a captured graph."""
+    members = W.batch_members(seed=1, count=256)
+    params = [dict(n=n, h=2 * half / n, n_r=N_R, n_theta=N_THETA, tol=TOL32, autotune=True)
+              for n, half, _ in members]
+    print("[bench] batch: planning (autotune) and building 256 densities", file=sys.stderr, flush=True)
+    bp = ps.BatchPlan(params, dtype=torch.float32)
+    packed = bp.pack([W.mixture_density(n, half, spec) for n, half, spec in members])
+    out = torch.empty_like(packed)
+
+    def fn():
+        bp.solve(packed, out)
+
+    for _ in range(max(2, args.warmup // 4)):
+        fn()
+    if args.launch == "graph":
+        fn = capture_graph(fn, torch)
+        fn()
+    k = max(10, args.steps // 10)
+    t = timed_rate(fn, k, torch)
+    step_s = t / k
+    alg = sum(solve_alg_bytes(n, 4) for n, _, _ in members)
+    # algorithmic bytes of each batched launch: the members' single-solve figures summed
+    nbytes = {"rows_forward": 0, "cols": 0, "nodes": 0, "cols_type1": 0, "rows_inverse": 0}
+    sizes = {}
+    for i, (n, _, _) in enumerate(members):
+        info = bp.member_info(i)
+        kb = kernel_bytes(info, 4)
+        for name in ("rows_forward", "nodes", "cols_type1", "rows_inverse"):
+            nbytes[name] += kb[name]
+        nbytes["cols"] += kb["cols_highfreq"] + kb["cols_type2"]
+        if n not in sizes:
+            sizes[n] = {"members": 0, "bin": info["bin"], "sub_nodes": info["sub_nodes"]}
+        sizes[n]["members"] += 1
+    kernels = event_kernels(lambda: bp.solve_timed(packed, out), 3, nbytes)
+    res = {"members": len(members), "points": int(bp.total), "solves_per_s": len(members) / step_s,
+           "ms_per_step": 1e3 * step_s, "alg_bytes": alg,
+           "alg_gbs": round(alg / step_s / 1e9, 1), "roofline_frac": round(alg / step_s / 1e9 / HBM_PEAK_GBS, 4),
+           "kernels": kernels, "sizes": {str(n): v for n, v in sorted(sizes.items())}, "steps": k}
+    bp.close()
+    return res
+
+
+def adjoint_leg(args, torch, ps, W) -> dict:
+    """Forward + transposed solve pairs at 1024^2 over [-16, 16)^2 (mixture seed 2),
+    the differentiation workload, both data paths."""
+    n, half = 1024, 16.0
+    rho = W.mixture_density(n, half, W.draw_mixture(2))
+    res = {}
+    for name, dt, tol, rb in (("f32", torch.float32, TOL32, 4), ("f64", torch.float64, TOL64, 8)):
+        plan = ps.Plan(n, 2 * half / n, dtype=dt, n_r=N_R, n_theta=N_THETA, tol=tol)
+        r = torch.as_tensor(rho, dtype=dt, device="cuda")
+        o = torch.empty_like(r)
+        b = torch.empty_like(r)
+
+        def pair():
+            plan.solve(r, o)
+            plan.solve_adjoint(o, b)
+
+        for _ in range(args.warmup):
+            pair()
+        fn = capture_graph(pair, torch) if args.launch == "graph" else pair
+        fn()
+        k = args.steps
+        t = timed_rate(fn, k, torch)
+        alg = 2 * solve_alg_bytes(n, rb)
+        res[name] = {"pairs_per_s": k / t, "alg_gbs": round(alg * k / t / 1e9, 1),
+                     "roofline_frac": round(alg * k / t / 1e9 / HBM_PEAK_GBS, 4)}
+        plan.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +221,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (and the error figures that need it)")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="time only the 2048^2 single solve (skip the batch and 1024^2 adjoint legs)")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="replay each solve from a captured HIP graph (default) or launch it eagerly")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -167,19 +285,7 @@ def main() -> int:
     torch.cuda.synchronize()
 
     if args.launch == "graph":
-        # one captured graph per step kind; a timed step is one replay (the
-        # graph holds exactly the kernels of one solve, or of one solve pair)
-        def capture(fn):
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                fn()
-            torch.cuda.current_stream().wait_stream(side)
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph):
-                fn()
-            return graph.replay
-        fwd32, fwd64, pair32, pair64 = (capture(f) for f in (fwd32, fwd64, pair32, pair64))
+        fwd32, fwd64, pair32, pair64 = (capture_graph(f, torch) for f in (fwd32, fwd64, pair32, pair64))
         for fn in (fwd32, fwd64, pair32, pair64):
             for _ in range(args.warmup):
                 fn()
@@ -194,20 +300,13 @@ def main() -> int:
     phi32 = out32.double().cpu().numpy()
     phi64 = out64.double().cpu().numpy()
 
-    # per-kernel durations from HIP events on the launch stream, FP32 data path
+    # per-kernel durations from HIP events on each kernel's launch stream, FP32 data path
     print("[bench] per-kernel event timing", file=sys.stderr, flush=True)
-    acc: dict[str, float] = {}
-    for _ in range(k):
-        for name, ms in plan32.solve_timed(rho32_dev, out32):
-            acc[name] = acc.get(name, 0.0) + ms
-    avg_ms = {name: v / k for name, v in acc.items()}
     nbytes = kernel_bytes(plan32.info, 4)
-    dominant = max(avg_ms, key=avg_ms.get)
-    achieved = nbytes[dominant] / (avg_ms[dominant] * 1e-3) / 1e9
-    kernels = {name: {"avg_us": round(avg_ms[name] * 1e3, 2),
-                      "alg_bytes": nbytes.get(name),
-                      "gbs": round(nbytes[name] / (avg_ms[name] * 1e-3) / 1e9, 1) if name in nbytes else None}
-               for name in avg_ms}
+    kernels = event_kernels(lambda: plan32.solve_timed(rho32_dev, out32), k, nbytes)
+    dominant = max(kernels, key=lambda name: kernels[name]["avg_us"])
+    achieved = kernels[dominant]["gbs"]
+    alg32, alg64 = solve_alg_bytes(N, 4), solve_alg_bytes(N, 8)
 
     result = {
         "metric": METRIC,
@@ -229,18 +328,27 @@ def main() -> int:
         "fp64_solves_per_s": k / t64,
         "fp32_over_fp64": t64 / t32,
         "fwd_bwd_solves_per_s": {"f32": k / tp32, "f64": k / tp64},
+        "solve_alg_bytes": {"f32": alg32, "f64": alg64},
+        "solve_roofline_frac": {"f32": round(alg32 * k / t32 / 1e9 / HBM_PEAK_GBS, 4),
+                                "f64": round(alg64 * k / t64 / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_f32": kernels,
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+        "node_sort": {"bin": plan32.info["bin"], "sub_nodes": plan32.info["sub_nodes"],
+                      "n_sub": plan32.info["n_sub"]},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
     }
+    plan32.close()
+    plan64.close()
+    if not args.no_extra_legs:
+        result["batch_uneven_f32"] = batch_leg(args, torch, ps, W)
+        print("[bench] adjoint pairs at 1024^2", file=sys.stderr, flush=True)
+        result["adjoint_pairs_1024"] = adjoint_leg(args, torch, ps, W)
     if not args.no_cpu_baseline:
         print("[bench] oracle leg on the host cores", file=sys.stderr, flush=True)
         ref, base = cpu_baseline(rho_used)
         result["cpu_baseline"] = base
         result["rel_err_vs_oracle"] = {"f32": rel_errs(phi32, ref), "f64": rel_errs(phi64, ref)}
-    plan32.close()
-    plan64.close()
     print(json.dumps(result), flush=True)
     return 0
 

@@ -57,6 +57,10 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
 
 /* phi_params.flags */
 #define PHI_COMPONENT_Y 1u   /* multiplier -ky^2/|k|^2 instead of -kx^2/|k|^2 (their sum is -1) */
+#define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
+                                subproblem sizes {32, 64} on the device and keep the fastest; the
+                                choice is visible in phi_plan_info.bin / .sub_nodes.  Results of
+                                different choices differ by rounding only. */
 
 /* Problem statement as the paper gives it (Sec. 2.1): the density on a uniform
  * box with spacing, the padding factor kappa, the partition width sigma and
@@ -71,7 +75,9 @@ typedef struct {
     double sigma;          /* partition width (<= 0: sqrt(ln 1e16) / (2 pi (kappa-1) L))       */
     double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
     phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
-    uint32_t flags;        /* PHI_COMPONENT_Y                                                    */
+    uint32_t flags;        /* PHI_COMPONENT_Y | PHI_AUTOTUNE                                     */
+    int32_t bin;           /* bin side of the node sort in fine-grid cells: 4, 8 or 16 (0: 8)    */
+    int32_t sub_nodes;     /* most nodes per spreading / interpolation block, 8..64 (0: 64)      */
 } phi_params;
 
 /* Derived quantities of a plan (filled by phi_describe / phi_plan_get_info). */
@@ -83,9 +89,14 @@ typedef struct {
     int32_t patch;         /* side Q of the fine-grid window the nodes touch     */
     int32_t patch_lo;      /* lowest fine-grid index of that window (= -Q/2)     */
     int32_t max_cell_nodes;/* most nodes whose first kernel tap is one cell      */
-    int32_t max_gather;    /* most nodes whose taps cover one window cell        */
+    int32_t max_gather;    /* most tile entries summed into one window cell      */
+    int32_t bin;           /* bin side of the node sort (cells)                  */
+    int32_t tile;          /* spread tile side bin + w - 1                       */
+    int32_t n_sub;         /* node blocks (runs of <= sub_nodes nodes of one bin) */
+    int32_t sub_nodes;     /* most nodes per node block                          */
     double h, half_width, sigma, cutoff, beta;
     size_t device_bytes;   /* tables + workspace allocated by phi_plan           */
+    int64_t n_contrib;     /* tile entries summed onto the fine-grid window      */
 } phi_plan_info;
 
 /* Fill *p with defaults for an n x n grid of spacing h: 64 x 128 polar nodes,
@@ -117,6 +128,12 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
  * plan); offsets (may be NULL) receives count + 1 element offsets, member i
  * occupying [offsets[i], offsets[i+1]). */
 phi_status phi_batch_layout(phi_plan_t plan, int32_t* count, int64_t* offsets);
+
+/* Derived quantities of member `member` of a batch plan, as phi_plan_get_info
+ * gives them for a single plan, except device_bytes = 0 (the batch's total is
+ * in phi_plan_get_info).  On a single plan member 0 is the plan itself.
+ * PHI_ERR_INVALID_ARG for a member index out of range. */
+phi_status phi_batch_member_info(phi_plan_t plan, int32_t member, phi_plan_info* info);
 
 /* Phi = A rho (Sec. 2.1, eq. 8: I1 + I2).  rho, phi: N x N device arrays. */
 phi_status phi_solve(phi_plan_t plan, const void* rho, void* phi, void* stream);

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libphisolve.so")
 PHI_F64 = 0
 PHI_F32 = 1
 PHI_COMPONENT_Y = 1
+PHI_AUTOTUNE = 2
 
 STATUS_NAMES = {
     0: "PHI_OK", 1: "PHI_ERR_INVALID_ARG", 2: "PHI_ERR_UNSUPPORTED", 3: "PHI_ERR_TOL_UNREACHABLE",
@@ -27,6 +28,7 @@ class PhiParams(ctypes.Structure):
         ("sigma", ctypes.c_double), ("cutoff", ctypes.c_double),
         ("dtype", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("bin", ctypes.c_int32), ("sub_nodes", ctypes.c_int32),
     ]
 
 
@@ -35,9 +37,12 @@ class PhiPlanInfo(ctypes.Structure):
         ("n", ctypes.c_int32), ("n_fine", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
         ("kernel_width", ctypes.c_int32), ("patch", ctypes.c_int32), ("patch_lo", ctypes.c_int32),
         ("max_cell_nodes", ctypes.c_int32), ("max_gather", ctypes.c_int32),
+        ("bin", ctypes.c_int32), ("tile", ctypes.c_int32), ("n_sub", ctypes.c_int32),
+        ("sub_nodes", ctypes.c_int32),
         ("h", ctypes.c_double), ("half_width", ctypes.c_double), ("sigma", ctypes.c_double),
         ("cutoff", ctypes.c_double), ("beta", ctypes.c_double),
         ("device_bytes", ctypes.c_size_t),
+        ("n_contrib", ctypes.c_int64),
     ]
 
 
@@ -62,6 +67,7 @@ def _declare(lib):
         "phi_plan": (st, [ctypes.POINTER(PhiParams), _P, ctypes.POINTER(_P)]),
         "phi_plan_batch": (st, [ctypes.POINTER(PhiParams), ctypes.c_int32, _P, ctypes.POINTER(_P)]),
         "phi_batch_layout": (st, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+        "phi_batch_member_info": (st, [_P, ctypes.c_int32, ctypes.POINTER(PhiPlanInfo)]),
         "phi_solve": (st, [_P, _P, _P, _P]),
         "phi_solve_adjoint": (st, [_P, _P, _P, _P]),
         "phi_solve_highfreq": (st, [_P, _P, _P, _P]),
@@ -110,6 +116,7 @@ def exported_symbols():
     """Names declared by include/phi_solve.h that the binding uses."""
     return [
         "phi_params_default", "phi_describe", "phi_plan", "phi_plan_batch", "phi_batch_layout",
+        "phi_batch_member_info",
         "phi_solve", "phi_solve_adjoint",
         "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1",
         "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre",

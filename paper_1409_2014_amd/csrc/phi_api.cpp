@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -228,6 +229,121 @@ phi_status register_plan(phi_plan_t plan, phi_plan_t* out) {
     return PHI_OK;
 }
 
+// A single plan on the current device, not yet registered.  On failure
+// nothing is left allocated.
+phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
+    *out = nullptr;
+    std::unique_ptr<phi_plan_s> plan(new phi_plan_s());
+    std::string err;
+    phi_status st = phi::build_host_plan(p, &plan->host, &err);
+    if (st != PHI_OK) return fail(nullptr, st, err);
+    plan->params = *p;
+    const phi::HostPlan& hp = plan->host;
+    hipError_t e = hipGetDevice(&plan->device);
+    if (e != hipSuccess) return device_fail(nullptr, e, "hipGetDevice");
+    const bool f32 = (p->dtype == PHI_F32);
+    const size_t es = f32 ? 4 : 8;
+    Layout L;
+    const TableParts tp = layout_tables(hp, es, L);
+    const WorkParts wp = layout_work(hp, es, L);
+    plan->block_bytes = L.cursor;
+    e = hipMalloc(&plan->block, L.cursor);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        plan->block = nullptr;
+        return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    char* base = static_cast<char*>(plan->block);
+    std::vector<std::vector<float>> keep;
+    e = upload_tables(hp, tp, base, f32, s, keep);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release(plan.get());
+        return device_fail(nullptr, e, "table upload");
+    }
+    st = create_streams(plan.get());
+    if (st != PHI_OK) {
+        release(plan.get());
+        return st;
+    }
+    fill_dev(hp, p->dtype, device_cu_count(plan->device), base, tp, wp, &plan->dev);
+    *out = plan.release();
+    return PHI_OK;
+}
+
+void destroy_unregistered(phi_plan_s* plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    release(plan);
+    delete plan;
+}
+
+// Picks the bin side and subproblem size of the node sort by timing whole
+// solves of a zero density with every candidate on the current device (two
+// warm-up solves, then the median of five).  *best = *p with the fastest
+// candidate's bin / sub_nodes and the autotune flag cleared.
+phi_status autotune(const phi_params* p, hipStream_t s, phi_params* best) {
+    static const int kBins[] = {4, 8, 16};
+    static const int kSubs[] = {32, 64};
+    phi::HostPlan probe;
+    std::string err;
+    phi_status st = phi::derive(p, &probe, &err);
+    if (st != PHI_OK) return fail(nullptr, st, err);
+    const size_t es = (p->dtype == PHI_F32) ? 4 : 8;
+    const size_t grid_bytes = static_cast<size_t>(probe.n) * probe.n * es;
+    void* io = nullptr;
+    hipError_t e = hipMalloc(&io, 2 * grid_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    e = hipMemsetAsync(io, 0, grid_bytes, s);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    *best = *p;
+    best->flags &= ~PHI_AUTOTUNE;
+    float best_ms = -1.f;
+    for (int b : kBins) {
+        for (int sn : kSubs) {
+            if (e != hipSuccess || st != PHI_OK) break;
+            phi_params cand = *best;
+            cand.bin = b;
+            cand.sub_nodes = sn;
+            phi_plan_s* pl = nullptr;
+            st = create_single(&cand, s, &pl);
+            if (st != PHI_OK) break;
+            void* in = io;
+            void* out_buf = static_cast<char*>(io) + grid_bytes;
+            std::vector<float> ms;
+            for (int it = 0; it < 7 && e == hipSuccess; ++it) {
+                if (it >= 2) e = hipEventRecord(ev[0], s);
+                if (e == hipSuccess) e = phi::enqueue(pl->dev, pl->streams, phi::Stage::Solve, in, out_buf, 0, s);
+                if (e == hipSuccess && it >= 2) e = hipEventRecord(ev[1], s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                float t = 0.f;
+                if (e == hipSuccess && it >= 2) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+                if (e == hipSuccess && it >= 2) ms.push_back(t);
+            }
+            destroy_unregistered(pl);
+            if (e != hipSuccess) break;
+            std::nth_element(ms.begin(), ms.begin() + ms.size() / 2, ms.end());
+            const float med = ms[ms.size() / 2];
+            if (best_ms < 0.f || med < best_ms) {
+                best_ms = med;
+                best->bin = b;
+                best->sub_nodes = sn;
+            }
+        }
+    }
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    (void)hipFree(io);
+    if (st != PHI_OK) return st;
+    if (e != hipSuccess) return device_fail(nullptr, e, "autotune");
+    return PHI_OK;
+}
+
 hipError_t enqueue_any(phi_plan_t plan, phi::Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
                        phi::KernelTimer* timer) {
     if (plan->n_members > 0) return phi::enqueue_batch(plan->batch, in, out, adjoint, s, timer);
@@ -297,6 +413,11 @@ static void fill_info(const phi::HostPlan& hp, size_t bytes, phi_plan_info* info
     info->patch_lo = hp.patch_lo;
     info->max_cell_nodes = hp.max_cell_nodes;
     info->max_gather = hp.max_gather;
+    info->bin = hp.bin;
+    info->tile = hp.tile;
+    info->n_sub = hp.n_sub;
+    info->sub_nodes = hp.sub_nodes;
+    info->n_contrib = static_cast<int64_t>(hp.contrib.size());
     info->h = hp.h;
     info->half_width = hp.half_width;
     info->sigma = hp.sigma;
@@ -324,64 +445,20 @@ phi_status phi_describe(const phi_params* p, phi_plan_info* info) {
 phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out) {
     if (!p || !out) return fail(nullptr, PHI_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
-    phi_plan_s* plan = nullptr;
     try {
-        plan = new phi_plan_s();
-        std::string err;
-        phi_status st = phi::build_host_plan(p, &plan->host, &err);
-        if (st != PHI_OK) {
-            delete plan;
-            return fail(nullptr, st, err);
-        }
-        plan->params = *p;
-        const phi::HostPlan& hp = plan->host;
-        hipError_t e = hipGetDevice(&plan->device);
-        if (e != hipSuccess) {
-            delete plan;
-            return device_fail(nullptr, e, "hipGetDevice");
-        }
-        const bool f32 = (p->dtype == PHI_F32);
-        const size_t es = f32 ? 4 : 8;
-        Layout L;
-        const TableParts tp = layout_tables(hp, es, L);
-        const WorkParts wp = layout_work(hp, es, L);
-        plan->block_bytes = L.cursor;
-        e = hipMalloc(&plan->block, L.cursor);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            plan->block = nullptr;
-            delete plan;
-            return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
-        }
-        char* base = static_cast<char*>(plan->block);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        std::vector<std::vector<float>> keep;
-        e = upload_tables(hp, tp, base, f32, s, keep);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            release(plan);
-            delete plan;
-            return device_fail(nullptr, e, "table upload");
+        phi_params chosen = *p;
+        if (p->flags & PHI_AUTOTUNE) {
+            phi_status st = autotune(p, s, &chosen);
+            if (st != PHI_OK) return st;
         }
-        st = create_streams(plan);
-        if (st != PHI_OK) {
-            release(plan);
-            delete plan;
-            return st;
-        }
-        fill_dev(hp, p->dtype, device_cu_count(plan->device), base, tp, wp, &plan->dev);
+        phi_plan_s* plan = nullptr;
+        phi_status st = create_single(&chosen, s, &plan);
+        if (st != PHI_OK) return st;
         return register_plan(plan, out);
     } catch (const std::bad_alloc&) {
-        if (plan) {
-            release(plan);
-            delete plan;
-        }
         return fail(nullptr, PHI_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
-        if (plan) {
-            release(plan);
-            delete plan;
-        }
         return fail(nullptr, PHI_ERR_INTERNAL, "unexpected exception");
     }
 }
@@ -408,7 +485,15 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
             if (found < 0) {
                 phi::HostPlan hp;
                 std::string err;
-                phi_status st = phi::build_host_plan(&p, &hp, &err);
+                phi_params chosen = p;
+                if (p.flags & PHI_AUTOTUNE) {
+                    phi_status st = autotune(&p, static_cast<hipStream_t>(stream), &chosen);
+                    if (st != PHI_OK) {
+                        delete plan;
+                        return st;
+                    }
+                }
+                phi_status st = phi::build_host_plan(&chosen, &hp, &err);
                 if (st != PHI_OK) {
                     delete plan;
                     return fail(nullptr, st, "member " + std::to_string(i) + ": " + err);
@@ -543,6 +628,20 @@ phi_status phi_batch_layout(phi_plan_t plan, int32_t* count, int64_t* offsets) {
     }
     *count = plan->n_members;
     if (offsets) std::memcpy(offsets, plan->offsets.data(), sizeof(int64_t) * (plan->n_members + 1));
+    return PHI_OK;
+}
+
+phi_status phi_batch_member_info(phi_plan_t plan, int32_t member, phi_plan_info* info) {
+    phi_status st = check_plan(plan);
+    if (st != PHI_OK) return st;
+    if (!info) return fail(plan, PHI_ERR_INVALID_ARG, "NULL info");
+    const int count = plan->n_members > 0 ? plan->n_members : 1;
+    if (member < 0 || member >= count) return fail(plan, PHI_ERR_INVALID_ARG, "member index out of range");
+    if (plan->n_members == 0) {
+        fill_info(plan->host, plan->block_bytes, info);
+    } else {
+        fill_info(plan->sets[plan->member_set[member]], 0, info);
+    }
     return PHI_OK;
 }
 

@@ -48,6 +48,8 @@ phi_status fill_defaults(phi_params* p, int32_t n, double h, phi_dtype dtype) {
     p->cutoff = 0.0;
     p->dtype = dtype;
     p->flags = 0;
+    p->bin = 0;
+    p->sub_nodes = 0;
     return PHI_OK;
 }
 
@@ -192,7 +194,13 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
         *err = fmt("tol %g outside [%g, 0.1] for this dtype", p->tol, tol_min);
         return PHI_ERR_TOL_UNREACHABLE;
     }
-    if ((p->flags & ~PHI_COMPONENT_Y) != 0) { *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG; }
+    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_AUTOTUNE)) != 0) { *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG; }
+    if (p->bin != 0 && p->bin != 4 && p->bin != 8 && p->bin != kMaxBinSize) {
+        *err = "bin must be 0, 4, 8 or 16"; return PHI_ERR_INVALID_ARG;
+    }
+    if (p->sub_nodes != 0 && (p->sub_nodes < 8 || p->sub_nodes > kMaxNodesPerSub)) {
+        *err = "sub_nodes must be 0 or in [8, 64]"; return PHI_ERR_INVALID_ARG;
+    }
 
     hp->n = n;
     hp->n_fine = 2 * n;
@@ -227,6 +235,9 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     if (q > hp->n_fine) q = hp->n_fine;
     hp->patch = q;
     hp->patch_lo = -q / 2;
+    // bins never exceed the window (which is a power of two >= 16)
+    hp->bin = std::min(p->bin > 0 ? p->bin : kBinSize, q);
+    hp->sub_nodes = p->sub_nodes > 0 ? p->sub_nodes : kMaxNodesPerSub;
     return PHI_OK;
 }
 
@@ -288,8 +299,8 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
         cx[j] = ax;
         cy[j] = ay;
     }
-    // bins of kBinSize x kBinSize window cells; nodes sorted by the bin of their first tap
-    const int bin = kBinSize;
+    // bins of bin x bin window cells; nodes sorted by the bin of their first tap
+    const int bin = hp->bin;
     const int nb = q_side / bin;        // the window side is a power of two >= 16
     const bool whole = (q_side == nf);
     std::vector<int> key(m);
@@ -312,7 +323,7 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
             hp->taps[(static_cast<size_t>(i) * 2 + 1) * w + t] = es_kernel((uy[j] - (l0y + t)) / half_w, hp->beta);
         }
     }
-    // subproblems: runs of at most kMaxNodesPerSub nodes of one bin
+    // subproblems: runs of at most sub_nodes nodes of one bin
     hp->sub.clear();
     int max_bin = 0;
     for (int i = 0; i < m;) {
@@ -320,15 +331,14 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
         int e = i;
         while (e < m && key[order[e]] == k) ++e;
         max_bin = std::max(max_bin, e - i);
-        for (int s0 = i; s0 < e; s0 += kMaxNodesPerSub) {
+        for (int s0 = i; s0 < e; s0 += hp->sub_nodes) {
             hp->sub.push_back(k % nb);
             hp->sub.push_back(k / nb);
             hp->sub.push_back(s0);
-            hp->sub.push_back(std::min(kMaxNodesPerSub, e - s0));
+            hp->sub.push_back(std::min(hp->sub_nodes, e - s0));
         }
         i = e;
     }
-    hp->bin = bin;
     hp->nb = nb;
     hp->tile = bin + w - 1;
     hp->n_sub = static_cast<int>(hp->sub.size() / 4);

@@ -16,8 +16,9 @@ namespace phi {
 constexpr int kMaxLogFine = 13;        // fine grid up to 8192 (N up to 4096)
 constexpr int kMinLogFine = 4;         // fine grid from 16 (N from 8)
 constexpr int kMaxKernelWidth = 16;
-constexpr int kBinSize = 8;            // bin side in fine-grid cells
-constexpr int kMaxNodesPerSub = 64;    // nodes per interp / spread subproblem
+constexpr int kBinSize = 8;            // default bin side in fine-grid cells
+constexpr int kMaxBinSize = 16;        // largest bin side
+constexpr int kMaxNodesPerSub = 64;    // most nodes per interp / spread subproblem
 
 struct HostPlan {
     // problem
@@ -39,6 +40,7 @@ struct HostPlan {
     std::vector<int32_t> cell;          // [2 M] first-tap window cell (x, y), 0 <= c < patch
     std::vector<double> taps;           // [M][2][w] psi(u_j - l0_j - t), x then y
     int bin = 8, nb = 0;                // bin side in cells, bins per window side
+    int sub_nodes = 64;                 // most nodes per subproblem
     int tile = 0;                       // spread tile side E = bin + w - 1
     std::vector<int32_t> sub;           // [4 n_sub] bin x, bin y, first node, node count (<= 64)
     int n_sub = 0;

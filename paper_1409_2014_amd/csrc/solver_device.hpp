@@ -264,7 +264,7 @@ __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, c
 // MODE 2: spread only, of coef (type-1 stage).
 constexpr int kNodeThreads = 256;
 constexpr int kLanesPerNode = 16;
-constexpr int kTileMax = kBinSize + kMaxKernelWidth - 1;
+constexpr int kTileMax = kMaxBinSize + kMaxKernelWidth - 1;
 
 template <typename R>
 struct NodeLds {
@@ -361,18 +361,18 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
     }
     if constexpr (MODE == 1) return;
     if constexpr (MODE == 0) __syncthreads();
-    // two threads per tile cell, each summing half of the nodes (in order), then
-    // one fixed shuffle step; the node loop is unrolled and branch-free so the
-    // LDS reads of several nodes are in flight together
+    // two threads per tile cell, each summing one half of the nodes (in order),
+    // then one fixed shuffle step; the node loop is unrolled and branch-free so
+    // the LDS reads of several nodes are in flight together
     cpx<R>* tile_out = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(sidx) * E * E;
-    constexpr int HALF = kMaxNodesPerSub / 2;
     constexpr int U = 8;
     const int part = threadIdx.x & 1;
+    const int half_count = (count + 1) >> 1;
+    const int j_lo = part ? half_count : 0;
+    const int j_hi = part ? count : half_count;
     for (int c = threadIdx.x >> 1; c < E * E; c += kNodeThreads / 2) {
         const int cb = c / E, ca = c - cb * E;
         R sx = 0, sy = 0, kx = 0, ky = 0;
-        const int j_lo = part * HALF;
-        const int j_hi = (j_lo + HALF < count) ? j_lo + HALF : count;
         for (int j0 = j_lo; j0 < j_hi; j0 += U) {
             R kk[U];
             cpx<R> vv[U];

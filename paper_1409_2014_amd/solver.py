@@ -30,7 +30,8 @@ def _dtype_code(dtype) -> int:
 
 def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta: int = 128,
                 tol: float | None = None, sigma: float | None = None, cutoff: float | None = None,
-                component: str = "x", pad: int = 2) -> B.PhiParams:
+                component: str = "x", pad: int = 2, bin: int = 0, sub_nodes: int = 0,
+                autotune: bool = False) -> B.PhiParams:
     code = _dtype_code(dtype)
     p = B.PhiParams()
     B.check(B.lib().phi_params_default(ctypes.byref(p), int(n), float(h), code))
@@ -41,7 +42,9 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
     p.pad = int(pad)
     p.sigma = float(sigma) if sigma else 0.0
     p.cutoff = float(cutoff) if cutoff else 0.0
-    p.flags = B.PHI_COMPONENT_Y if component in ("y", "yy") else 0
+    p.flags = (B.PHI_COMPONENT_Y if component in ("y", "yy") else 0) | (B.PHI_AUTOTUNE if autotune else 0)
+    p.bin = int(bin)
+    p.sub_nodes = int(sub_nodes)
     return p
 
 
@@ -98,7 +101,10 @@ class Plan:
     """A solve plan on one GPU (tables + workspace live on the device).
 
     Plan(n, h, dtype=torch.float32|float64, n_r=64, n_theta=128, tol=None,
-         sigma=None, cutoff=None, component="x")"""
+         sigma=None, cutoff=None, component="x", bin=0, sub_nodes=0, autotune=False)
+
+    bin / sub_nodes set the node sort (0: 8 cells, 64 nodes); autotune=True
+    times the candidates on the device at plan time and keeps the fastest."""
 
     def __init__(self, n: int, h: float, *, dtype=torch.float64, device=None, **kwargs):
         if not torch.cuda.is_available():
@@ -251,6 +257,12 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+    def member_info(self, i: int) -> dict:
+        """Derived plan quantities of member i (bin / sub_nodes as chosen, ...)."""
+        info = B.PhiPlanInfo()
+        B.check(B.lib().phi_batch_member_info(self._handle, int(i), ctypes.byref(info)), self._handle)
+        return _info_dict(info)
 
     def pack(self, grids) -> torch.Tensor:
         """One packed device tensor from a list of n_i x n_i tensors or arrays."""

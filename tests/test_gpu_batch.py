@@ -49,17 +49,19 @@ def member_list(count, seed=1, sizes=None):
     return out
 
 
-def batch_params(members, dtype):
-    return [dict(n=n, h=2 * half / n, n_r=64, n_theta=128, tol=TOLS[dtype]) for n, half, _ in members]
+def batch_params(members, dtype, **extra):
+    return [dict(n=n, h=2 * half / n, n_r=64, n_theta=128, tol=TOLS[dtype], **extra) for n, half, _ in members]
 
 
-def single_solves(ps, members, dtype, adjoint=False, inputs=None):
-    """Each member through a single plan of its own parameters (one plan per size)."""
+def single_solves(ps, members, dtype, adjoint=False, inputs=None, sort=None):
+    """Each member through a single plan of its own parameters (one plan per
+    size); sort[i] = (bin, sub_nodes) of member i when not the defaults."""
     plans, outs = {}, []
     for i, (n, half, rho) in enumerate(members):
-        key = (n, half)
+        extra = {} if sort is None else dict(bin=sort[i][0], sub_nodes=sort[i][1])
+        key = (n, half, tuple(sorted(extra.items())))
         if key not in plans:
-            plans[key] = ps.Plan(n, 2 * half / n, dtype=dtype, n_r=64, n_theta=128, tol=TOLS[dtype])
+            plans[key] = ps.Plan(n, 2 * half / n, dtype=dtype, n_r=64, n_theta=128, tol=TOLS[dtype], **extra)
         src = torch.as_tensor(rho if inputs is None else inputs[i], dtype=dtype, device="cuda")
         fn = plans[key].solve_adjoint if adjoint else plans[key].solve
         outs.append(fn(src.contiguous()))
@@ -115,28 +117,36 @@ def test_batch_adjoint_matches_single_plans_and_oracle(ps, dtype):
 
 def test_full_uneven_batch_fp32(ps):
     """The 256-member batch with sides drawn from {128, 256, 512, 1024} at
-    h = 1/32: every member bitwise equal to its single-plan solve, one member
-    of each side against the oracle."""
+    h = 1/32 and autotuned node sorts: every member bitwise equal to its
+    single-plan solve with the same node sort, four members of each side
+    against the oracle."""
     members = member_list(256, seed=1)
-    print("case: 256-member uneven batch FP32", flush=True)
+    print("case: 256-member uneven batch FP32, autotuned", flush=True)
     dtype = torch.float32
-    bp = ps.BatchPlan(batch_params(members, dtype), dtype=dtype)
+    bp = ps.BatchPlan(batch_params(members, dtype, autotune=True), dtype=dtype)
+    sort = []
+    for i in range(len(members)):
+        info = bp.member_info(i)
+        assert info["n"] == members[i][0]
+        sort.append((info["bin"], info["sub_nodes"]))
+    print("chosen node sorts by side:", sorted(set((m[0],) + s for m, s in zip(members, sort))), flush=True)
     packed = bp.pack([m[2] for m in members])
     out = bp.solve(packed)
     torch.cuda.synchronize()
     got = [g.cpu().numpy() for g in bp.unpack(out)]
     used = [g.double().cpu().numpy() for g in bp.unpack(packed)]
-    single = single_solves(ps, members, dtype, inputs=used)
+    single = single_solves(ps, members, dtype, inputs=used, sort=sort)
     bad = [i for i in range(len(members)) if not np.array_equal(got[i], single[i])]
     assert not bad, f"members {bad[:8]} differ from their single-plan solves"
-    seen = set()
+    checked = {}
     for i, (n, half, _) in enumerate(members):
-        if n in seen:
+        if checked.get(n, 0) >= 4:
             continue
-        seen.add(n)
+        checked[n] = checked.get(n, 0) + 1
         ref = O.phi(used[i], O.SplitParams(n=n, h=2 * half / n, n_r=64, n_theta=128))
         assert rel_linf(got[i], ref) <= 1e-6, f"member {i} N={n}"
-    assert seen == {128, 256, 512, 1024}
+        assert rel_l2(got[i], ref) <= 1e-6, f"member {i} N={n}"
+    assert checked == {128: 4, 256: 4, 512: 4, 1024: 4}
     bp.close()
 
 

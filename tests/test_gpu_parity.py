@@ -273,3 +273,35 @@ def test_graph_replay_matches_eager(ps):
         # unrelated eager work on the same plan between replays
         plan.solve(o)
         torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# node sort parameters and the plan-time autotuner
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype,bin_side,sub_nodes", [
+    (torch.float64, 4, 32), (torch.float64, 16, 64), (torch.float64, 16, 8),
+    (torch.float32, 4, 64), (torch.float32, 16, 32)])
+def test_node_sort_parameters_match_oracle(ps, dtype, bin_side, sub_nodes):
+    print(f"case: 256x256 mixture {dtype} bin={bin_side} sub={sub_nodes}", flush=True)
+    n, half = 256, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(11, 8, 4.0, (0.5, 1.5)))
+    tol = 1e-12 if dtype == torch.float64 else 1e-7
+    plan, rho_used, got = run_solve(ps, rho, n, 2 * half / n, dtype, tol=tol, bin=bin_side, sub_nodes=sub_nodes)
+    assert plan.info["bin"] == bin_side and plan.info["sub_nodes"] == sub_nodes
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=64, n_theta=128))
+    bar = 1e-10 if dtype == torch.float64 else 1e-6
+    assert rel_linf(got, ref) <= bar
+    assert rel_l2(got, ref) <= bar
+
+
+def test_autotuned_plan_matches_oracle(ps):
+    print("case: 512x512 mixture FP32 autotune", flush=True)
+    n, half = 512, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(12, 8, 4.0, (0.5, 1.5)))
+    plan, rho_used, got = run_solve(ps, rho, n, 2 * half / n, torch.float32, tol=1e-7, autotune=True)
+    assert plan.info["bin"] in (4, 8, 16) and plan.info["sub_nodes"] in (32, 64)
+    print(f"autotuned bin={plan.info['bin']} sub_nodes={plan.info['sub_nodes']}", flush=True)
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=64, n_theta=128))
+    assert rel_linf(got, ref) <= 1e-6
+    assert rel_l2(got, ref) <= 1e-6

@@ -115,6 +115,9 @@ def test_describe_small_grid_uses_whole_fine_grid(lib):
     (dict(n=64, h=0.25, tol=1e-16), 3),
     (dict(n=64, h=0.25, pad=3), 2),
     (dict(n=64, h=0.25, pad=1), 1),
+    (dict(n=64, h=0.25, bin=5), 1),                 # bin side not in {4, 8, 16}
+    (dict(n=64, h=0.25, sub_nodes=65), 1),          # more nodes per block than the LDS holds
+    (dict(n=64, h=0.25, sub_nodes=4), 1),
 ])
 def test_invalid_parameters_return_documented_codes(lib, kwargs, status):
     import paper_1409_2014_amd.solver as S
@@ -141,3 +144,27 @@ def test_nonsquare_grid_is_unsupported(lib):
     p.ny = 64
     p.hy = 0.5
     assert lib.phi_describe(ctypes.byref(p), ctypes.byref(info)) == 2
+
+
+@pytest.mark.parametrize("bin_side,sub_nodes", [(4, 32), (8, 64), (16, 64), (16, 8)])
+def test_node_sort_follows_the_bin_of_the_first_tap(lib, bin_side, sub_nodes):
+    """Plan order groups the nodes by the bin of their first kernel tap (bin
+    index non-decreasing), every block holds at most sub_nodes nodes, and the
+    spread tile is bin + w - 1 cells wide."""
+    import paper_1409_2014_amd.solver as S
+    kw = dict(n=256, h=1 / 16, n_r=32, n_theta=64, tol=1e-7, dtype="float32", bin=bin_side,
+              sub_nodes=sub_nodes)
+    d = S.describe(**kw)
+    w, q, lo, nf, h = d["kernel_width"], d["patch"], d["patch_lo"], d["n_fine"], d["h"]
+    assert d["bin"] == bin_side and d["sub_nodes"] == sub_nodes
+    assert d["tile"] == bin_side + w - 1
+    kx, ky, _ = S.host_polar_nodes(**kw)
+    cx = np.ceil(nf * h * kx - 0.5 * w).astype(int) - lo
+    cy = np.ceil(nf * h * ky - 0.5 * w).astype(int) - lo
+    assert cx.min() >= 0 and cx.max() + w <= q and cy.min() >= 0 and cy.max() + w <= q
+    nb = q // bin_side
+    key = (cy // bin_side) * nb + cx // bin_side
+    assert np.all(np.diff(key) >= 0)
+    counts = np.bincount(key)
+    assert d["n_sub"] == int(np.sum((counts + sub_nodes - 1) // sub_nodes))
+    assert d["max_cell_nodes"] == int(counts.max())
