@@ -12,6 +12,8 @@ Modules
                 type-2 / type-1 direct sums, Phi, literal transpose
   closed_forms  exact potentials that pin the oracle (Examples 1 and 2,
                 anisotropic Gaussians, the I2 of a point source)
+  ds_stepper    split-step (Strang) time integration of the DS system with
+                Phi from split_solver, the L4 loss and its reverse-mode gradient
 
 Every function is pinned by a test under tests/ against values printed in the
 paper (Tables 2 and 5), closed forms, invariants, or brute force.
@@ -33,3 +35,4 @@ from .split_solver import (  # noqa: F401
     phi_transpose,
 )
 from . import closed_forms  # noqa: F401
+from . import ds_stepper  # noqa: F401

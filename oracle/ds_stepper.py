@@ -1,0 +1,146 @@
+"""FP64 oracle of the split-step time integration of the DS system -- TEST
+INFRASTRUCTURE ONLY (tests, the smoke check and the benchmark's CPU leg).
+
+The DS system (Sec. 1, eqs. 1-2), in the 2 pi Fourier convention of eq. 5:
+
+    i u_t = -u_xx + alpha u_yy - 2 beta |u|^2 u - 4 beta Phi u,
+    -Laplace(Phi) = d_xx |u|^2,  i.e.  Phi_hat = -kx^2/|k|^2 rho_hat,  rho = |u|^2,
+
+on a periodic box (Sec. 2.3).  The time-splitting method (Sec. 2.3) splits the
+right-hand side into
+
+    A: i v_t = (-d_xx + alpha d_yy) v      exact in Fourier space:
+       v_hat(t + s) = v_hat(t) exp(-i 4 pi^2 (kx^2 - alpha ky^2) s);
+    B: i w_t = (-2 beta |w|^2 - 4 beta Phi) w   |w| is constant in time, so with
+       Phi frozen at the density of the substep's input (Sec. 2.3)
+       w(t + s) = w(t) exp(i s (2 beta rho + 4 beta Phi)).
+
+One step of length tau is the symmetric (Strang) composition
+e^{A tau/2} e^{B tau} e^{A tau/2} (the paper introduces the first-order Lie
+composition and uses a fourth-order one in its experiments; the symmetric
+second-order one is the composition this path integrates).  Phi comes from the
+split quadrature of split_solver.phi, so the oracle stepper is exactly what
+the GPU stepper computes, with direct sums in place of NUFFTs.
+
+Gradients of a real loss J(u) of the complex field u are represented as the
+complex field g = dJ/dRe(u) + i dJ/dIm(u), so that the first-order change is
+dJ = Re sum(conj(g) du).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from .split_solver import SplitParams, phi, phi_transpose
+
+__all__ = [
+    "DSParams",
+    "linear_flow",
+    "nonlinear_phase",
+    "nonlinear_flow",
+    "strang_step",
+    "evolve",
+    "loss_l4",
+    "loss_l4_gradient",
+    "nonlinear_flow_adjoint",
+]
+
+
+@dataclasses.dataclass(frozen=True)
+class DSParams:
+    """Grid (n points of spacing h on [-L, L)^2, L = n h / 2), coefficients
+    alpha, beta of eq. 1, time step tau, polar node counts of the Phi solve."""
+    n: int
+    h: float
+    alpha: float = 1.0
+    beta: float = 1.0
+    tau: float = 1e-3
+    n_r: int = 64
+    n_theta: int = 128
+
+    def split(self) -> SplitParams:
+        return SplitParams(n=self.n, h=self.h, n_r=self.n_r, n_theta=self.n_theta)
+
+
+def _wavenumbers(p: DSParams) -> np.ndarray:
+    """k = m / (n h), m in FFT order: the Fourier modes of the periodic box."""
+    return np.fft.fftfreq(p.n, d=p.h)
+
+
+def linear_flow(u: np.ndarray, p: DSParams, t: float) -> np.ndarray:
+    """Exact flow of i v_t = (-d_xx + alpha d_yy) v over time t (Sec. 2.3,
+    first substep), via the discrete Fourier transform of the periodic box;
+    axis 1 is x, axis 0 is y."""
+    k = _wavenumbers(p)
+    kx2 = (k ** 2)[None, :]
+    ky2 = (k ** 2)[:, None]
+    mult = np.exp(-1j * 4.0 * math.pi ** 2 * (kx2 - p.alpha * ky2) * t)
+    return np.fft.ifft2(np.fft.fft2(u) * mult)
+
+
+def nonlinear_phase(v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
+    """t (2 beta rho + 4 beta Phi[rho]) with rho = |v|^2 (Sec. 2.3, second substep)."""
+    rho = np.abs(v) ** 2
+    return t * (2.0 * p.beta * rho + 4.0 * p.beta * phi(rho, p.split()))
+
+
+def nonlinear_flow(v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
+    """Exact pointwise flow of the second substep over time t."""
+    return v * np.exp(1j * nonlinear_phase(v, p, t))
+
+
+def strang_step(u: np.ndarray, p: DSParams) -> np.ndarray:
+    """e^{A tau/2} e^{B tau} e^{A tau/2} u."""
+    v = linear_flow(u, p, 0.5 * p.tau)
+    w = nonlinear_flow(v, p, p.tau)
+    return linear_flow(w, p, 0.5 * p.tau)
+
+
+def evolve(u0: np.ndarray, p: DSParams, steps: int) -> np.ndarray:
+    u = np.asarray(u0, dtype=np.complex128)
+    for _ in range(steps):
+        u = strang_step(u, p)
+    return u
+
+
+def loss_l4(u: np.ndarray, p: DSParams) -> float:
+    """J(u) = h^2 sum |u|^4 (the quadrature of the L4 norm to the fourth power)."""
+    return float(p.h ** 2 * np.sum(np.abs(u) ** 4))
+
+
+def nonlinear_flow_adjoint(g: np.ndarray, v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
+    """Gradient with respect to the input v of the second substep, given the
+    gradient g with respect to its output w = v e^{i phi(v)},
+    phi = t (2 beta rho + 4 beta A rho), rho = |v|^2, A the Phi operator.
+
+    dw = e^{i phi} dv + i w dphi, so Re sum conj(g) dw = Re sum conj(g e^{-i phi}) dv
+    + sum s dphi with s = Re(conj(g) i w) = -Im(conj(g) w); sum s dphi =
+    sum r drho with r = t (2 beta s + 4 beta A^T s); drho = 2 Re(conj(v) dv), so
+    the gradient is g e^{-i phi} + 2 r v."""
+    ph = nonlinear_phase(v, p, t)
+    w = v * np.exp(1j * ph)
+    s = -np.imag(np.conj(g) * w)
+    r = t * (2.0 * p.beta * s + 4.0 * p.beta * phi_transpose(s, p.split()))
+    return g * np.exp(-1j * ph) + 2.0 * r * v
+
+
+def loss_l4_gradient(u0: np.ndarray, p: DSParams, steps: int) -> tuple[float, np.ndarray]:
+    """J(evolve(u0)) and its gradient with respect to u0, by the reverse pass
+    through every substep with all intermediate states kept.  The linear
+    substep is unitary with a unit-modulus Fourier multiplier, so its adjoint
+    is the same flow backwards in time."""
+    u = np.asarray(u0, dtype=np.complex128)
+    vs = []
+    for _ in range(steps):
+        v = linear_flow(u, p, 0.5 * p.tau)
+        vs.append(v)
+        u = linear_flow(nonlinear_flow(v, p, p.tau), p, 0.5 * p.tau)
+    loss = loss_l4(u, p)
+    g = 4.0 * p.h ** 2 * np.abs(u) ** 2 * u        # dJ/dRe u + i dJ/dIm u
+    for v in reversed(vs):
+        g = linear_flow(g, p, -0.5 * p.tau)
+        g = nonlinear_flow_adjoint(g, v, p, p.tau)
+        g = linear_flow(g, p, -0.5 * p.tau)
+    return loss, g

@@ -1,0 +1,173 @@
+"""Pins of the oracle stepper (CPU only): the linear substep against the exact
+evolution of a Gaussian, the nonlinear substep against the closed-form
+potential of an isotropic Gaussian, mass conservation, second-order
+convergence of the symmetric composition, and the reverse-mode gradient
+against central finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed_forms as C
+from oracle import ds_stepper as D
+import workloads as W
+
+
+def gaussian_free_flow(x, y, t, s1, s2, alpha):
+    """Exact solution of i v_t = -v_xx + alpha v_yy from exp(-x^2/s1 - y^2/s2) on
+    the whole plane: v_t = i v_xx + (-i alpha) v_yy is a heat equation with
+    complex diffusivities D_x = i, D_y = -i alpha, whose Gaussian solution is
+    sqrt(s / (s + 4 D t)) exp(-x^2 / (s + 4 D t)) in each variable."""
+    ax = s1 + 4j * t
+    ay = s2 - 4j * alpha * t
+    return np.sqrt(s1 / ax) * np.exp(-x ** 2 / ax) * np.sqrt(s2 / ay) * np.exp(-y ** 2 / ay)
+
+
+@pytest.mark.parametrize("alpha", [1.0, -1.0])
+def test_linear_flow_matches_exact_gaussian_evolution(alpha):
+    n, half = 128, 16.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=alpha)
+    x, y, _ = W.grid_2d(n, half)
+    u0 = np.exp(-x ** 2 / 1.0 - y ** 2 / 2.0).astype(np.complex128)
+    t = 0.3
+    got = D.linear_flow(u0, p, t)
+    ref = gaussian_free_flow(x, y, t, 1.0, 2.0, alpha)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    # the flow backwards in time undoes it
+    assert np.max(np.abs(D.linear_flow(got, p, -t) - u0)) < 1e-13
+
+
+def test_nonlinear_phase_uses_the_potential_of_the_density():
+    """v = exp(-r^2 / 2) has rho = exp(-r^2), whose Phi is known in closed form
+    (Sec. 3.1 Example 1 family); the phase is t (2 beta rho + 4 beta Phi)."""
+    n, half = 64, 8.0
+    p = D.DSParams(n=n, h=2 * half / n, beta=0.7, n_r=32, n_theta=64)
+    x, y, _ = W.grid_2d(n, half)
+    v = np.exp(-(x ** 2 + y ** 2) / 2.0).astype(np.complex128)
+    t = 0.05
+    w = D.nonlinear_flow(v, p, t)
+    rho = np.exp(-(x ** 2 + y ** 2))
+    expect = v * np.exp(1j * t * (2 * 0.7 * rho + 4 * 0.7 * C.phi_isotropic_gaussian(x, y)))
+    assert np.max(np.abs(w - expect)) < 1e-12
+    assert np.max(np.abs(np.abs(w) - np.abs(v))) < 1e-15
+
+
+def test_steps_conserve_mass():
+    n, half = 32, 4.0
+    p = D.DSParams(n=n, h=2 * half / n, tau=1e-2, n_r=16, n_theta=32)
+    x, y, _ = W.grid_2d(n, half)
+    u = np.exp(-(x ** 2 + 2 * y ** 2)).astype(np.complex128) * np.exp(0.3j * x)
+    m0 = np.sum(np.abs(u) ** 2)
+    for _ in range(5):
+        u = D.strang_step(u, p)
+        assert abs(np.sum(np.abs(u) ** 2) - m0) < 1e-13 * m0
+
+
+def test_symmetric_composition_is_second_order():
+    n, half = 32, 4.0
+    x, y, _ = W.grid_2d(n, half)
+    u0 = (np.exp(-(x ** 2 + 2 * y ** 2)) * np.exp(0.5j * x)).astype(np.complex128)
+    base = dict(n=n, h=2 * half / n, alpha=1.0, beta=2.0, n_r=16, n_theta=32)
+    t_end = 0.08
+    ref = D.evolve(u0, D.DSParams(tau=t_end / 64, **base), 64)
+    errs = [np.max(np.abs(D.evolve(u0, D.DSParams(tau=t_end / m, **base), m) - ref)) for m in (4, 8)]
+    ratio = errs[0] / errs[1]
+    assert 3.5 < ratio < 4.5, (errs, ratio)
+
+
+def test_reverse_mode_gradient_matches_central_differences():
+    n, half = 16, 4.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.5, tau=2e-2, n_r=12, n_theta=24)
+    x, y, _ = W.grid_2d(n, half)
+    u0 = (np.exp(-(x ** 2 + 2 * y ** 2)) * np.exp(0.4j * y)).astype(np.complex128)
+    steps = 3
+    loss, g = D.loss_l4_gradient(u0, p, steps)
+    assert abs(loss - D.loss_l4(D.evolve(u0, p, steps), p)) < 1e-14 * loss
+    rng = np.random.default_rng(7)
+    eps = 1e-5
+    for _ in range(4):
+        d = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        fd = (D.loss_l4(D.evolve(u0 + eps * d, p, steps), p)
+              - D.loss_l4(D.evolve(u0 - eps * d, p, steps), p)) / (2 * eps)
+        dot = float(np.sum(np.real(np.conj(g) * d)))
+        assert abs(fd - dot) <= 1e-7 * abs(dot), (fd, dot)
+
+
+def test_linear_part_of_a_step_is_the_exact_flow():
+    """With beta = 0 the nonlinear substep is the identity and `steps` Strang
+    steps must reproduce the exact linear evolution over steps * tau."""
+    n, half = 64, 8.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=0.0, tau=0.05, n_r=16, n_theta=32)
+    x, y, _ = W.grid_2d(n, half)
+    u0 = np.exp(-x ** 2 - y ** 2 / 1.5).astype(np.complex128)
+    got = D.evolve(u0, p, 4)
+    assert np.max(np.abs(got - gaussian_free_flow(x, y, 0.2, 1.0, 1.5, 1.0))) < 1e-12
+
+
+# ---- the pins above must catch plausible mistakes in the stepper -------------
+
+def _ds_pins_hold():
+    checks = []
+    for fn in (lambda: test_linear_flow_matches_exact_gaussian_evolution(1.0),
+               lambda: test_linear_flow_matches_exact_gaussian_evolution(-1.0),
+               test_nonlinear_phase_uses_the_potential_of_the_density,
+               test_symmetric_composition_is_second_order,
+               test_linear_part_of_a_step_is_the_exact_flow,
+               test_reverse_mode_gradient_matches_central_differences):
+        try:
+            fn()
+            checks.append(True)
+        except AssertionError:
+            checks.append(False)
+    return all(checks)
+
+
+def _alpha_sign(monkeypatch):
+    orig = D.linear_flow
+    monkeypatch.setattr(D, "linear_flow", lambda u, p, t: orig(u, D.DSParams(**{**p.__dict__, "alpha": -p.alpha}), t))
+
+
+def _no_two_pi(monkeypatch):
+    def flow(u, p, t):
+        k = np.fft.fftfreq(p.n, d=p.h)
+        mult = np.exp(-1j * ((k ** 2)[None, :] - p.alpha * (k ** 2)[:, None]) * t)
+        return np.fft.ifft2(np.fft.fft2(u) * mult)
+    monkeypatch.setattr(D, "linear_flow", flow)
+
+
+def _half_local_term(monkeypatch):
+    orig = D.nonlinear_phase
+    monkeypatch.setattr(D, "nonlinear_phase",
+                        lambda v, p, t: orig(v, p, t) - t * p.beta * np.abs(v) ** 2)
+
+
+def _lie_composition(monkeypatch):
+    monkeypatch.setattr(D, "strang_step", lambda u, p: D.nonlinear_flow(D.linear_flow(u, p, p.tau), p, p.tau))
+
+
+def _full_linear_substeps(monkeypatch):
+    monkeypatch.setattr(D, "strang_step", lambda u, p: D.linear_flow(
+        D.nonlinear_flow(D.linear_flow(u, p, p.tau), p, p.tau), p, p.tau))
+
+
+def _adj_local_only(g, v, p, t):
+    """The adjoint of the nonlinear substep with the potential's A^T term dropped."""
+    ph = D.nonlinear_phase(v, p, t)
+    w = v * np.exp(1j * ph)
+    s = -np.imag(np.conj(g) * w)
+    return g * np.exp(-1j * ph) + 2.0 * (t * 2.0 * p.beta * s) * v
+
+
+def _adjoint_without_potential_term(monkeypatch):
+    monkeypatch.setattr(D, "nonlinear_flow_adjoint", _adj_local_only)
+
+
+def test_unmodified_stepper_passes_the_pins():
+    assert _ds_pins_hold()
+
+
+@pytest.mark.parametrize("mutation", [_alpha_sign, _no_two_pi, _half_local_term, _lie_composition,
+                                      _full_linear_substeps, _adjoint_without_potential_term])
+def test_planted_stepper_mistake_is_caught(monkeypatch, mutation):
+    mutation(monkeypatch)
+    assert not _ds_pins_hold()
