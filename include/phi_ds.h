@@ -1,0 +1,77 @@
+/* Split-step time integration of the DS system on one GPU: the consumer of the
+ * potential solve (include/phi_solve.h).
+ *
+ *   i u_t = -u_xx + alpha u_yy - 2 beta |u|^2 u - 4 beta Phi u,
+ *   Phi_hat = -kx^2/|k|^2 rho_hat,  rho = |u|^2             (Sec. 1, eqs. 1-2)
+ *
+ * on the periodic box of the solve's grid (Sec. 2.3).  One step of length tau is
+ * the symmetric composition e^{A tau/2} e^{B tau} e^{A tau/2} of
+ *   A: i v_t = (-d_xx + alpha d_yy) v, exact in Fourier space:
+ *      v_hat <- v_hat e^{-i 4 pi^2 (kx^2 - alpha ky^2) tau/2}, k = m/(N h);
+ *   B: w = v e^{i tau (2 beta |v|^2 + 4 beta Phi[|v|^2])}, pointwise (Sec. 2.3),
+ *      Phi from one phi_solve of the stepper's own plan.
+ * Consecutive half steps of A are applied as one full step.
+ *
+ * Fields are N x N complex arrays in device memory, row-major [y][x] with x
+ * contiguous, interleaved (re, im) in the data precision of the solve
+ * parameters (F32 -> complex64, F64 -> complex128).  Gradients of a real loss
+ * J are fields g = dJ/dRe(u) + i dJ/dIm(u).  All calls only enqueue work on
+ * `stream` (stream-ordered, asynchronous); one call in flight per stepper.
+ * Errors are reported by status; the message is phi_last_error(NULL). */
+#ifndef PHI_DS_H
+#define PHI_DS_H
+
+#include <stdint.h>
+
+#include "phi_solve.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct phi_ds_s* phi_ds_t;
+
+/* Creates a stepper on the current device: a potential-solve plan for *solve
+ * (grid side 16..4096, spacing, polar nodes, tolerance, dtype, flags), the
+ * Fourier multipliers of the linear substep for tau/2 and tau (FP64, rounded to
+ * the data precision) and a workspace of 2 complex and 2 real N x N fields.
+ * alpha, beta: coefficients of eq. 1; tau: time step (all finite). */
+phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, double tau, void* stream,
+                         phi_ds_t* out);
+
+/* Frees the stepper and its plan after synchronizing its device.  NULL is a no-op. */
+phi_status phi_ds_destroy(phi_ds_t ds);
+
+/* The potential-solve plan the stepper owns (valid until phi_ds_destroy). */
+phi_status phi_ds_plan(phi_ds_t ds, phi_plan_t* plan);
+
+/* Advances u in place by `steps` (>= 0) steps.  v_store (may be NULL) receives
+ * the input v_i of the i-th nonlinear substep at element offset i N^2 (complex
+ * fields), phi_store (may be NULL) the potential Phi_i of that substep at
+ * offset i N^2 (real fields): what phi_ds_backward needs to run the reverse
+ * pass of the same steps.  One potential solve per step. */
+phi_status phi_ds_forward(phi_ds_t ds, void* u, int32_t steps, void* v_store, void* phi_store, void* stream);
+
+/* Reverse pass of `steps` steps: g holds the gradient with respect to the
+ * state after the steps and is overwritten with the gradient with respect to
+ * the state before them.  v_store and phi_store are the stores a phi_ds_forward
+ * of the same steps from that earlier state wrote (both required).  Each step
+ * takes one transposed potential solve (phi_solve_adjoint): with
+ * w = v e^{i phi}, phi = tau (2 beta |v|^2 + 4 beta Phi),
+ *   g_v = g_w e^{-i phi} + 2 tau (2 beta s + 4 beta A^T s) v,  s = -Im(conj(g_w) w),
+ * and the linear substeps run backwards in time (their adjoints). */
+phi_status phi_ds_backward(phi_ds_t ds, void* g, int32_t steps, const void* v_store, const void* phi_store,
+                           void* stream);
+
+/* out[0] = h^2 sum |u|^2 (mass), out[1] = h^2 sum |u|^4; out: 2 doubles in device
+ * memory, FP64 sums in a fixed order. */
+phi_status phi_ds_moments(phi_ds_t ds, const void* u, double* out, void* stream);
+
+/* g = 4 h^2 |u|^2 u: the gradient of J = h^2 sum |u|^4. */
+phi_status phi_ds_loss_grad(phi_ds_t ds, const void* u, void* g, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHI_DS_H */

@@ -19,4 +19,5 @@ from .solver import (  # noqa: F401
     host_es_transform,
     host_polar_nodes,
 )
+from .stepper import DSStepper, DSEvolve, ds_evolve  # noqa: F401
 from ._binding import PhiError, LIB_PATH  # noqa: F401

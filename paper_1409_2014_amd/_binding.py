@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/phi_solve.h (argument marshalling only)."""
+"""ctypes declarations of the C ABI in include/phi_solve.h and include/phi_ds.h
+(argument marshalling only)."""
 from __future__ import annotations
 
 import ctypes
@@ -84,6 +85,14 @@ def _declare(lib):
         "phi_host_es_kernel": (st, [ctypes.c_int32, _DP, ctypes.c_double, _DP]),
         "phi_host_es_transform": (st, [ctypes.c_int32, _DP, ctypes.c_double, _DP]),
         "phi_host_polar_nodes": (st, [ctypes.POINTER(PhiParams), _DP, _DP, _DP]),
+        "phi_ds_create": (st, [ctypes.POINTER(PhiParams), ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               _P, ctypes.POINTER(_P)]),
+        "phi_ds_destroy": (st, [_P]),
+        "phi_ds_plan": (st, [_P, ctypes.POINTER(_P)]),
+        "phi_ds_forward": (st, [_P, _P, ctypes.c_int32, _P, _P, _P]),
+        "phi_ds_backward": (st, [_P, _P, ctypes.c_int32, _P, _P, _P]),
+        "phi_ds_moments": (st, [_P, _P, _P, _P]),
+        "phi_ds_loss_grad": (st, [_P, _P, _P, _P]),
         "phi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "phi_last_error": (ctypes.c_char_p, [_P]),
     }
@@ -122,4 +131,6 @@ def exported_symbols():
         "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",
         "phi_status_string", "phi_last_error",
+        "phi_ds_create", "phi_ds_destroy", "phi_ds_plan", "phi_ds_forward", "phi_ds_backward",
+        "phi_ds_moments", "phi_ds_loss_grad",
     ]

@@ -46,8 +46,9 @@ def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     incs = [f"-I{INCLUDE}", f"-I{CSRC}", f"-I{ROCM}/include"]
     jobs = []
-    for src, compiler in (("plan_host.cpp", "gxx"), ("phi_api.cpp", "gxx"), ("solver_kernels.hip", "hipcc"),
-                          ("batch_kernels.hip", "hipcc")):
+    for src, compiler in (("plan_host.cpp", "gxx"), ("phi_api.cpp", "gxx"), ("ds_api.cpp", "gxx"),
+                          ("solver_kernels.hip", "hipcc"), ("batch_kernels.hip", "hipcc"),
+                          ("ds_kernels.hip", "hipcc")):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         path = os.path.join(CSRC, src)
         if compiler == "gxx":

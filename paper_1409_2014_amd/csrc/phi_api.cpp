@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "api_errors.hpp"
 #include "phi_solve.h"
 #include "plan_host.hpp"
 #include "solver_kernels.hpp"
@@ -154,7 +155,13 @@ hipError_t upload_tables(const phi::HostPlan& hp, const TableParts& t, char* bas
     if (e == hipSuccess) e = up(t.cst, hp.contrib_start.data());
     if (e == hipSuccess) e = up(t.con, hp.contrib.data());
     if (e == hipSuccess) e = up(t.taps, narrow(hp.taps));
-    if (e == hipSuccess) e = up(t.twr, narrow(hp.twr));
+    const void* twr = hp.twr.data();
+    if (f32) {
+        keep.emplace_back();
+        phi::round_unit_pairs(hp.twr, &keep.back());
+        twr = keep.back().data();
+    }
+    if (e == hipSuccess) e = up(t.twr, twr);
     return e;
 }
 
@@ -378,6 +385,11 @@ void push_items(std::vector<phi::WorkItem>* v, int member, int kind, int count, 
 }
 
 }  // namespace
+
+phi_status phi::thread_error(phi_status st, const std::string& msg) {
+    g_thread_error = msg;
+    return st;
+}
 
 extern "C" {
 

@@ -146,6 +146,33 @@ void unit_root(long long m, long long n, double* re, double* im) {
     *im = -sr;
 }
 
+void round_unit_pairs(const std::vector<double>& in, std::vector<float>* out) {
+    out->resize(in.size());
+    for (size_t i = 0; i + 1 < in.size(); i += 2) {
+        const double re = in[i], im = in[i + 1];
+        const float r0 = static_cast<float>(re), i0 = static_cast<float>(im);
+        const float rc[3] = {std::nextafter(r0, -2.0f), r0, std::nextafter(r0, 2.0f)};
+        const float ic[3] = {std::nextafter(i0, -2.0f), i0, std::nextafter(i0, 2.0f)};
+        float br = r0, bi = i0;
+        double bm = std::fabs(static_cast<double>(r0) * r0 + static_cast<double>(i0) * i0 - 1.0);
+        double bd = 0.0;
+        for (float a : rc) {
+            for (float b : ic) {
+                const double m = std::fabs(static_cast<double>(a) * a + static_cast<double>(b) * b - 1.0);
+                const double d = std::fabs(a - re) + std::fabs(b - im);
+                if (m < bm || (m == bm && d < bd)) {
+                    bm = m;
+                    bd = d;
+                    br = a;
+                    bi = b;
+                }
+            }
+        }
+        (*out)[i] = br;
+        (*out)[i + 1] = bi;
+    }
+}
+
 void fft_stage_twiddles(int log, std::vector<double>* out) {
     const int s16 = log / 4, rem = log % 4, nst = s16 + (rem ? 1 : 0);
     const long long f = 1LL << log;

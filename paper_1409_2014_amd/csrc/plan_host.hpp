@@ -69,6 +69,11 @@ void unit_root(long long m, long long n, double* re, double* im);
 // fft_reg.hpp): stage s >= 1 of radix R and span p holds W_{pR}^{t k},
 // t = 1..R-1, k = 0..p-1, at (t-1) p + k; stages back to back.
 void fft_stage_twiddles(int log, std::vector<double>* out);
+// FP32 copies of unit-modulus (re, im) pairs (twiddles, phase multipliers):
+// each pair is taken among the floats within one ulp of its components such
+// that re^2 + im^2 is closest to 1 (ties: the nearest pair), so rounding does
+// not bias the modulus of long products of such factors.
+void round_unit_pairs(const std::vector<double>& in, std::vector<float>* out);
 double es_kernel(double z, double beta);
 // int_{-1}^{1} phi(z) cos(omega z) dz
 double es_transform(double omega, double beta);

@@ -24,9 +24,13 @@ def lib():
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "phi_solve.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(phi_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for header in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if header.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", header)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(phi_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function(lib):
