@@ -13,10 +13,11 @@ steps; the same line carries the FP64 rate, the FP32/FP64 ratio, the rate of
 forward + transposed solve pairs, the relative errors of both data paths
 against the FP64 oracle, the dominant kernel's HBM roofline figure (HIP events
 recorded around every kernel on its launch stream) and the oracle's own rate
-on the host cores.  Two further legs (skipped with --no-extra-legs): a batch
+on the host cores.  Further legs (skipped with --no-extra-legs): a batch
 of 256 densities with sides drawn from {128, 256, 512, 1024} at h = 1/32
-(seed 1; autotuned node sorts), and forward + transposed solve pairs at
-1024^2 over [-16, 16)^2 (mixture seed 2).
+(seed 1; autotuned node sorts), forward + transposed solve pairs at
+1024^2 over [-16, 16)^2 (mixture seed 2), and 500 split steps of the DS system
+at 2048^2 with the checkpointed gradient of the final L4 norm.
 """
 from __future__ import annotations
 
@@ -214,6 +215,47 @@ def adjoint_leg(args, torch, ps, W) -> dict:
     return res
 
 
+def stepper_leg(args, torch, ps, W) -> dict:
+    """500 Strang steps of the DS system (alpha = beta = 1, tau = 1e-3) on a
+    2048^2 grid over [-32, 32)^2 from u0 = exp(-(x^2 + 2 y^2)), one potential
+    solve per step; then the gradient of h^2 sum |u(T)|^4 with respect to u0 by
+    the reverse pass with a checkpoint every 50 steps.  Both data paths."""
+    n, half, steps, every = 2048, 32.0, 500, 50
+    x, y, h = W.grid_2d(n, half)
+    u0 = np.exp(-(x ** 2 + 2 * y ** 2))
+    res = {}
+    for name, dt, cdt, tol in (("c64", torch.float32, torch.complex64, TOL32),
+                               ("c128", torch.float64, torch.complex128, TOL64)):
+        print(f"[bench] stepper {name}: {steps} steps, gradient with checkpoints every {every}",
+              file=sys.stderr, flush=True)
+        st = ps.DSStepper(n, h, alpha=1.0, beta=1.0, tau=1e-3, dtype=dt, n_r=N_R, n_theta=N_THETA, tol=tol)
+        u = torch.as_tensor(u0, dtype=cdt, device="cuda").contiguous()
+        w = u.clone()
+        st.forward(w, 2)
+        st.loss_and_grad(u, 4, 2)
+        torch.cuda.synchronize()
+        w = u.clone()
+        t0 = time.perf_counter()
+        st.forward(w, steps)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        m = st.moments(u).cpu().numpy()
+        m_end = st.moments(w).cpu().numpy()
+        t0 = time.perf_counter()
+        loss, g, counts = st.loss_and_grad(u, steps, every)
+        torch.cuda.synchronize()
+        t_fb = time.perf_counter() - t0
+        solves = counts["forward_solves"] + counts["recomputed_solves"] + counts["adjoint_solves"]
+        res[name] = {"forward_ms": round(1e3 * t_fwd, 2), "steps_per_s": round(steps / t_fwd, 1),
+                     "fwd_bwd_ms": round(1e3 * t_fb, 2), "counts": counts,
+                     "fwd_bwd_solves_per_s": round(solves / t_fb, 1),
+                     "mass_drift": float(abs(m_end[0] - m[0]) / m[0]), "loss": float(loss),
+                     "grad_norm": float(torch.linalg.vector_norm(g))}
+        st.close()
+        del w, g
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,8 +263,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (and the error figures that need it)")
-    ap.add_argument("--no-extra-legs", action="store_true",
-                    help="time only the 2048^2 single solve (skip the batch and 1024^2 adjoint legs)")
+    ap.add_argument("--legs", default="batch,adjoint,stepper",
+                    help="comma-separated further legs to run after the 2048^2 single solve "
+                         "(batch, adjoint, stepper; empty for none)")
+    ap.add_argument("--no-extra-legs", action="store_true", help="same as --legs ''")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="replay each solve from a captured HIP graph (default) or launch it eagerly")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -340,10 +384,18 @@ def main() -> int:
     }
     plan32.close()
     plan64.close()
-    if not args.no_extra_legs:
+    legs = set() if args.no_extra_legs else {x.strip() for x in args.legs.split(",") if x.strip()}
+    unknown = legs - {"batch", "adjoint", "stepper"}
+    if unknown:
+        print(f"unknown legs {sorted(unknown)}", file=sys.stderr)
+        return 2
+    if "batch" in legs:
         result["batch_uneven_f32"] = batch_leg(args, torch, ps, W)
+    if "adjoint" in legs:
         print("[bench] adjoint pairs at 1024^2", file=sys.stderr, flush=True)
         result["adjoint_pairs_1024"] = adjoint_leg(args, torch, ps, W)
+    if "stepper" in legs:
+        result["ds_stepper_2048"] = stepper_leg(args, torch, ps, W)
     if not args.no_cpu_baseline:
         print("[bench] oracle leg on the host cores", file=sys.stderr, flush=True)
         ref, base = cpu_baseline(rho_used)
