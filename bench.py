@@ -37,6 +37,21 @@ if ROOT not in sys.path:
 METRIC = "Φ solves/s at 2048² grid: FP32 vs FP64 at rel-err 1e-6; fwd+bwd solves/s"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel (FP32 cols_highfreq, 2048^2) from two rocprofv3
+# --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over the
+# dispatches of a short eager run), each scaled by what the same counter reads for
+# a plain 256 MiB device copy in the same run.  Valid only for the kernel sources
+# whose SHA-256 is recorded: after any change to them `traffic` is reported as null
+# until the counters are taken again.
+TRAFFIC_RECORD = {
+    "kernel": "cols_highfreq",
+    "fetch_kib": 16754.09, "write_kib": 32784.0,
+    "copy_fetch_kib": 131088.375, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
+                "solver_kernels.hpp"),
+    "sha256": "5653f3ef58bd5eea1bda2bb3a17721524038e8b1bd2d207def26ef0bdb86ee2a",
+}
+
 N = 2048
 HALF = 16.0
 N_R, N_THETA = 64, 128
@@ -68,6 +83,24 @@ def solve_alg_bytes(n: int, real_bytes: int) -> int:
     half spectrum of the padded transform (N (n_f/2 + 1) complex values) that a
     row-column realisation cannot keep on chip."""
     return 2 * n * n * real_bytes + 4 * n * (n + 1) * 2 * real_bytes
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from TRAFFIC_RECORD, or None when it covers
+    another kernel or the kernel sources changed since the counters were taken."""
+    import hashlib
+    rec = TRAFFIC_RECORD
+    if kernel != rec["kernel"]:
+        return None
+    h = hashlib.sha256()
+    for name in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_1409_2014_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sha256"]:
+        return None
+    fetch = rec["fetch_kib"] * rec["copy_true_kib"] / rec["copy_fetch_kib"]
+    write = rec["write_kib"] * rec["copy_true_kib"] / rec["copy_write_kib"]
+    return round((fetch + write) * 1024)
 
 
 def timed_rate(fn, steps: int, torch) -> float:
@@ -380,7 +413,7 @@ def main() -> int:
                       "n_sub": plan32.info["n_sub"]},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": recorded_traffic(dominant)},
     }
     plan32.close()
     plan64.close()

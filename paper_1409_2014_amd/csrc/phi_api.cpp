@@ -117,11 +117,16 @@ TableParts layout_tables(const phi::HostPlan& hp, size_t es, Layout& L) {
     return t;
 }
 
+// Column stride of the column-major spectra: N plus 64 elements, so that the
+// rows of one block, written across all columns at once, do not fall into a
+// few cache sets (a power-of-two stride maps every column to the same sets).
+size_t column_stride(const phi::HostPlan& hp) { return static_cast<size_t>(hp.n) + 64; }
+
 WorkParts layout_work(const phi::HostPlan& hp, size_t es, Layout& L) {
     WorkParts w;
-    const size_t n = hp.n, q = hp.patch, m = hp.n_nodes;
-    w.xt = L.take((n + 1) * n * 2 * es);
-    w.tt = L.take(q * n * 2 * es);
+    const size_t n = hp.n, q = hp.patch, m = hp.n_nodes, cs = column_stride(hp);
+    w.xt = L.take((n + 1) * cs * 2 * es);
+    w.tt = L.take(q * cs * 2 * es);
     w.win = L.take(q * q * 2 * es);
     w.pts = L.take(m * 2 * es);
     w.tiles = L.take(static_cast<size_t>(hp.n_sub) * hp.tile * hp.tile * 2 * es);
@@ -165,7 +170,7 @@ hipError_t upload_tables(const phi::HostPlan& hp, const TableParts& t, char* bas
     return e;
 }
 
-void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, int n_cu, char* base, const TableParts& t,
+void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableParts& t,
               const WorkParts& w, phi::DevPlan* d) {
     const double f = hp.n_fine;
     d->dtype = dtype;
@@ -177,7 +182,7 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, int n_cu, char* base, co
     d->width = hp.width;
     d->n_nodes = hp.n_nodes;
     d->component_y = hp.component_y;
-    d->n_cu = n_cu;
+    d->col_stride = static_cast<int>(column_stride(hp));
     d->h2 = hp.h * hp.h;
     d->inv_f2 = 1.0 / (f * f);
     d->deconv = reinterpret_cast<const double*>(base + t.deconv.off);
@@ -201,12 +206,6 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, int n_cu, char* base, co
     d->pts = base + w.pts.off;
     d->tiles = base + w.tiles.off;
     d->u = base + w.u.off;
-}
-
-int device_cu_count(int device) {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n < 1) n = 1;
-    return n;
 }
 
 phi_status create_streams(phi_plan_t plan) {
@@ -273,7 +272,7 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
         release(plan.get());
         return st;
     }
-    fill_dev(hp, p->dtype, device_cu_count(plan->device), base, tp, wp, &plan->dev);
+    fill_dev(hp, p->dtype, base, tp, wp, &plan->dev);
     *out = plan.release();
     return PHI_OK;
 }
@@ -576,10 +575,9 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         std::vector<std::vector<float>> keep;
         for (size_t k = 0; k < plan->sets.size() && e == hipSuccess; ++k)
             e = upload_tables(plan->sets[k], tparts[k], base, f32, s, keep);
-        const int n_cu = device_cu_count(plan->device);
         std::vector<phi::DevPlan> devs(count);
         for (int i = 0; i < count; ++i)
-            fill_dev(plan->sets[plan->member_set[i]], dtype, n_cu, base, tparts[plan->member_set[i]], wparts[i],
+            fill_dev(plan->sets[plan->member_set[i]], dtype, base, tparts[plan->member_set[i]], wparts[i],
                      &devs[i]);
         auto up = [&](const Part& pt, const void* src) -> hipError_t {
             if (pt.bytes == 0) return hipSuccess;

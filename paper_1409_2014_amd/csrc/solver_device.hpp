@@ -104,7 +104,7 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
         const cpx<R> a = l[lds_pad(m)];
         const cpx<R> b = l[lds_pad((F - m) & (F - 1))];
         // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2
-        if (idx < ITEMS) xt[static_cast<size_t>(m) * N + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+        if (idx < ITEMS) xt[static_cast<size_t>(m) * P.col_stride + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
     }
     cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
     for (int idx = threadIdx.x; idx < P.patch * G; idx += NT * G) {
@@ -115,7 +115,7 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
         const cpx<R> a = l[lds_pad(lf & (F - 1))];
         const cpx<R> b = l[lds_pad((-lf) & (F - 1))];
         // transform of the imaginary part: (Z[l] - conj Z[-l]) / (2i)
-        tt[static_cast<size_t>(i) * N + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
+        tt[static_cast<size_t>(i) * P.col_stride + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
     }
 }
 
@@ -158,7 +158,7 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
     const int m1 = m1_base + g;   // 0..N (+ idle lanes of the last block)
     const bool active = m1 <= N;
     // idle lanes load column N and never store: no branch around the loads
-    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : N) * N;
+    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : N) * P.col_stride;
     // (b, 1 - e^{-b}) of the 16 rows this thread multiplies; in FP32 fetched
     // before the transform so that their latency is hidden by it (in FP64 the
     // registers are needed by the transform itself)
@@ -222,7 +222,7 @@ __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, c
     const int q = P.patch;
     const int i1 = i1_base + g;
     const bool active = i1 < q;
-    const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(active ? i1 : 0) * N;
+    const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(active ? i1 : 0) * P.col_stride;
     const cpx<R> zero = {R(0), R(0)};
     cpx<R> v[16];
 #pragma unroll
@@ -511,7 +511,7 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
         const int m = idc / G;
         const int r = row0 + gg;
         cpx<R> x = {R(0), R(0)};
-        if constexpr (USE_I1) x = xt[static_cast<size_t>(m) * N + r];
+        if constexpr (USE_I1) x = xt[static_cast<size_t>(m) * P.col_stride + r];
         cpx<R> hh = {R(0), R(0)};
         if constexpr (USE_I2) {
             const int ia = posmod_dev(m - lo, F);

@@ -14,7 +14,7 @@ struct DevPlan {
     phi_dtype dtype;
     int n, n_fine, log_fine;
     int patch, patch_lo, width, n_nodes, component_y;
-    int n_cu;               // compute units of the plan's device (persistent grids)
+    int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
     double h2, inv_f2;
     // FP64 tables
     const double* deconv;   // [N] 2 pi / (n_fine psi_hat(n'))
@@ -32,8 +32,8 @@ struct DevPlan {
     const void* twr;        // register-FFT stage twiddles, data precision, twr_count complex
     int twr_count;
     // workspace, element type = data precision
-    void* xt;       // (N+1) x N complex: I1 half spectrum, column-major
-    void* tt;       // Q x N complex: type-2 row window, column-major
+    void* xt;       // (N+1) columns of N complex: I1 half spectrum, column-major, col_stride apart
+    void* tt;       // Q columns of N complex: type-2 row window, column-major, col_stride apart
     void* win;      // Q x Q complex: type-2 fine-grid window, [y][x]
     void* pts;      // M complex: a_j = q_j rho_hat_j
     void* tiles;    // n_sub x E x E complex: each subproblem's spread tile
