@@ -144,6 +144,14 @@ def cpu_baseline(rho_used: np.ndarray):
                            f"{len(os.sched_getaffinity(0))} host cores visible)"}
 
 
+def time_split(kernels: dict) -> dict:
+    fft = sum(kernels[k]["avg_us"] for k in ("rows_forward", "cols_highfreq", "rows_inverse") if k in kernels)
+    node = sum(kernels[k]["avg_us"] for k in ("cols_type2", "nodes", "cols_type1") if k in kernels)
+    return {"fft_side_us": round(fft, 2), "node_side_us": round(node, 2),
+            "node_side_fraction": round(node / (fft + node), 3) if fft + node > 0 else None,
+            "node_side_concurrent": True}
+
+
 def capture_graph(fn, torch):
     """One captured graph per step kind; a timed step is one replay (the graph
     holds exactly the kernels of one call of fn)."""
@@ -409,6 +417,9 @@ def main() -> int:
         "solve_roofline_frac": {"f32": round(alg32 * k / t32 / 1e9 / HBM_PEAK_GBS, 4),
                                 "f64": round(alg64 * k / t64 / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_f32": kernels,
+        # the paper's split of solve time (Sec. 3): FFT-side kernels (I1, with the type-2
+        # row transform and the recombination fused in) against the node-side kernels
+        "time_split_f32": time_split(kernels),
         "node_sort": {"bin": plan32.info["bin"], "sub_nodes": plan32.info["sub_nodes"],
                       "n_sub": plan32.info["n_sub"]},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
