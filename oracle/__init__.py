@@ -14,9 +14,11 @@ Modules
                 anisotropic Gaussians, the I2 of a point source)
   ds_stepper    split-step (Strang) time integration of the DS system with
                 Phi from split_solver, the L4 loss and its reverse-mode gradient
+  periodic      the standard periodic FFT potential solver the paper compares
+                against (Tables 1 and 4)
 
 Every function is pinned by a test under tests/ against values printed in the
-paper (Tables 2 and 5), closed forms, invariants, or brute force.
+paper (Tables 1, 2, 4 and 5), closed forms, invariants, or brute force.
 """
 from .split_solver import (  # noqa: F401
     SplitParams,
@@ -36,3 +38,4 @@ from .split_solver import (  # noqa: F401
 )
 from . import closed_forms  # noqa: F401
 from . import ds_stepper  # noqa: F401
+from . import periodic  # noqa: F401
