@@ -16,8 +16,9 @@ recorded around every kernel on its launch stream) and the oracle's own rate
 on the host cores.  Further legs (skipped with --no-extra-legs): a batch
 of 256 densities with sides drawn from {128, 256, 512, 1024} at h = 1/32
 (seed 1; autotuned node sorts), forward + transposed solve pairs at
-1024^2 over [-16, 16)^2 (mixture seed 2), and 500 split steps of the DS system
-at 2048^2 with the checkpointed gradient of the final L4 norm.
+1024^2 over [-16, 16)^2 (mixture seed 2), 500 split steps of the DS system at
+2048^2 with the checkpointed gradient of the final L4 norm, and the standard
+periodic FFT solver (throughput, and time to accuracy against the split solver).
 """
 from __future__ import annotations
 
@@ -297,6 +298,57 @@ def stepper_leg(args, torch, ps, W) -> dict:
     return res
 
 
+def periodic_leg(args, torch, ps, W) -> dict:
+    """The standard periodic FFT solver (the paper's baseline): solves/s on the C2
+    density at 2048^2 (both data paths, graph replay), and the paper's
+    time-to-accuracy comparison on Example 1 (rho = pi e^{-pi^2 r^2}): the periodic
+    solver on [-32, 32)^2 at h = 1/16 against the split solver on [-8, 8)^2 at
+    h = 1/4, FP64, errors against the closed form."""
+    import oracle.closed_forms as C
+    res = {}
+    rho = W.mixture_density(N, HALF, W.draw_mixture(SEED))
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        plan = ps.Plan(N, 2 * HALF / N, dtype=dt, n_r=N_R, n_theta=N_THETA)
+        r = torch.as_tensor(rho, dtype=dt, device="cuda")
+        o = torch.empty_like(r)
+
+        def fn():
+            plan.periodic(r, o)
+
+        for _ in range(args.warmup):
+            fn()
+        g = capture_graph(fn, torch) if args.launch == "graph" else fn
+        g()
+        t = timed_rate(g, args.steps, torch)
+        res[f"solves_per_s_{name}"] = args.steps / t
+        plan.close()
+
+    def example1(half, h, split):
+        n = int(round(2 * half / h))
+        x, y, _ = W.grid_2d(n, half)
+        exact = C.phi_isotropic_gaussian(x, y, math.pi, math.pi ** 2)
+        plan = ps.Plan(n, h, dtype=torch.float64, n_r=N_R, n_theta=N_THETA, tol=TOL64)
+        r = torch.as_tensor(W.paper_gaussian_density(n, half), dtype=torch.float64, device="cuda")
+        o = torch.empty_like(r)
+
+        def fn():
+            (plan.solve if split else plan.periodic)(r, o)
+
+        for _ in range(args.warmup):
+            fn()
+        g = capture_graph(fn, torch) if args.launch == "graph" else fn
+        g()
+        t = timed_rate(g, args.steps, torch)
+        err = float(np.max(np.abs(o.cpu().numpy() - exact)) / np.max(np.abs(exact)))
+        plan.close()
+        return {"grid": n, "half_width": half, "h": h, "rel_linf": err, "us_per_solve": round(1e6 * t / args.steps, 2)}
+
+    res["example1_accuracy"] = {"periodic_L32_h1_16": example1(32.0, 1 / 16, False),
+                                "split_L8_h1_4": example1(8.0, 0.25, True),
+                                "split_L8_h1_8": example1(8.0, 0.125, True)}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,9 +356,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (and the error figures that need it)")
-    ap.add_argument("--legs", default="batch,adjoint,stepper",
+    ap.add_argument("--legs", default="batch,adjoint,stepper,periodic",
                     help="comma-separated further legs to run after the 2048^2 single solve "
-                         "(batch, adjoint, stepper; empty for none)")
+                         "(batch, adjoint, stepper, periodic; empty for none)")
     ap.add_argument("--no-extra-legs", action="store_true", help="same as --legs ''")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="replay each solve from a captured HIP graph (default) or launch it eagerly")
@@ -429,7 +481,7 @@ def main() -> int:
     plan32.close()
     plan64.close()
     legs = set() if args.no_extra_legs else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"batch", "adjoint", "stepper"}
+    unknown = legs - {"batch", "adjoint", "stepper", "periodic"}
     if unknown:
         print(f"unknown legs {sorted(unknown)}", file=sys.stderr)
         return 2
@@ -440,6 +492,9 @@ def main() -> int:
         result["adjoint_pairs_1024"] = adjoint_leg(args, torch, ps, W)
     if "stepper" in legs:
         result["ds_stepper_2048"] = stepper_leg(args, torch, ps, W)
+    if "periodic" in legs:
+        print("[bench] periodic FFT solver", file=sys.stderr, flush=True)
+        result["periodic_fft"] = periodic_leg(args, torch, ps, W)
     if not args.no_cpu_baseline:
         print("[bench] oracle leg on the host cores", file=sys.stderr, flush=True)
         ref, base = cpu_baseline(rho_used)

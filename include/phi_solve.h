@@ -162,6 +162,15 @@ phi_status phi_nodes_type2(phi_plan_t plan, const void* rho, void* rho_hat, void
  * coef: M interleaved (re, im) pairs in plan order; field: N x N device array. */
 phi_status phi_nodes_type1(phi_plan_t plan, const void* coef, void* field, void* stream);
 
+/* The standard periodic FFT solver the paper compares against (Sec. 1; Sec. 3.1,
+ * Tables 1 and 4): Phi_hat(k_m) = -kx^2/|k|^2 rho_hat(k_m) on the plan's N x N
+ * periodic grid, k_m = m/(N h) in FFT order, Phi_hat(0) = 0 (-ky^2/|k|^2 with
+ * PHI_COMPONENT_Y).  rho, phi: N x N device arrays as for phi_solve.  The
+ * operator is symmetric, so it is also its own transpose.  Uses the plan's
+ * workspace (one call in flight per plan, as phi_solve).  N = 16 .. 4096;
+ * PHI_ERR_UNSUPPORTED for smaller grids and for batch plans. */
+phi_status phi_solve_periodic(phi_plan_t plan, const void* rho, void* phi, void* stream);
+
 /* I1 alone (Sec. 2.1, eq. 9) and I2 alone (eq. 12); phi_solve = their sum. */
 phi_status phi_solve_highfreq(phi_plan_t plan, const void* rho, void* i1, void* stream);
 phi_status phi_solve_lowfreq(phi_plan_t plan, const void* rho, void* i2, void* stream);

@@ -75,6 +75,7 @@ def _declare(lib):
         "phi_solve_lowfreq": (st, [_P, _P, _P, _P]),
         "phi_nodes_type2": (st, [_P, _P, _P, _P]),
         "phi_nodes_type1": (st, [_P, _P, _P, _P]),
+        "phi_solve_periodic": (st, [_P, _P, _P, _P]),
         "phi_destroy": (st, [_P]),
         "phi_solve_timed": (st, [_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float),
                                  ctypes.POINTER(ctypes.c_char_p), ctypes.c_int32,
@@ -127,7 +128,7 @@ def exported_symbols():
         "phi_params_default", "phi_describe", "phi_plan", "phi_plan_batch", "phi_batch_layout",
         "phi_batch_member_info",
         "phi_solve", "phi_solve_adjoint",
-        "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1",
+        "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1", "phi_solve_periodic",
         "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",
         "phi_status_string", "phi_last_error",

@@ -93,7 +93,7 @@ struct Layout {
 };
 // everything a plan reads and never writes
 struct TableParts {
-    Part deconv, gx, gy, gyr, q, cell, sub, cst, con, taps, twr;
+    Part deconv, gx, gy, gyr, q, cell, sub, cst, con, taps, twr, twn;
 };
 // everything a solve writes
 struct WorkParts {
@@ -114,6 +114,7 @@ TableParts layout_tables(const phi::HostPlan& hp, size_t es, Layout& L) {
     t.con = L.take(hp.contrib.size() * 4);
     t.taps = L.take(hp.taps.size() * es);
     t.twr = L.take(hp.twr.size() * es);
+    t.twn = L.take(hp.twn.size() * es);
     return t;
 }
 
@@ -167,6 +168,13 @@ hipError_t upload_tables(const phi::HostPlan& hp, const TableParts& t, char* bas
         twr = keep.back().data();
     }
     if (e == hipSuccess) e = up(t.twr, twr);
+    const void* twn = hp.twn.data();
+    if (f32) {
+        keep.emplace_back();
+        phi::round_unit_pairs(hp.twn, &keep.back());
+        twn = keep.back().data();
+    }
+    if (e == hipSuccess) e = up(t.twn, twn);
     return e;
 }
 
@@ -200,6 +208,8 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->tile = hp.tile;
     d->twr = base + t.twr.off;
     d->twr_count = static_cast<int>(hp.twr.size() / 2);
+    d->twn = base + t.twn.off;
+    d->twn_count = static_cast<int>(hp.twn.size() / 2);
     d->xt = base + w.xt.off;
     d->tt = base + w.tt.off;
     d->win = base + w.win.off;
@@ -717,6 +727,14 @@ phi_status phi_nodes_type2(phi_plan_t plan, const void* rho, void* rho_hat, void
 
 phi_status phi_nodes_type1(phi_plan_t plan, const void* coef, void* field, void* stream) {
     return run(plan, phi::Stage::Type1, coef, field, 0, stream);
+}
+
+phi_status phi_solve_periodic(phi_plan_t plan, const void* rho, void* phi_out, void* stream) {
+    phi_status st = check_plan(plan);
+    if (st != PHI_OK) return st;
+    if (plan->n_members == 0 && plan->host.n < 16)
+        return fail(plan, PHI_ERR_UNSUPPORTED, "the periodic solver takes grid sides 16 .. 4096");
+    return run(plan, phi::Stage::Periodic, rho, phi_out, 0, stream);
 }
 
 phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t adjoint, void* stream,

@@ -444,6 +444,8 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
     // ---- register-FFT stage twiddles --------------------------------------------
     const int lg = hp->log_fine;
     fft_stage_twiddles(lg, &hp->twr);
+    hp->twn.clear();
+    if (lg - 1 >= kMinLogFine) fft_stage_twiddles(lg - 1, &hp->twn);
     return PHI_OK;
 }
 

@@ -54,6 +54,7 @@ struct HostPlan {
     std::vector<double> gx;             // [2 (N+1)] (a, 1 - e^{-a}),  a = kx^2 / sigma^2, kx = m/(n_fine h)
     std::vector<double> gy;             // [2 n_fine] (b, 1 - e^{-b}), signed frequency
     std::vector<double> twr;            // (re, im) per-stage twiddles of the register FFT of length n_fine
+    std::vector<double> twn;            // the same for length n (the periodic solver, n >= 16)
 };
 
 phi_status fill_defaults(phi_params* p, int32_t n, double h, phi_dtype dtype);

@@ -289,6 +289,8 @@ hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s
 
 hipError_t enqueue(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
                    hipStream_t s, KernelTimer* timer) {
+    // the periodic operator is symmetric: its transpose is the same chain
+    if (stage == Stage::Periodic) return enqueue_periodic(P, in, out, s, timer);
     if (P.dtype == PHI_F32) return enqueue_typed<float>(P, ss, stage, in, out, adjoint, s, timer);
     return enqueue_typed<double>(P, ss, stage, in, out, adjoint, s, timer);
 }

@@ -31,6 +31,8 @@ struct DevPlan {
     int n_sub, bin, tile;      // subproblems, bin side, tile side E = bin + w - 1
     const void* twr;        // register-FFT stage twiddles, data precision, twr_count complex
     int twr_count;
+    const void* twn;        // the same for length N (periodic solver), twn_count complex
+    int twn_count;
     // workspace, element type = data precision
     void* xt;       // (N+1) columns of N complex: I1 half spectrum, column-major, col_stride apart
     void* tt;       // Q columns of N complex: type-2 row window, column-major, col_stride apart
@@ -47,7 +49,7 @@ struct StreamSet {
     hipEvent_t fork = nullptr, join = nullptr;
 };
 
-enum class Stage { Solve, HighFreq, LowFreq, Type2, Type1 };
+enum class Stage { Solve, HighFreq, LowFreq, Type2, Type1, Periodic };
 
 // Optional per-kernel timing: events recorded on the kernel's launch stream
 // just before and just after each kernel.  The events are created by the owner.
@@ -57,6 +59,10 @@ struct KernelTimer {
     const char* names[kMax];
     int count = 0;
 };
+
+// The standard periodic FFT solver on the plan's grid (three passes of N-point
+// FFTs over the I1 half-spectrum workspace); N >= 16.
+hipError_t enqueue_periodic(const DevPlan& P, const void* in, void* out, hipStream_t s, KernelTimer* timer);
 
 // Records the start (end = false) or the end (end = true) of kernel `name` on
 // stream s; no-op without a timer.

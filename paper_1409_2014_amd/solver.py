@@ -169,6 +169,10 @@ class Plan:
     def lowfreq(self, rho: torch.Tensor, out=None) -> torch.Tensor:
         return self._call(B.lib().phi_solve_lowfreq, self._check_grid(rho, "rho"), self._grid_out(out))
 
+    def periodic(self, rho: torch.Tensor, out=None) -> torch.Tensor:
+        """The standard periodic FFT solver on the same grid (the paper's baseline)."""
+        return self._call(B.lib().phi_solve_periodic, self._check_grid(rho, "rho"), self._grid_out(out))
+
     def type2(self, rho: torch.Tensor) -> torch.Tensor:
         """rho_hat at the plan's polar nodes (complex, plan order)."""
         m = self.info["n_nodes"]
