@@ -15,12 +15,16 @@ right-hand side into
        Phi frozen at the density of the substep's input (Sec. 2.3)
        w(t + s) = w(t) exp(i s (2 beta rho + 4 beta Phi)).
 
-One step of length tau is the symmetric (Strang) composition
-e^{A tau/2} e^{B tau} e^{A tau/2} (the paper introduces the first-order Lie
-composition and uses a fourth-order one in its experiments; the symmetric
-second-order one is the composition this path integrates).  Phi comes from the
-split quadrature of split_solver.phi, so the oracle stepper is exactly what
-the GPU stepper computes, with direct sums in place of NUFFTs.
+One step of length tau is a composition of these flows (Sec. 2.3):
+  "strang"    e^{A tau/2} e^{B tau} e^{A tau/2}, second order;
+  "yoshida4"  e^{A a1 tau} e^{B b1 tau} e^{A a2 tau} e^{B b2 tau} e^{A a3 tau}
+              e^{B b3 tau} e^{A a4 tau} with b1 = b3 = 1/(2 - 2^(1/3)),
+              b2 = -2^(1/3) b3, a1 = a4 = b3/2, a2 = a3 = (b3 + b2)/2 (the
+              fourth-order composition the paper uses for its experiments).
+Phi comes from the split quadrature of split_solver.phi ("split"), so the
+oracle stepper is exactly what the GPU stepper computes with direct sums in
+place of NUFFTs, or from the standard periodic FFT solver ("periodic", the
+paper's baseline).
 
 Gradients of a real loss J(u) of the complex field u are represented as the
 complex field g = dJ/dRe(u) + i dJ/dIm(u), so that the first-order change is
@@ -33,6 +37,7 @@ import math
 
 import numpy as np
 
+from .periodic import phi_periodic
 from .split_solver import SplitParams, phi, phi_transpose
 
 __all__ = [
@@ -41,6 +46,8 @@ __all__ = [
     "nonlinear_phase",
     "nonlinear_flow",
     "strang_step",
+    "composition",
+    "step",
     "evolve",
     "loss_l4",
     "loss_l4_gradient",
@@ -51,7 +58,9 @@ __all__ = [
 @dataclasses.dataclass(frozen=True)
 class DSParams:
     """Grid (n points of spacing h on [-L, L)^2, L = n h / 2), coefficients
-    alpha, beta of eq. 1, time step tau, polar node counts of the Phi solve."""
+    alpha, beta of eq. 1, time step tau, polar node counts of the Phi solve,
+    the composition ("strang" or "yoshida4") and the potential solver ("split"
+    or "periodic")."""
     n: int
     h: float
     alpha: float = 1.0
@@ -59,6 +68,8 @@ class DSParams:
     tau: float = 1e-3
     n_r: int = 64
     n_theta: int = 128
+    scheme: str = "strang"
+    potential: str = "split"
 
     def split(self) -> SplitParams:
         return SplitParams(n=self.n, h=self.h, n_r=self.n_r, n_theta=self.n_theta)
@@ -80,15 +91,53 @@ def linear_flow(u: np.ndarray, p: DSParams, t: float) -> np.ndarray:
     return np.fft.ifft2(np.fft.fft2(u) * mult)
 
 
+def potential(rho: np.ndarray, p: DSParams) -> np.ndarray:
+    """Phi[rho] by the stepper's potential solver."""
+    if p.potential == "periodic":
+        return phi_periodic(rho, p.h)
+    return phi(rho, p.split())
+
+
+def potential_transpose(g: np.ndarray, p: DSParams) -> np.ndarray:
+    """The transpose of the potential operator (the periodic one is symmetric)."""
+    if p.potential == "periodic":
+        return phi_periodic(g, p.h)
+    return phi_transpose(g, p.split())
+
+
 def nonlinear_phase(v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
     """t (2 beta rho + 4 beta Phi[rho]) with rho = |v|^2 (Sec. 2.3, second substep)."""
     rho = np.abs(v) ** 2
-    return t * (2.0 * p.beta * rho + 4.0 * p.beta * phi(rho, p.split()))
+    return t * (2.0 * p.beta * rho + 4.0 * p.beta * potential(rho, p))
 
 
 def nonlinear_flow(v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
     """Exact pointwise flow of the second substep over time t."""
     return v * np.exp(1j * nonlinear_phase(v, p, t))
+
+
+def composition(scheme: str):
+    """(linear times, nonlinear times) of one step as fractions of tau:
+    e^{A c_0 tau} e^{B d_0 tau} e^{A c_1 tau} ... e^{B d_{K-1} tau} e^{A c_K tau}."""
+    if scheme == "strang":
+        return [0.5, 0.5], [1.0]
+    if scheme == "yoshida4":
+        b1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+        b2 = -(2.0 ** (1.0 / 3.0)) * b1
+        a1 = 0.5 * b1
+        a2 = 0.5 * (b1 + b2)
+        return [a1, a2, a2, a1], [b1, b2, b1]
+    raise ValueError(f"unknown scheme {scheme}")
+
+
+def step(u: np.ndarray, p: DSParams) -> np.ndarray:
+    """One step of the scheme's composition."""
+    lin, nonlin = composition(p.scheme)
+    u = linear_flow(u, p, lin[0] * p.tau)
+    for d, c in zip(nonlin, lin[1:]):
+        u = nonlinear_flow(u, p, d * p.tau)
+        u = linear_flow(u, p, c * p.tau)
+    return u
 
 
 def strang_step(u: np.ndarray, p: DSParams) -> np.ndarray:
@@ -101,7 +150,7 @@ def strang_step(u: np.ndarray, p: DSParams) -> np.ndarray:
 def evolve(u0: np.ndarray, p: DSParams, steps: int) -> np.ndarray:
     u = np.asarray(u0, dtype=np.complex128)
     for _ in range(steps):
-        u = strang_step(u, p)
+        u = strang_step(u, p) if p.scheme == "strang" else step(u, p)
     return u
 
 
@@ -122,7 +171,7 @@ def nonlinear_flow_adjoint(g: np.ndarray, v: np.ndarray, p: DSParams, t: float) 
     ph = nonlinear_phase(v, p, t)
     w = v * np.exp(1j * ph)
     s = -np.imag(np.conj(g) * w)
-    r = t * (2.0 * p.beta * s + 4.0 * p.beta * phi_transpose(s, p.split()))
+    r = t * (2.0 * p.beta * s + 4.0 * p.beta * potential_transpose(s, p))
     return g * np.exp(-1j * ph) + 2.0 * r * v
 
 
@@ -131,16 +180,21 @@ def loss_l4_gradient(u0: np.ndarray, p: DSParams, steps: int) -> tuple[float, np
     through every substep with all intermediate states kept.  The linear
     substep is unitary with a unit-modulus Fourier multiplier, so its adjoint
     is the same flow backwards in time."""
+    lin, nonlin = composition(p.scheme)
     u = np.asarray(u0, dtype=np.complex128)
     vs = []
     for _ in range(steps):
-        v = linear_flow(u, p, 0.5 * p.tau)
-        vs.append(v)
-        u = linear_flow(nonlinear_flow(v, p, p.tau), p, 0.5 * p.tau)
+        u = linear_flow(u, p, lin[0] * p.tau)
+        for d, c in zip(nonlin, lin[1:]):
+            vs.append(u)
+            u = linear_flow(nonlinear_flow(u, p, d * p.tau), p, c * p.tau)
     loss = loss_l4(u, p)
     g = 4.0 * p.h ** 2 * np.abs(u) ** 2 * u        # dJ/dRe u + i dJ/dIm u
-    for v in reversed(vs):
-        g = linear_flow(g, p, -0.5 * p.tau)
-        g = nonlinear_flow_adjoint(g, v, p, p.tau)
-        g = linear_flow(g, p, -0.5 * p.tau)
+    k = len(vs)
+    for _ in range(steps):
+        for d, c in zip(reversed(nonlin), reversed(lin[1:])):
+            k -= 1
+            g = linear_flow(g, p, -c * p.tau)
+            g = nonlinear_flow_adjoint(g, vs[k], p, d * p.tau)
+        g = linear_flow(g, p, -lin[0] * p.tau)
     return loss, g

@@ -104,6 +104,68 @@ def test_linear_part_of_a_step_is_the_exact_flow():
     assert np.max(np.abs(got - gaussian_free_flow(x, y, 0.2, 1.0, 1.5, 1.0))) < 1e-12
 
 
+def lump(x, y, t):
+    """Arkadiev's exact solution of the H-E DS system (alpha = 1, beta = -1),
+    Sec. 3.2 Example 3 case I."""
+    return 2.0 * np.exp(1j * (2.0 * y + 4.0 * t)) / ((x + 1.0) ** 2 + (y + 4.0 * t) ** 2 + 1.0)
+
+
+@pytest.mark.parametrize("scheme", ["strang", "yoshida4"])
+@pytest.mark.parametrize("pot", ["split", "periodic"])
+def test_short_time_evolution_of_the_exact_lump(scheme, pot):
+    """On [-8, 8)^2 at h = 1/2 the lump's algebraic tails are cut by the box, so
+    the error is about 1e-2 after T = 0.05; a sign error in alpha or beta or in
+    the coupling gives 0.1 or more."""
+    n, half = 32, 8.0
+    x, y, h = W.grid_2d(n, half)
+    p = D.DSParams(n=n, h=h, alpha=1.0, beta=-1.0, tau=0.005, n_r=32, n_theta=64, scheme=scheme, potential=pot)
+    u = D.evolve(lump(x, y, 0.0), p, 10)
+    ex = lump(x, y, 0.05)
+    assert np.linalg.norm(u - ex) / np.linalg.norm(ex) < 0.02
+
+
+def test_yoshida_composition_is_fourth_order():
+    """A smooth field on a coarse grid keeps the step in the asymptotic regime:
+    halving tau divides the error by 16 (the symmetric composition: by 4)."""
+    n, half = 16, 4.0
+    x, y, _ = W.grid_2d(n, half)
+    u0 = (np.exp(-(x ** 2 + 2 * y ** 2) / 2) * np.exp(0.3j * x)).astype(np.complex128)
+    base = dict(n=n, h=2 * half / n, alpha=1.0, beta=2.0, n_r=12, n_theta=24, scheme="yoshida4")
+    t_end = 0.1
+    ref = D.evolve(u0, D.DSParams(tau=t_end / 128, **base), 128)
+    errs = [np.max(np.abs(D.evolve(u0, D.DSParams(tau=t_end / m, **base), m) - ref)) for m in (4, 8, 16)]
+    for a, b in zip(errs, errs[1:]):
+        assert 14.0 < a / b < 18.5, errs
+
+
+def test_yoshida_linear_part_is_the_exact_flow():
+    n, half = 64, 8.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=-1.0, beta=0.0, tau=0.05, n_r=16, n_theta=32, scheme="yoshida4")
+    x, y, _ = W.grid_2d(n, half)
+    got = D.evolve(np.exp(-x ** 2 - y ** 2 / 1.5).astype(np.complex128), p, 4)
+    assert np.max(np.abs(got - gaussian_free_flow(x, y, 0.2, 1.0, 1.5, -1.0))) < 1e-12
+
+
+@pytest.mark.parametrize("scheme,pot", [("yoshida4", "split"), ("strang", "periodic"), ("yoshida4", "periodic")])
+def test_gradient_of_other_schemes_matches_central_differences(scheme, pot):
+    n, half = 16, 4.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=-1.0, beta=1.5, tau=2e-2, n_r=12, n_theta=24, scheme=scheme,
+                   potential=pot)
+    x, y, _ = W.grid_2d(n, half)
+    u0 = (np.exp(-(x ** 2 + 2 * y ** 2)) * np.exp(0.4j * y)).astype(np.complex128)
+    steps = 2
+    loss, g = D.loss_l4_gradient(u0, p, steps)
+    assert abs(loss - D.loss_l4(D.evolve(u0, p, steps), p)) < 1e-14 * loss
+    rng = np.random.default_rng(11)
+    eps = 1e-5
+    for _ in range(3):
+        d = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        fd = (D.loss_l4(D.evolve(u0 + eps * d, p, steps), p)
+              - D.loss_l4(D.evolve(u0 - eps * d, p, steps), p)) / (2 * eps)
+        dot = float(np.sum(np.real(np.conj(g) * d)))
+        assert abs(fd - dot) <= 1e-7 * abs(dot), (fd, dot)
+
+
 # ---- the pins above must catch plausible mistakes in the stepper -------------
 
 def _ds_pins_hold():
@@ -113,7 +175,10 @@ def _ds_pins_hold():
                test_nonlinear_phase_uses_the_potential_of_the_density,
                test_symmetric_composition_is_second_order,
                test_linear_part_of_a_step_is_the_exact_flow,
-               test_reverse_mode_gradient_matches_central_differences):
+               test_reverse_mode_gradient_matches_central_differences,
+               test_yoshida_composition_is_fourth_order,
+               lambda: test_short_time_evolution_of_the_exact_lump("yoshida4", "split"),
+               lambda: test_gradient_of_other_schemes_matches_central_differences("yoshida4", "split")):
         try:
             fn()
             checks.append(True)
@@ -162,12 +227,34 @@ def _adjoint_without_potential_term(monkeypatch):
     monkeypatch.setattr(D, "nonlinear_flow_adjoint", _adj_local_only)
 
 
+def _strang_weights_in_yoshida(monkeypatch):
+    orig = D.composition
+    monkeypatch.setattr(D, "composition", lambda scheme: orig("strang") if scheme == "yoshida4" else orig(scheme))
+
+
+def _yoshida_middle_sign(monkeypatch):
+    orig = D.composition
+
+    def comp(scheme):
+        lin, nonlin = orig(scheme)
+        if scheme == "yoshida4":
+            nonlin = [nonlin[0], -nonlin[1], nonlin[2]]
+        return lin, nonlin
+    monkeypatch.setattr(D, "composition", comp)
+
+
+def _beta_sign(monkeypatch):
+    orig = D.nonlinear_phase
+    monkeypatch.setattr(D, "nonlinear_phase", lambda v, p, t: -orig(v, p, t))
+
+
 def test_unmodified_stepper_passes_the_pins():
     assert _ds_pins_hold()
 
 
 @pytest.mark.parametrize("mutation", [_alpha_sign, _no_two_pi, _half_local_term, _lie_composition,
-                                      _full_linear_substeps, _adjoint_without_potential_term])
+                                      _full_linear_substeps, _adjoint_without_potential_term,
+                                      _strang_weights_in_yoshida, _yoshida_middle_sign, _beta_sign])
 def test_planted_stepper_mistake_is_caught(monkeypatch, mutation):
     mutation(monkeypatch)
     assert not _ds_pins_hold()
