@@ -4,13 +4,20 @@
  *   i u_t = -u_xx + alpha u_yy - 2 beta |u|^2 u - 4 beta Phi u,
  *   Phi_hat = -kx^2/|k|^2 rho_hat,  rho = |u|^2             (Sec. 1, eqs. 1-2)
  *
- * on the periodic box of the solve's grid (Sec. 2.3).  One step of length tau is
- * the symmetric composition e^{A tau/2} e^{B tau} e^{A tau/2} of
+ * on the periodic box of the solve's grid (Sec. 2.3).  A step of length tau is a
+ * composition of the exact flows of
  *   A: i v_t = (-d_xx + alpha d_yy) v, exact in Fourier space:
- *      v_hat <- v_hat e^{-i 4 pi^2 (kx^2 - alpha ky^2) tau/2}, k = m/(N h);
- *   B: w = v e^{i tau (2 beta |v|^2 + 4 beta Phi[|v|^2])}, pointwise (Sec. 2.3),
- *      Phi from one phi_solve of the stepper's own plan.
- * Consecutive half steps of A are applied as one full step.
+ *      v_hat <- v_hat e^{-i 4 pi^2 (kx^2 - alpha ky^2) s}, k = m/(N h);
+ *   B: w = v e^{i s (2 beta |v|^2 + 4 beta Phi[|v|^2])}, pointwise (Sec. 2.3),
+ *      Phi from one potential solve of the stepper's own plan:
+ *   PHI_DS_STRANG    e^{A tau/2} e^{B tau} e^{A tau/2}            (1 solve per step)
+ *   PHI_DS_YOSHIDA4  e^{A a1 tau} e^{B b1 tau} e^{A a2 tau} e^{B b2 tau}
+ *                    e^{A a2 tau} e^{B b1 tau} e^{A a1 tau}, b1 = 1/(2 - 2^(1/3)),
+ *                    b2 = -2^(1/3) b1, a1 = b1/2, a2 = (b1 + b2)/2 (3 solves per
+ *                    step; the fourth-order composition of Sec. 2.3).
+ * The last A of a step and the first A of the next are applied as one.
+ * The potential solver is the split solver (phi_solve, PHI_DS_SPLIT) or the
+ * standard periodic FFT solver (phi_solve_periodic, PHI_DS_PERIODIC).
  *
  * Fields are N x N complex arrays in device memory, row-major [y][x] with x
  * contiguous, interleaved (re, im) in the data precision of the solve
@@ -31,13 +38,24 @@ extern "C" {
 
 typedef struct phi_ds_s* phi_ds_t;
 
+typedef enum { PHI_DS_STRANG = 0, PHI_DS_YOSHIDA4 = 1 } phi_ds_scheme;
+typedef enum { PHI_DS_SPLIT = 0, PHI_DS_PERIODIC = 1 } phi_ds_potential;
+
+typedef struct {
+    double alpha, beta;    /* coefficients of eq. 1 (finite)                */
+    double tau;            /* time step (finite)                            */
+    int32_t scheme;        /* phi_ds_scheme                                 */
+    int32_t potential;     /* phi_ds_potential                              */
+} phi_ds_options;
+
 /* Creates a stepper on the current device: a potential-solve plan for *solve
  * (grid side 16..4096, spacing, polar nodes, tolerance, dtype, flags), the
- * Fourier multipliers of the linear substep for tau/2 and tau (FP64, rounded to
- * the data precision) and a workspace of 2 complex and 2 real N x N fields.
- * alpha, beta: coefficients of eq. 1; tau: time step (all finite). */
-phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, double tau, void* stream,
-                         phi_ds_t* out);
+ * Fourier multipliers of the scheme's linear substeps (FP64, rounded to the
+ * data precision) and a workspace of 2 complex and 2 real N x N fields. */
+phi_status phi_ds_create(const phi_params* solve, const phi_ds_options* options, void* stream, phi_ds_t* out);
+
+/* Nonlinear substeps (= potential solves) per step: 1 (Strang) or 3 (Yoshida). */
+phi_status phi_ds_substeps(phi_ds_t ds, int32_t* per_step);
 
 /* Frees the stepper and its plan after synchronizing its device.  NULL is a no-op. */
 phi_status phi_ds_destroy(phi_ds_t ds);
@@ -46,19 +64,21 @@ phi_status phi_ds_destroy(phi_ds_t ds);
 phi_status phi_ds_plan(phi_ds_t ds, phi_plan_t* plan);
 
 /* Advances u in place by `steps` (>= 0) steps.  v_store (may be NULL) receives
- * the input v_i of the i-th nonlinear substep at element offset i N^2 (complex
- * fields), phi_store (may be NULL) the potential Phi_i of that substep at
- * offset i N^2 (real fields): what phi_ds_backward needs to run the reverse
- * pass of the same steps.  One potential solve per step. */
+ * the input v_i of the i-th nonlinear substep (i = 0 .. steps * substeps - 1) at
+ * element offset i N^2 (complex fields), phi_store (may be NULL) the potential
+ * Phi_i of that substep at offset i N^2 (real fields): what phi_ds_backward
+ * needs to run the reverse pass of the same steps.  One potential solve per
+ * nonlinear substep. */
 phi_status phi_ds_forward(phi_ds_t ds, void* u, int32_t steps, void* v_store, void* phi_store, void* stream);
 
 /* Reverse pass of `steps` steps: g holds the gradient with respect to the
  * state after the steps and is overwritten with the gradient with respect to
  * the state before them.  v_store and phi_store are the stores a phi_ds_forward
  * of the same steps from that earlier state wrote (both required).  Each step
- * takes one transposed potential solve (phi_solve_adjoint): with
- * w = v e^{i phi}, phi = tau (2 beta |v|^2 + 4 beta Phi),
- *   g_v = g_w e^{-i phi} + 2 tau (2 beta s + 4 beta A^T s) v,  s = -Im(conj(g_w) w),
+ * nonlinear substep of duration s takes one transposed potential solve
+ * (phi_solve_adjoint; the periodic operator is symmetric): with
+ * w = v e^{i phi}, phi = s (2 beta |v|^2 + 4 beta Phi),
+ *   g_v = g_w e^{-i phi} + 2 s (2 beta q + 4 beta A^T q) v,  q = -Im(conj(g_w) w),
  * and the linear substeps run backwards in time (their adjoints). */
 phi_status phi_ds_backward(phi_ds_t ds, void* g, int32_t steps, const void* v_store, const void* phi_store,
                            void* stream);

@@ -47,6 +47,17 @@ class PhiPlanInfo(ctypes.Structure):
     ]
 
 
+class PhiDsOptions(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("tau", ctypes.c_double),
+        ("scheme", ctypes.c_int32), ("potential", ctypes.c_int32),
+    ]
+
+
+PHI_DS_SCHEMES = {"strang": 0, "yoshida4": 1}
+PHI_DS_POTENTIALS = {"split": 0, "periodic": 1}
+
+
 class PhiError(RuntimeError):
     def __init__(self, status: int, message: str):
         self.status = status
@@ -86,8 +97,8 @@ def _declare(lib):
         "phi_host_es_kernel": (st, [ctypes.c_int32, _DP, ctypes.c_double, _DP]),
         "phi_host_es_transform": (st, [ctypes.c_int32, _DP, ctypes.c_double, _DP]),
         "phi_host_polar_nodes": (st, [ctypes.POINTER(PhiParams), _DP, _DP, _DP]),
-        "phi_ds_create": (st, [ctypes.POINTER(PhiParams), ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                               _P, ctypes.POINTER(_P)]),
+        "phi_ds_create": (st, [ctypes.POINTER(PhiParams), ctypes.POINTER(PhiDsOptions), _P, ctypes.POINTER(_P)]),
+        "phi_ds_substeps": (st, [_P, ctypes.POINTER(ctypes.c_int32)]),
         "phi_ds_destroy": (st, [_P]),
         "phi_ds_plan": (st, [_P, ctypes.POINTER(_P)]),
         "phi_ds_forward": (st, [_P, _P, ctypes.c_int32, _P, _P, _P]),
@@ -132,6 +143,6 @@ def exported_symbols():
         "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",
         "phi_status_string", "phi_last_error",
-        "phi_ds_create", "phi_ds_destroy", "phi_ds_plan", "phi_ds_forward", "phi_ds_backward",
+        "phi_ds_create", "phi_ds_substeps", "phi_ds_destroy", "phi_ds_plan", "phi_ds_forward", "phi_ds_backward",
         "phi_ds_moments", "phi_ds_loss_grad",
     ]

@@ -22,6 +22,14 @@ struct phi_ds_s {
     int device = 0;
     int n = 0;
     size_t elem = 0;             // bytes of one real value
+    int potential = PHI_DS_SPLIT;
+    double tau = 0;
+    // one step: e^{A lin[0]} e^{B non[0]} e^{A lin[1]} ... e^{B non[K-1]} e^{A lin[K]}
+    // (durations in units of tau); the tables hold the distinct linear durations
+    // first (lin[0]), interior, between steps (lin[K] + lin[0]) and last (lin[K])
+    std::vector<double> non;         // K nonlinear durations
+    std::vector<int> lin_inner_table;  // tables of lin[1 .. K-1]
+    int lin_first_table = 0, lin_between_table = 0, lin_last_table = 0;
     void* block = nullptr;       // tables + workspace
     void* work_c = nullptr;      // N^2 complex: v or g_w
     void* work_r1 = nullptr;     // N^2 real: rho or s
@@ -81,6 +89,42 @@ void release(phi_ds_s* ds) {
     ds->plan = nullptr;
 }
 
+// The scheme's substep durations (fractions of tau).
+void composition(int scheme, std::vector<double>* lin, std::vector<double>* non) {
+    if (scheme == PHI_DS_YOSHIDA4) {
+        const double b1 = 1.0 / (2.0 - std::cbrt(2.0));
+        const double b2 = -std::cbrt(2.0) * b1;
+        const double a1 = 0.5 * b1, a2 = 0.5 * (b1 + b2);
+        *lin = {a1, a2, a2, a1};
+        *non = {b1, b2, b1};
+    } else {
+        *lin = {0.5, 0.5};
+        *non = {1.0};
+    }
+}
+
+// Index of duration d in the table list (added when new).
+int table_of(std::vector<double>* times, double d) {
+    for (size_t i = 0; i < times->size(); ++i)
+        if (std::fabs((*times)[i] - d) <= 1e-15 * std::fabs(d)) return static_cast<int>(i);
+    times->push_back(d);
+    return static_cast<int>(times->size()) - 1;
+}
+
+phi_status solve_potential(phi_ds_s* ds, const void* in, void* out, bool transpose, void* stream) {
+    if (ds->potential == PHI_DS_PERIODIC) return phi_solve_periodic(ds->plan, in, out, stream);
+    return transpose ? phi_solve_adjoint(ds->plan, in, out, stream) : phi_solve(ds->plan, in, out, stream);
+}
+
+// Linear-substep table after nonlinear substep k (0-based) of a run of
+// `total` nonlinear substeps, K per step.
+int table_after(const phi_ds_s* ds, int k, int total) {
+    const int K = static_cast<int>(ds->non.size());
+    const int j = k % K;
+    if (j + 1 < K) return ds->lin_inner_table[j];
+    return (k + 1 < total) ? ds->lin_between_table : ds->lin_last_table;
+}
+
 #define DS_TRY(expr, where)                               \
     do {                                                  \
         hipError_t e_ = (expr);                           \
@@ -91,16 +135,30 @@ void release(phi_ds_s* ds) {
 
 extern "C" {
 
-phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, double tau, void* stream,
-                         phi_ds_t* out) {
-    if (!solve || !out) return err(PHI_ERR_INVALID_ARG, "NULL argument");
+phi_status phi_ds_create(const phi_params* solve, const phi_ds_options* opt, void* stream, phi_ds_t* out) {
+    if (!solve || !opt || !out) return err(PHI_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
-    if (!std::isfinite(alpha) || !std::isfinite(beta) || !std::isfinite(tau))
+    if (!std::isfinite(opt->alpha) || !std::isfinite(opt->beta) || !std::isfinite(opt->tau))
         return err(PHI_ERR_INVALID_ARG, "alpha, beta and tau must be finite");
+    if (opt->scheme != PHI_DS_STRANG && opt->scheme != PHI_DS_YOSHIDA4)
+        return err(PHI_ERR_INVALID_ARG, "unknown scheme");
+    if (opt->potential != PHI_DS_SPLIT && opt->potential != PHI_DS_PERIODIC)
+        return err(PHI_ERR_INVALID_ARG, "unknown potential solver");
     if (solve->nx < 16 || solve->nx > 4096)
         return err(PHI_ERR_UNSUPPORTED, "the stepper takes grid sides 16 .. 4096");
     try {
         std::unique_ptr<phi_ds_s> ds(new phi_ds_s());
+        ds->potential = opt->potential;
+        ds->tau = opt->tau;
+        std::vector<double> lin;
+        composition(opt->scheme, &lin, &ds->non);
+        const int K = static_cast<int>(ds->non.size());
+        std::vector<double> times;     // distinct linear durations, fractions of tau
+        ds->lin_first_table = table_of(&times, lin[0]);
+        for (int j = 1; j < K; ++j) ds->lin_inner_table.push_back(table_of(&times, lin[j]));
+        ds->lin_between_table = table_of(&times, lin[K] + lin[0]);
+        ds->lin_last_table = table_of(&times, lin[K]);
+        if (static_cast<int>(times.size()) > phi::kDsMaxTimes) return err(PHI_ERR_INTERNAL, "too many substep durations");
         phi_status st = phi_plan(solve, stream, &ds->plan);
         if (st != PHI_OK) return st;   // message already recorded
         phi_plan_info info;
@@ -125,12 +183,14 @@ phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, dou
         std::vector<double> twr;
         phi::fft_stage_twiddles(log_n, &twr);
         const double h = info.h;
-        std::vector<double> tabs[4] = {multiplier(n, h, 1.0, 0.5 * tau, -1.0), multiplier(n, h, 1.0, tau, -1.0),
-                                       multiplier(n, h, alpha, 0.5 * tau, 1.0), multiplier(n, h, alpha, tau, 1.0)};
-        // layout: 4 multiplier tables, twiddles, partial sums, spec, work_c, work_r1, work_r2
+        const int nt = static_cast<int>(times.size());
+        std::vector<std::vector<double>> tabs;
+        for (int i = 0; i < nt; ++i) tabs.push_back(multiplier(n, h, 1.0, times[i] * opt->tau, -1.0));
+        for (int i = 0; i < nt; ++i) tabs.push_back(multiplier(n, h, opt->alpha, times[i] * opt->tau, 1.0));
+        // layout: 2 nt multiplier tables, twiddles, partial sums, spec, work_c, work_r1, work_r2
         size_t off = 0;
-        size_t o_tab[4];
-        for (int i = 0; i < 4; ++i) {
+        std::vector<size_t> o_tab(tabs.size());
+        for (size_t i = 0; i < tabs.size(); ++i) {
             o_tab[i] = off;
             off = align256(off + 2 * n * es);
         }
@@ -163,7 +223,7 @@ phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, dou
             phi::round_unit_pairs(v, &keep.back());
             return keep.back().data();
         };
-        for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        for (size_t i = 0; i < tabs.size() && e == hipSuccess; ++i)
             e = hipMemcpyAsync(base + o_tab[i], narrow(tabs[i]), 2 * n * es, hipMemcpyHostToDevice, s);
         if (e == hipSuccess && !twr.empty())
             e = hipMemcpyAsync(base + o_twr, narrow(twr), twr.size() * es, hipMemcpyHostToDevice, s);
@@ -176,13 +236,13 @@ phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, dou
         d.dtype = solve->dtype;
         d.n = n;
         d.log_n = log_n;
-        d.tau = tau;
-        d.beta = beta;
+        d.beta = opt->beta;
         d.h2 = h * h;
-        d.ex_half = base + o_tab[0];
-        d.ex_full = base + o_tab[1];
-        d.ey_half = base + o_tab[2];
-        d.ey_full = base + o_tab[3];
+        d.n_times = nt;
+        for (int i = 0; i < nt; ++i) {
+            d.ex[i] = base + o_tab[i];
+            d.ey[i] = base + o_tab[nt + i];
+        }
         d.twr = base + o_twr;
         d.twr_count = static_cast<int>(twr.size() / 2);
         d.spec = base + o_spec;
@@ -199,6 +259,12 @@ phi_status phi_ds_create(const phi_params* solve, double alpha, double beta, dou
     } catch (...) {
         return err(PHI_ERR_INTERNAL, "unexpected exception");
     }
+}
+
+phi_status phi_ds_substeps(phi_ds_t ds, int32_t* per_step) {
+    if (!is_live(ds) || !per_step) return err(PHI_ERR_INVALID_ARG, "NULL or destroyed stepper");
+    *per_step = static_cast<int32_t>(ds->non.size());
+    return PHI_OK;
 }
 
 phi_status phi_ds_destroy(phi_ds_t ds) {
@@ -232,27 +298,31 @@ phi_status phi_ds_forward(phi_ds_t ds, void* u, int32_t steps, void* v_store, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     const phi::DsDev& D = ds->dev;
     const size_t nn = static_cast<size_t>(ds->n) * ds->n;
+    const int K = static_cast<int>(ds->non.size());
+    const int total = steps * K;
     char* vs = static_cast<char*>(v_store);
     char* ps = static_cast<char*>(phi_store);
-    // e^{A tau/2}, then per step: complete the linear substep (v_i, rho_i), Phi_i,
-    // the nonlinear substep fused into the next linear substep (a full step
-    // between steps, a half step after the last)
-    DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Plain, 0, 0, u, nullptr, nullptr, nullptr, nullptr, s),
+    // the first linear substep; then per nonlinear substep: complete the linear
+    // substep (v_k, rho_k), Phi_k, the nonlinear substep fused into the next
+    // linear substep (consecutive linear substeps of two steps merged)
+    const int t0 = ds->lin_first_table;
+    DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Plain, 0, t0, u, nullptr, nullptr, nullptr, nullptr, 0.0, s),
            "ds rows_forward");
-    DS_TRY(phi::ds_cols(D, 0, 0, s), "ds cols");
-    for (int i = 0; i < steps; ++i) {
-        void* v = vs ? static_cast<void*>(vs + i * nn * 2 * ds->elem) : ds->work_c;
-        void* pot = ps ? static_cast<void*>(ps + i * nn * ds->elem) : ds->work_r2;
-        DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::Density, v, ds->work_r1, nullptr, nullptr, s),
+    DS_TRY(phi::ds_cols(D, 0, t0, s), "ds cols");
+    for (int k = 0; k < total; ++k) {
+        const double ntau = ds->non[k % K] * ds->tau;
+        void* v = vs ? static_cast<void*>(vs + static_cast<size_t>(k) * nn * 2 * ds->elem) : ds->work_c;
+        void* pot = ps ? static_cast<void*>(ps + static_cast<size_t>(k) * nn * ds->elem) : ds->work_r2;
+        DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::Density, v, ds->work_r1, nullptr, nullptr, ntau, s),
                "ds rows_inverse");
-        st = phi_solve(ds->plan, ds->work_r1, pot, stream);
+        st = solve_potential(ds, ds->work_r1, pot, false, stream);
         if (st != PHI_OK) return st;
-        const int full = (i + 1 < steps) ? 1 : 0;
-        DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Nonlinear, 0, full, v, nullptr, pot, nullptr, nullptr, s),
+        const int tn = table_after(ds, k, total);
+        DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Nonlinear, 0, tn, v, nullptr, pot, nullptr, nullptr, ntau, s),
                "ds rows_forward");
-        DS_TRY(phi::ds_cols(D, 0, full, s), "ds cols");
+        DS_TRY(phi::ds_cols(D, 0, tn, s), "ds cols");
     }
-    DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::Field, u, nullptr, nullptr, nullptr, s), "ds rows_inverse");
+    DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::Field, u, nullptr, nullptr, nullptr, 0.0, s), "ds rows_inverse");
     return PHI_OK;
 }
 
@@ -266,28 +336,32 @@ phi_status phi_ds_backward(phi_ds_t ds, void* g, int32_t steps, const void* v_st
     hipStream_t s = static_cast<hipStream_t>(stream);
     const phi::DsDev& D = ds->dev;
     const size_t nn = static_cast<size_t>(ds->n) * ds->n;
+    const int K = static_cast<int>(ds->non.size());
+    const int total = steps * K;
     const char* vs = static_cast<const char*>(v_store);
     const char* ps = static_cast<const char*>(phi_store);
-    // adjoint of the trailing e^{A tau/2}; then per step, last to first: the
-    // gradient at the nonlinear substep's output and its source s, A^T s, the
-    // adjoint nonlinear update fused into the adjoint of the preceding linear substep
-    DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Plain, 1, 0, g, nullptr, nullptr, nullptr, nullptr, s),
+    // adjoint of the last linear substep; then per nonlinear substep, last to
+    // first: the gradient at its output and the source q, A^T q, the adjoint
+    // update fused into the adjoint of the linear substep before it
+    const int tl = ds->lin_last_table;
+    DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Plain, 1, tl, g, nullptr, nullptr, nullptr, nullptr, 0.0, s),
            "ds rows_forward");
-    DS_TRY(phi::ds_cols(D, 1, 0, s), "ds cols");
-    for (int i = steps - 1; i >= 0; --i) {
-        const void* v = vs + i * nn * 2 * ds->elem;
-        const void* pot = ps + i * nn * ds->elem;
-        DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::AdjointSource, ds->work_c, ds->work_r1, v, pot, s),
+    DS_TRY(phi::ds_cols(D, 1, tl, s), "ds cols");
+    for (int k = total - 1; k >= 0; --k) {
+        const double ntau = ds->non[k % K] * ds->tau;
+        const void* v = vs + static_cast<size_t>(k) * nn * 2 * ds->elem;
+        const void* pot = ps + static_cast<size_t>(k) * nn * ds->elem;
+        DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::AdjointSource, ds->work_c, ds->work_r1, v, pot, ntau, s),
                "ds rows_inverse");
-        st = phi_solve_adjoint(ds->plan, ds->work_r1, ds->work_r2, stream);
+        st = solve_potential(ds, ds->work_r1, ds->work_r2, true, stream);
         if (st != PHI_OK) return st;
-        const int full = (i > 0) ? 1 : 0;
-        DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Adjoint, 1, full, ds->work_c, v, pot, ds->work_r1,
-                                    ds->work_r2, s),
+        const int tp = (k > 0) ? table_after(ds, k - 1, total) : ds->lin_first_table;
+        DS_TRY(phi::ds_rows_forward(D, phi::DsRowIn::Adjoint, 1, tp, ds->work_c, v, pot, ds->work_r1, ds->work_r2,
+                                    ntau, s),
                "ds rows_forward");
-        DS_TRY(phi::ds_cols(D, 1, full, s), "ds cols");
+        DS_TRY(phi::ds_cols(D, 1, tp, s), "ds cols");
     }
-    DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::Field, g, nullptr, nullptr, nullptr, s), "ds rows_inverse");
+    DS_TRY(phi::ds_rows_inverse(D, phi::DsRowOut::Field, g, nullptr, nullptr, nullptr, 0.0, s), "ds rows_inverse");
     return PHI_OK;
 }
 

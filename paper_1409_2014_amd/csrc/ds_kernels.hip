@@ -15,10 +15,10 @@
 //                  1/N^2; writes the field and, by mode, rho = |v|^2 (the input
 //                  of the potential solve) or the adjoint source s.
 //
-// The nonlinear substep (Sec. 2.3: w = v e^{i tau (2 beta |v|^2 + 4 beta Phi)}) is
-// pointwise and rides in the next rows_forward; its adjoint likewise.  The
-// adjoint of a linear substep is the same three passes with conjugated
-// multipliers (the flow backwards in time).
+// The nonlinear substep of duration s (Sec. 2.3: w = v e^{i s (2 beta |v|^2 +
+// 4 beta Phi)}) is pointwise and rides in the next rows_forward; its adjoint
+// likewise.  The adjoint of a linear substep is the same three passes with
+// conjugated multipliers (the flow backwards in time).
 #include <hip/hip_runtime.h>
 
 #include "ds_kernels.hpp"
@@ -74,7 +74,7 @@ __device__ __forceinline__ cpx<R> nonlinear_rotation(cpx<R> v, R pot, R tau, R b
 template <typename R, int LOG, int MODE, bool CONJ>
 __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) void k_ds_rows_forward(
     DsDev D, const cpx<R>* __restrict__ x, const cpx<R>* __restrict__ v, const R* __restrict__ pot,
-    const R* __restrict__ s, const R* __restrict__ t, const cpx<R>* __restrict__ ex) {
+    const R* __restrict__ s, const R* __restrict__ t, const cpx<R>* __restrict__ ex, R ntau) {
     using Sh = FftShape<LOG>;
     constexpr int N = Sh::F;
     constexpr int NT = Sh::NT;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
     cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(D.twr);
     const size_t base = static_cast<size_t>(row0 + g) * N;
-    const R tau = static_cast<R>(D.tau), beta = static_cast<R>(D.beta);
+    const R tau = ntau, beta = static_cast<R>(D.beta);
     cpx<R> a[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * ds_cols_per_block<LOG>()) void 
 template <typename R, int LOG, int MODE>
 __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) void k_ds_rows_inverse(
     DsDev D, cpx<R>* __restrict__ out_c, R* __restrict__ out_r, const cpx<R>* __restrict__ v,
-    const R* __restrict__ pot) {
+    const R* __restrict__ pot, R ntau) {
     using Sh = FftShape<LOG>;
     constexpr int N = Sh::F;
     constexpr int NT = Sh::NT;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
     for (int i = 0; i < 16; ++i) a[i] = lds[lds_pad(tid + NT * i)];
     fft_reg<R, LOG, 1>(a, lds, tw, tid);
     const R scale = static_cast<R>(1.0 / (static_cast<double>(N) * N));
-    const R tau = static_cast<R>(D.tau), beta = static_cast<R>(D.beta);
+    const R tau = ntau, beta = static_cast<R>(D.beta);
     const size_t base = static_cast<size_t>(row0 + g) * N;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -282,28 +282,28 @@ __global__ __launch_bounds__(kReduceThreads) void k_ds_loss_grad(const cpx<R>* _
 
 template <typename R, int LOG, int MODE, bool CONJ>
 hipError_t launch_rows_forward(const DsDev& D, const void* x, const void* v, const void* pot, const void* s,
-                               const void* t, const void* ex, hipStream_t st) {
+                               const void* t, const void* ex, double ntau, hipStream_t st) {
     if (D.twr_count != FftShape<LOG>::tw_size() || D.n != (1 << LOG)) return hipErrorInvalidValue;
     constexpr int G = ds_rows_per_block<R, LOG>();
     hipLaunchKernelGGL((k_ds_rows_forward<R, LOG, MODE, CONJ>), dim3(D.n / G), dim3(FftShape<LOG>::NT * G), 0, st,
                        D, static_cast<const cpx<R>*>(x), static_cast<const cpx<R>*>(v),
                        static_cast<const R*>(pot), static_cast<const R*>(s), static_cast<const R*>(t),
-                       static_cast<const cpx<R>*>(ex));
+                       static_cast<const cpx<R>*>(ex), static_cast<R>(ntau));
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
 hipError_t rows_forward_log(const DsDev& D, DsRowIn mode, int conj, const void* x, const void* v, const void* pot,
-                            const void* s, const void* t, const void* ex, hipStream_t st) {
+                            const void* s, const void* t, const void* ex, double ntau, hipStream_t st) {
     // the forward chain uses (plain | nonlinear, direct), the reverse chain (plain | adjoint, conjugated)
     if (mode == DsRowIn::Plain && !conj)
-        return launch_rows_forward<R, LOG, 0, false>(D, x, v, pot, s, t, ex, st);
+        return launch_rows_forward<R, LOG, 0, false>(D, x, v, pot, s, t, ex, ntau, st);
     if (mode == DsRowIn::Plain && conj)
-        return launch_rows_forward<R, LOG, 0, true>(D, x, v, pot, s, t, ex, st);
+        return launch_rows_forward<R, LOG, 0, true>(D, x, v, pot, s, t, ex, ntau, st);
     if (mode == DsRowIn::Nonlinear && !conj)
-        return launch_rows_forward<R, LOG, 1, false>(D, x, v, pot, s, t, ex, st);
+        return launch_rows_forward<R, LOG, 1, false>(D, x, v, pot, s, t, ex, ntau, st);
     if (mode == DsRowIn::Adjoint && conj)
-        return launch_rows_forward<R, LOG, 2, true>(D, x, v, pot, s, t, ex, st);
+        return launch_rows_forward<R, LOG, 2, true>(D, x, v, pot, s, t, ex, ntau, st);
     return hipErrorInvalidValue;
 }
 
@@ -323,62 +323,64 @@ hipError_t cols_log(const DsDev& D, int conj, const void* ey, hipStream_t st) {
 
 template <typename R, int LOG, int MODE>
 hipError_t launch_rows_inverse(const DsDev& D, void* out_c, void* out_r, const void* v, const void* pot,
-                               hipStream_t st) {
+                               double ntau, hipStream_t st) {
     if (D.twr_count != FftShape<LOG>::tw_size() || D.n != (1 << LOG)) return hipErrorInvalidValue;
     constexpr int G = ds_rows_per_block<R, LOG>();
     hipLaunchKernelGGL((k_ds_rows_inverse<R, LOG, MODE>), dim3(D.n / G), dim3(FftShape<LOG>::NT * G), 0, st, D,
                        static_cast<cpx<R>*>(out_c), static_cast<R*>(out_r), static_cast<const cpx<R>*>(v),
-                       static_cast<const R*>(pot));
+                       static_cast<const R*>(pot), static_cast<R>(ntau));
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
 hipError_t rows_inverse_log(const DsDev& D, DsRowOut mode, void* out_c, void* out_r, const void* v,
-                            const void* pot, hipStream_t st) {
+                            const void* pot, double ntau, hipStream_t st) {
     switch (mode) {
-        case DsRowOut::Field: return launch_rows_inverse<R, LOG, 0>(D, out_c, out_r, v, pot, st);
-        case DsRowOut::Density: return launch_rows_inverse<R, LOG, 1>(D, out_c, out_r, v, pot, st);
-        case DsRowOut::AdjointSource: return launch_rows_inverse<R, LOG, 2>(D, out_c, out_r, v, pot, st);
+        case DsRowOut::Field: return launch_rows_inverse<R, LOG, 0>(D, out_c, out_r, v, pot, ntau, st);
+        case DsRowOut::Density: return launch_rows_inverse<R, LOG, 1>(D, out_c, out_r, v, pot, ntau, st);
+        case DsRowOut::AdjointSource: return launch_rows_inverse<R, LOG, 2>(D, out_c, out_r, v, pot, ntau, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename R>
-hipError_t rows_forward_t(const DsDev& D, DsRowIn mode, int conj, int full, const void* x, const void* v,
-                          const void* pot, const void* s, const void* t, hipStream_t st) {
-    const void* ex = full ? D.ex_full : D.ex_half;
-    PHI_DS_DISPATCH_LOG(D.log_n, (rows_forward_log<R, L_>(D, mode, conj, x, v, pot, s, t, ex, st)));
+hipError_t rows_forward_t(const DsDev& D, DsRowIn mode, int conj, int time, const void* x, const void* v,
+                          const void* pot, const void* s, const void* t, double ntau, hipStream_t st) {
+    if (time < 0 || time >= D.n_times) return hipErrorInvalidValue;
+    const void* ex = D.ex[time];
+    PHI_DS_DISPATCH_LOG(D.log_n, (rows_forward_log<R, L_>(D, mode, conj, x, v, pot, s, t, ex, ntau, st)));
 }
 
 template <typename R>
-hipError_t cols_t(const DsDev& D, int conj, int full, hipStream_t st) {
-    const void* ey = full ? D.ey_full : D.ey_half;
+hipError_t cols_t(const DsDev& D, int conj, int time, hipStream_t st) {
+    if (time < 0 || time >= D.n_times) return hipErrorInvalidValue;
+    const void* ey = D.ey[time];
     PHI_DS_DISPATCH_LOG(D.log_n, (cols_log<R, L_>(D, conj, ey, st)));
 }
 
 template <typename R>
 hipError_t rows_inverse_t(const DsDev& D, DsRowOut mode, void* out_c, void* out_r, const void* v, const void* pot,
-                          hipStream_t st) {
-    PHI_DS_DISPATCH_LOG(D.log_n, (rows_inverse_log<R, L_>(D, mode, out_c, out_r, v, pot, st)));
+                          double ntau, hipStream_t st) {
+    PHI_DS_DISPATCH_LOG(D.log_n, (rows_inverse_log<R, L_>(D, mode, out_c, out_r, v, pot, ntau, st)));
 }
 
 }  // namespace
 
-hipError_t ds_rows_forward(const DsDev& D, DsRowIn mode, int conj, int full, const void* x, const void* v,
-                           const void* pot, const void* s, const void* t, hipStream_t st) {
-    if (D.dtype == PHI_F32) return rows_forward_t<float>(D, mode, conj, full, x, v, pot, s, t, st);
-    return rows_forward_t<double>(D, mode, conj, full, x, v, pot, s, t, st);
+hipError_t ds_rows_forward(const DsDev& D, DsRowIn mode, int conj, int time, const void* x, const void* v,
+                           const void* pot, const void* s, const void* t, double ntau, hipStream_t st) {
+    if (D.dtype == PHI_F32) return rows_forward_t<float>(D, mode, conj, time, x, v, pot, s, t, ntau, st);
+    return rows_forward_t<double>(D, mode, conj, time, x, v, pot, s, t, ntau, st);
 }
 
-hipError_t ds_cols(const DsDev& D, int conj, int full, hipStream_t st) {
-    if (D.dtype == PHI_F32) return cols_t<float>(D, conj, full, st);
-    return cols_t<double>(D, conj, full, st);
+hipError_t ds_cols(const DsDev& D, int conj, int time, hipStream_t st) {
+    if (D.dtype == PHI_F32) return cols_t<float>(D, conj, time, st);
+    return cols_t<double>(D, conj, time, st);
 }
 
 hipError_t ds_rows_inverse(const DsDev& D, DsRowOut mode, void* out_c, void* out_r, const void* v,
-                           const void* pot, hipStream_t st) {
-    if (D.dtype == PHI_F32) return rows_inverse_t<float>(D, mode, out_c, out_r, v, pot, st);
-    return rows_inverse_t<double>(D, mode, out_c, out_r, v, pot, st);
+                           const void* pot, double ntau, hipStream_t st) {
+    if (D.dtype == PHI_F32) return rows_inverse_t<float>(D, mode, out_c, out_r, v, pot, ntau, st);
+    return rows_inverse_t<double>(D, mode, out_c, out_r, v, pot, ntau, st);
 }
 
 hipError_t ds_moments(const DsDev& D, const void* u, double* out, hipStream_t st) {

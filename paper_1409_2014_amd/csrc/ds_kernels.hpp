@@ -10,16 +10,17 @@ namespace phi {
 
 // Device tables and workspace of a stepper (device pointers, data precision
 // unless stated).  Complex values are interleaved (re, im).
+constexpr int kDsMaxTimes = 4;   // distinct linear-substep durations of a composition
+
 struct DsDev {
     phi_dtype dtype;
     int n, log_n;
-    double tau, beta, h2;
+    double beta, h2;
     // Fourier multipliers of the linear substep in FFT order (index m -> k = m/(N h)
-    // for m < N/2, (m - N)/(N h) otherwise), for a half and a full step:
-    const void* ex_half;   // [N] e^{-i 4 pi^2 kx^2 tau/2}
-    const void* ex_full;   // [N] e^{-i 4 pi^2 kx^2 tau}
-    const void* ey_half;   // [N] e^{+i 4 pi^2 alpha ky^2 tau/2}
-    const void* ey_full;   // [N] e^{+i 4 pi^2 alpha ky^2 tau}
+    // for m < N/2, (m - N)/(N h) otherwise), one pair per distinct duration s_i:
+    const void* ex[kDsMaxTimes];   // [N] e^{-i 4 pi^2 kx^2 s_i}
+    const void* ey[kDsMaxTimes];   // [N] e^{+i 4 pi^2 alpha ky^2 s_i}
+    int n_times;
     const void* twr;       // register-FFT stage twiddles of length N
     int twr_count;
     void* spec;            // N x N complex, column-major [kx][y]: the field after the x transform
@@ -41,18 +42,20 @@ enum class DsRowOut {
     AdjointSource = 2,   // the field g and s = -Im(conj(g) v e^{i phi})
 };
 
-// First pass of a linear substep: per grid row, the pointwise update, the
-// forward x transform and the x multiplier (conjugated when conj != 0: the
-// adjoint flow); the result goes to spec.  full selects the full or half step.
-hipError_t ds_rows_forward(const DsDev& D, DsRowIn mode, int conj, int full, const void* x, const void* v,
-                           const void* pot, const void* s, const void* t, hipStream_t st);
-// Second pass: per column of spec, forward y transform, y multiplier, inverse
-// y transform (in place).
-hipError_t ds_cols(const DsDev& D, int conj, int full, hipStream_t st);
+// First pass of a linear substep: per grid row, the pointwise update of the
+// nonlinear substep of duration ntau (or its adjoint), the forward x transform
+// and the x multiplier of table `time` (conjugated when conj != 0: the adjoint
+// flow); the result goes to spec.
+hipError_t ds_rows_forward(const DsDev& D, DsRowIn mode, int conj, int time, const void* x, const void* v,
+                           const void* pot, const void* s, const void* t, double ntau, hipStream_t st);
+// Second pass: per column of spec, forward y transform, y multiplier of table
+// `time`, inverse y transform (in place).
+hipError_t ds_cols(const DsDev& D, int conj, int time, hipStream_t st);
 // Last pass: per grid row, inverse x transform and 1/N^2; writes the field to
-// out_c (row-major) and, by mode, rho or s to out_r.
+// out_c (row-major) and, by mode, rho or the adjoint source s of the nonlinear
+// substep of duration ntau to out_r.
 hipError_t ds_rows_inverse(const DsDev& D, DsRowOut mode, void* out_c, void* out_r, const void* v,
-                           const void* pot, hipStream_t st);
+                           const void* pot, double ntau, hipStream_t st);
 // out[0] = h^2 sum |u|^2, out[1] = h^2 sum |u|^4 (FP64, fixed summation order).
 hipError_t ds_moments(const DsDev& D, const void* u, double* out, hipStream_t st);
 // g = 4 h^2 |u|^2 u: the gradient of h^2 sum |u|^4 (dJ/dRe u + i dJ/dIm u).

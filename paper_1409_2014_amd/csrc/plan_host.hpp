@@ -16,7 +16,7 @@ namespace phi {
 constexpr int kMaxLogFine = 13;        // fine grid up to 8192 (N up to 4096)
 constexpr int kMinLogFine = 4;         // fine grid from 16 (N from 8)
 constexpr int kMaxKernelWidth = 16;
-constexpr int kBinSize = 8;            // default bin side in fine-grid cells
+constexpr int kBinSize = 4;            // default bin side in fine-grid cells (measured best or equal)
 constexpr int kMaxBinSize = 16;        // largest bin side
 constexpr int kMaxNodesPerSub = 64;    // most nodes per interp / spread subproblem
 

@@ -103,7 +103,7 @@ class Plan:
     Plan(n, h, dtype=torch.float32|float64, n_r=64, n_theta=128, tol=None,
          sigma=None, cutoff=None, component="x", bin=0, sub_nodes=0, autotune=False)
 
-    bin / sub_nodes set the node sort (0: 8 cells, 64 nodes); autotune=True
+    bin / sub_nodes set the node sort (0: 4 cells, 64 nodes); autotune=True
     times the candidates on the device at plan time and keeps the fastest."""
 
     def __init__(self, n: int, h: float, *, dtype=torch.float64, device=None, **kwargs):

@@ -26,10 +26,11 @@ def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
 
 
 class DSStepper:
-    """Strang split-step integrator of the DS system on an n x n periodic grid
-    of spacing h (Sec. 2.3):
+    """Split-step integrator of the DS system on an n x n periodic grid of
+    spacing h (Sec. 2.3):
 
         DSStepper(n, h, alpha=1.0, beta=1.0, tau=1e-3, dtype=torch.float64,
+                  scheme="strang" | "yoshida4", potential="split" | "periodic",
                   n_r=64, n_theta=128, tol=None, ...)
 
     The remaining keyword arguments configure the potential solve (as Plan).
@@ -37,7 +38,8 @@ class DSStepper:
     of shape (n, n), indexed [y][x]."""
 
     def __init__(self, n: int, h: float, *, alpha: float = 1.0, beta: float = 1.0, tau: float = 1e-3,
-                 dtype=torch.float64, device=None, **solve_kwargs):
+                 dtype=torch.float64, device=None, scheme: str = "strang", potential: str = "split",
+                 **solve_kwargs):
         if not torch.cuda.is_available():
             raise RuntimeError("the DS stepper needs a ROCm GPU (torch.cuda is not available)")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
@@ -47,11 +49,17 @@ class DSStepper:
         self.n = int(n)
         self.h = float(h)
         self.alpha, self.beta, self.tau = float(alpha), float(beta), float(tau)
+        self.scheme, self.potential = scheme, potential
         params = make_params(n, h, dtype=dtype, **solve_kwargs)
+        opts = B.PhiDsOptions(self.alpha, self.beta, self.tau, B.PHI_DS_SCHEMES[scheme],
+                              B.PHI_DS_POTENTIALS[potential])
         self._handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            B.check(B.lib().phi_ds_create(ctypes.byref(params), self.alpha, self.beta, self.tau,
+            B.check(B.lib().phi_ds_create(ctypes.byref(params), ctypes.byref(opts),
                                           _stream_handle(self.device), ctypes.byref(self._handle)))
+        k = ctypes.c_int32(0)
+        B.check(B.lib().phi_ds_substeps(self._handle, ctypes.byref(k)))
+        self.substeps = int(k.value)
         plan = ctypes.c_void_p()
         B.check(B.lib().phi_ds_plan(self._handle, ctypes.byref(plan)))
         info = B.PhiPlanInfo()
@@ -78,10 +86,11 @@ class DSStepper:
                              f"{self.device}, got {tuple(u.shape)} {u.dtype} on {u.device}")
 
     def new_store(self, steps: int):
-        """(v_store, phi_store) for `steps` steps: the nonlinear substeps' inputs
-        and potentials that the reverse pass of those steps reads."""
-        v = torch.empty((steps, self.n, self.n), dtype=self.cdtype, device=self.device)
-        p = torch.empty((steps, self.n, self.n), dtype=self.dtype, device=self.device)
+        """(v_store, phi_store) for `steps` steps: the inputs and potentials of
+        their steps * substeps nonlinear substeps, which the reverse pass reads."""
+        k = steps * self.substeps
+        v = torch.empty((k, self.n, self.n), dtype=self.cdtype, device=self.device)
+        p = torch.empty((k, self.n, self.n), dtype=self.dtype, device=self.device)
         return v, p
 
     def _call(self, name, *args):
@@ -94,7 +103,7 @@ class DSStepper:
         for a later reverse pass when given."""
         self._check_field(u, "u")
         v, p = (None, None) if store is None else store
-        if store is not None and (v.shape[0] < steps or p.shape[0] < steps):
+        if store is not None and (v.shape[0] < steps * self.substeps or p.shape[0] < steps * self.substeps):
             raise ValueError("store holds fewer steps than requested")
         self._call("phi_ds_forward", _ptr(u), int(steps), _ptr(v), _ptr(p))
         return u
@@ -104,7 +113,7 @@ class DSStepper:
         the store a forward of the same steps filled."""
         self._check_field(g, "g")
         v, p = store
-        if v.shape[0] < steps or p.shape[0] < steps:
+        if v.shape[0] < steps * self.substeps or p.shape[0] < steps * self.substeps:
             raise ValueError("store holds fewer steps than requested")
         self._call("phi_ds_backward", _ptr(g), int(steps), _ptr(v), _ptr(p))
         return g
@@ -139,7 +148,7 @@ class DSStepper:
         reverse pass (the last keeps the store of the first run).
 
         Returns (J as a 0-d float64 device tensor, gradient, counts of forward,
-        recomputed and transposed potential solves)."""
+        recomputed and transposed potential solves: substeps per step each)."""
         lens = self.segments(steps, checkpoint_every)
         store = self.new_store(max(lens)) if lens else None
         u = u0.clone()
@@ -156,7 +165,8 @@ class DSStepper:
                 self.forward(w, lens[k], store)
                 recomputed += lens[k]
             self.backward(g, lens[k], store)
-        counts = {"forward_solves": steps, "recomputed_solves": recomputed, "adjoint_solves": steps}
+        k = self.substeps
+        counts = {"forward_solves": k * steps, "recomputed_solves": k * recomputed, "adjoint_solves": k * steps}
         return loss, g, counts
 
 

@@ -87,6 +87,43 @@ def test_steps_match_oracle_stepper(ps, dtype, bar, alpha):
     st.close()
 
 
+@pytest.mark.parametrize("scheme,pot,dtype,bar", [
+    ("yoshida4", "split", torch.float64, 1e-10), ("yoshida4", "periodic", torch.float64, 1e-10),
+    ("strang", "periodic", torch.float64, 1e-10), ("yoshida4", "split", torch.float32, 1e-5)])
+def test_other_schemes_match_oracle_stepper(ps, scheme, pot, dtype, bar):
+    print(f"case: stepper 64^2 6 steps {scheme} {pot} {dtype}", flush=True)
+    n, half, steps = 64, 4.0, 6
+    p = D.DSParams(n=n, h=2 * half / n, alpha=-1.0, beta=1.0, tau=1e-2, n_r=32, n_theta=64, scheme=scheme,
+                   potential=pot)
+    st = ps.DSStepper(n, p.h, alpha=-1.0, beta=1.0, tau=p.tau, dtype=dtype, n_r=32, n_theta=64, tol=TOL[dtype],
+                      scheme=scheme, potential=pot)
+    assert st.substeps == (3 if scheme == "yoshida4" else 1)
+    u = dev(initial(n, half, kx=0.7, ky=-0.3), dtype)
+    u_used = u.cpu().numpy().astype(np.complex128)
+    st.forward(u, steps)
+    err = rel_linf(u.cpu().numpy(), D.evolve(u_used, p, steps))
+    print(f"rel L-inf after {steps} steps: {err:.3e}", flush=True)
+    assert err <= bar
+    st.close()
+
+
+@pytest.mark.parametrize("scheme,pot", [("yoshida4", "split"), ("yoshida4", "periodic")])
+def test_gradient_of_other_schemes_matches_oracle(ps, scheme, pot):
+    print(f"case: L4 gradient 32^2 {scheme} {pot}", flush=True)
+    n, half, steps = 32, 4.0, 4
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.5, tau=2e-2, n_r=16, n_theta=32, scheme=scheme,
+                   potential=pot)
+    st = ps.DSStepper(n, p.h, alpha=1.0, beta=1.5, tau=p.tau, dtype=torch.float64, n_r=16, n_theta=32, tol=1e-12,
+                      scheme=scheme, potential=pot)
+    u = dev(initial(n, half, ky=0.4), torch.float64)
+    loss, g, counts = st.loss_and_grad(u, steps, checkpoint_every=3)
+    assert counts == {"forward_solves": 12, "recomputed_solves": 9, "adjoint_solves": 12}
+    ref_loss, ref_g = D.loss_l4_gradient(u.cpu().numpy(), p, steps)
+    assert abs(float(loss) - ref_loss) <= 1e-12 * ref_loss
+    assert rel_linf(g.cpu().numpy(), ref_g) <= 1e-9
+    st.close()
+
+
 @pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_mass_is_conserved(ps, dtype, bar):
     print(f"case: mass over 100 steps 256^2 {dtype}", flush=True)
