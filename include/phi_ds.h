@@ -8,8 +8,10 @@
  * composition of the exact flows of
  *   A: i v_t = (-d_xx + alpha d_yy) v, exact in Fourier space:
  *      v_hat <- v_hat e^{-i 4 pi^2 (kx^2 - alpha ky^2) s}, k = m/(N h);
- *   B: w = v e^{i s (2 beta |v|^2 + 4 beta Phi[|v|^2])}, pointwise (Sec. 2.3),
- *      Phi from one potential solve of the stepper's own plan:
+ *   B: w = v e^{i s (c_l |v|^2 + c_p Phi[|v|^2])}, pointwise (Sec. 2.3),
+ *      Phi from one potential solve of the stepper's own plan; c_l = 2 beta and
+ *      c_p = 4 beta for eq. 1 (the E-E system of Sec. 3.3, i u_t = -(u_xx + u_yy)
+ *      + chi |u|^2 u + gamma Phi u, has alpha = -1, c_l = -chi, c_p = -gamma):
  *   PHI_DS_STRANG    e^{A tau/2} e^{B tau} e^{A tau/2}            (1 solve per step)
  *   PHI_DS_YOSHIDA4  e^{A a1 tau} e^{B b1 tau} e^{A a2 tau} e^{B b2 tau}
  *                    e^{A a2 tau} e^{B b1 tau} e^{A a1 tau}, b1 = 1/(2 - 2^(1/3)),
@@ -42,8 +44,10 @@ typedef enum { PHI_DS_STRANG = 0, PHI_DS_YOSHIDA4 = 1 } phi_ds_scheme;
 typedef enum { PHI_DS_SPLIT = 0, PHI_DS_PERIODIC = 1 } phi_ds_potential;
 
 typedef struct {
-    double alpha, beta;    /* coefficients of eq. 1 (finite)                */
-    double tau;            /* time step (finite)                            */
+    double alpha;          /* coefficient of u_yy in eq. 1 (finite)              */
+    double c_local;        /* phase coefficient of |u|^2: 2 beta for eq. 1       */
+    double c_potential;    /* phase coefficient of Phi: 4 beta for eq. 1         */
+    double tau;            /* time step (finite)                                 */
     int32_t scheme;        /* phi_ds_scheme                                 */
     int32_t potential;     /* phi_ds_potential                              */
 } phi_ds_options;
@@ -77,8 +81,8 @@ phi_status phi_ds_forward(phi_ds_t ds, void* u, int32_t steps, void* v_store, vo
  * of the same steps from that earlier state wrote (both required).  Each step
  * nonlinear substep of duration s takes one transposed potential solve
  * (phi_solve_adjoint; the periodic operator is symmetric): with
- * w = v e^{i phi}, phi = s (2 beta |v|^2 + 4 beta Phi),
- *   g_v = g_w e^{-i phi} + 2 s (2 beta q + 4 beta A^T q) v,  q = -Im(conj(g_w) w),
+ * w = v e^{i phi}, phi = s (c_l |v|^2 + c_p Phi),
+ *   g_v = g_w e^{-i phi} + 2 s (c_l q + c_p A^T q) v,  q = -Im(conj(g_w) w),
  * and the linear substeps run backwards in time (their adjoints). */
 phi_status phi_ds_backward(phi_ds_t ds, void* g, int32_t steps, const void* v_store, const void* phi_store,
                            void* stream);

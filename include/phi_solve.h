@@ -76,7 +76,7 @@ typedef struct {
     double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
     phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
     uint32_t flags;        /* PHI_COMPONENT_Y | PHI_AUTOTUNE                                     */
-    int32_t bin;           /* bin side of the node sort in fine-grid cells: 4, 8 or 16 (0: 8)    */
+    int32_t bin;           /* bin side of the node sort in fine-grid cells: 4, 8 or 16 (0: 4)    */
     int32_t sub_nodes;     /* most nodes per spreading / interpolation block, 8..64 (0: 64)      */
 } phi_params;
 

@@ -14,6 +14,10 @@ right-hand side into
     B: i w_t = (-2 beta |w|^2 - 4 beta Phi) w   |w| is constant in time, so with
        Phi frozen at the density of the substep's input (Sec. 2.3)
        w(t + s) = w(t) exp(i s (2 beta rho + 4 beta Phi)).
+The coefficients of rho and Phi in the phase, c_local = 2 beta and
+c_potential = 4 beta for eq. 1, can be set apart: the E-E system of Sec. 3.3,
+i u_t = -(u_xx + u_yy) + chi |u|^2 u + gamma Phi u, has alpha = -1,
+c_local = -chi, c_potential = -gamma.
 
 One step of length tau is a composition of these flows (Sec. 2.3):
   "strang"    e^{A tau/2} e^{B tau} e^{A tau/2}, second order;
@@ -70,6 +74,13 @@ class DSParams:
     n_theta: int = 128
     scheme: str = "strang"
     potential: str = "split"
+    c_local: float | None = None        # default 2 beta
+    c_potential: float | None = None    # default 4 beta
+
+    def coefficients(self) -> tuple[float, float]:
+        cl = 2.0 * self.beta if self.c_local is None else self.c_local
+        cp = 4.0 * self.beta if self.c_potential is None else self.c_potential
+        return cl, cp
 
     def split(self) -> SplitParams:
         return SplitParams(n=self.n, h=self.h, n_r=self.n_r, n_theta=self.n_theta)
@@ -106,9 +117,11 @@ def potential_transpose(g: np.ndarray, p: DSParams) -> np.ndarray:
 
 
 def nonlinear_phase(v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
-    """t (2 beta rho + 4 beta Phi[rho]) with rho = |v|^2 (Sec. 2.3, second substep)."""
+    """t (c_local rho + c_potential Phi[rho]) with rho = |v|^2 (Sec. 2.3, second
+    substep; c_local = 2 beta, c_potential = 4 beta for eq. 1)."""
     rho = np.abs(v) ** 2
-    return t * (2.0 * p.beta * rho + 4.0 * p.beta * potential(rho, p))
+    cl, cp = p.coefficients()
+    return t * (cl * rho + cp * potential(rho, p))
 
 
 def nonlinear_flow(v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
@@ -162,16 +175,17 @@ def loss_l4(u: np.ndarray, p: DSParams) -> float:
 def nonlinear_flow_adjoint(g: np.ndarray, v: np.ndarray, p: DSParams, t: float) -> np.ndarray:
     """Gradient with respect to the input v of the second substep, given the
     gradient g with respect to its output w = v e^{i phi(v)},
-    phi = t (2 beta rho + 4 beta A rho), rho = |v|^2, A the Phi operator.
+    phi = t (c_l rho + c_p A rho), rho = |v|^2, A the Phi operator.
 
     dw = e^{i phi} dv + i w dphi, so Re sum conj(g) dw = Re sum conj(g e^{-i phi}) dv
     + sum s dphi with s = Re(conj(g) i w) = -Im(conj(g) w); sum s dphi =
-    sum r drho with r = t (2 beta s + 4 beta A^T s); drho = 2 Re(conj(v) dv), so
+    sum r drho with r = t (c_l s + c_p A^T s); drho = 2 Re(conj(v) dv), so
     the gradient is g e^{-i phi} + 2 r v."""
     ph = nonlinear_phase(v, p, t)
     w = v * np.exp(1j * ph)
     s = -np.imag(np.conj(g) * w)
-    r = t * (2.0 * p.beta * s + 4.0 * p.beta * potential_transpose(s, p))
+    cl, cp = p.coefficients()
+    r = t * (cl * s + cp * potential_transpose(s, p))
     return g * np.exp(-1j * ph) + 2.0 * r * v
 
 

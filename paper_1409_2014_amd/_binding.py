@@ -49,7 +49,8 @@ class PhiPlanInfo(ctypes.Structure):
 
 class PhiDsOptions(ctypes.Structure):
     _fields_ = [
-        ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("tau", ctypes.c_double),
+        ("alpha", ctypes.c_double), ("c_local", ctypes.c_double), ("c_potential", ctypes.c_double),
+        ("tau", ctypes.c_double),
         ("scheme", ctypes.c_int32), ("potential", ctypes.c_int32),
     ]
 

@@ -138,8 +138,9 @@ extern "C" {
 phi_status phi_ds_create(const phi_params* solve, const phi_ds_options* opt, void* stream, phi_ds_t* out) {
     if (!solve || !opt || !out) return err(PHI_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
-    if (!std::isfinite(opt->alpha) || !std::isfinite(opt->beta) || !std::isfinite(opt->tau))
-        return err(PHI_ERR_INVALID_ARG, "alpha, beta and tau must be finite");
+    if (!std::isfinite(opt->alpha) || !std::isfinite(opt->c_local) || !std::isfinite(opt->c_potential) ||
+        !std::isfinite(opt->tau))
+        return err(PHI_ERR_INVALID_ARG, "alpha, the phase coefficients and tau must be finite");
     if (opt->scheme != PHI_DS_STRANG && opt->scheme != PHI_DS_YOSHIDA4)
         return err(PHI_ERR_INVALID_ARG, "unknown scheme");
     if (opt->potential != PHI_DS_SPLIT && opt->potential != PHI_DS_PERIODIC)
@@ -236,7 +237,8 @@ phi_status phi_ds_create(const phi_params* solve, const phi_ds_options* opt, voi
         d.dtype = solve->dtype;
         d.n = n;
         d.log_n = log_n;
-        d.beta = opt->beta;
+        d.c_local = opt->c_local;
+        d.c_potential = opt->c_potential;
         d.h2 = h * h;
         d.n_times = nt;
         for (int i = 0; i < nt; ++i) {

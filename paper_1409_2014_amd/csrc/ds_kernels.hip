@@ -15,8 +15,8 @@
 //                  1/N^2; writes the field and, by mode, rho = |v|^2 (the input
 //                  of the potential solve) or the adjoint source s.
 //
-// The nonlinear substep of duration s (Sec. 2.3: w = v e^{i s (2 beta |v|^2 +
-// 4 beta Phi)}) is pointwise and rides in the next rows_forward; its adjoint
+// The nonlinear substep of duration s (Sec. 2.3: w = v e^{i s (c_l |v|^2 +
+// c_p Phi)}, c_l = 2 beta and c_p = 4 beta for the DS system) is pointwise and rides in the next rows_forward; its adjoint
 // likewise.  The adjoint of a linear substep is the same three passes with
 // conjugated multipliers (the flow backwards in time).
 #include <hip/hip_runtime.h>
@@ -61,11 +61,11 @@ __device__ __forceinline__ cpx<R> mul_tab(cpx<R> x, cpx<R> m) {
     else return {x.x * m.x - x.y * m.y, x.x * m.y + x.y * m.x};
 }
 
-// e^{i phi} with phi = tau (2 beta |v|^2 + 4 beta Phi)
+// e^{i phi} with phi = tau (c_l |v|^2 + c_p Phi)
 template <typename R>
-__device__ __forceinline__ cpx<R> nonlinear_rotation(cpx<R> v, R pot, R tau, R beta) {
+__device__ __forceinline__ cpx<R> nonlinear_rotation(cpx<R> v, R pot, R tau, R cl, R cp) {
     const R rho = v.x * v.x + v.y * v.y;
-    const R ph = tau * (R(2) * beta * rho + R(4) * beta * pot);
+    const R ph = tau * (cl * rho + cp * pot);
     R sn, cs;
     sin_cos(ph, &sn, &cs);
     return {cs, sn};
@@ -87,7 +87,7 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
     cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(D.twr);
     const size_t base = static_cast<size_t>(row0 + g) * N;
-    const R tau = ntau, beta = static_cast<R>(D.beta);
+    const R tau = ntau, cl = static_cast<R>(D.c_local), cp = static_cast<R>(D.c_potential);
     cpx<R> a[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -96,12 +96,12 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
         if constexpr (MODE == static_cast<int>(DsRowIn::Plain)) {
             a[i] = xv;
         } else if constexpr (MODE == static_cast<int>(DsRowIn::Nonlinear)) {
-            a[i] = cmul(xv, nonlinear_rotation(xv, pot[idx], tau, beta));
+            a[i] = cmul(xv, nonlinear_rotation(xv, pot[idx], tau, cl, cp));
         } else {
-            // adjoint of the nonlinear substep: g e^{-i phi} + 2 tau (2 beta s + 4 beta t) v
+            // adjoint of the nonlinear substep: g e^{-i phi} + 2 tau (c_l q + c_p t) v
             const cpx<R> vv = v[idx];
-            const cpx<R> e = nonlinear_rotation(vv, pot[idx], tau, beta);
-            const R r = R(2) * tau * (R(2) * beta * s[idx] + R(4) * beta * t[idx]);
+            const cpx<R> e = nonlinear_rotation(vv, pot[idx], tau, cl, cp);
+            const R r = R(2) * tau * (cl * s[idx] + cp * t[idx]);
             a[i] = {xv.x * e.x + xv.y * e.y + r * vv.x, xv.y * e.x - xv.x * e.y + r * vv.y};
         }
     }
@@ -181,7 +181,7 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
     for (int i = 0; i < 16; ++i) a[i] = lds[lds_pad(tid + NT * i)];
     fft_reg<R, LOG, 1>(a, lds, tw, tid);
     const R scale = static_cast<R>(1.0 / (static_cast<double>(N) * N));
-    const R tau = ntau, beta = static_cast<R>(D.beta);
+    const R tau = ntau, cl = static_cast<R>(D.c_local), cp = static_cast<R>(D.c_potential);
     const size_t base = static_cast<size_t>(row0 + g) * N;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -193,7 +193,7 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
         } else if constexpr (MODE == static_cast<int>(DsRowOut::AdjointSource)) {
             // s = -Im(conj(g) w), w = v e^{i phi}: the nonlinear substep's output
             const cpx<R> vv = v[idx];
-            const cpx<R> w = cmul(vv, nonlinear_rotation(vv, pot[idx], tau, beta));
+            const cpx<R> w = cmul(vv, nonlinear_rotation(vv, pot[idx], tau, cl, cp));
             out_r[idx] = -(f.x * w.y - f.y * w.x);
         }
     }

@@ -15,7 +15,7 @@ constexpr int kDsMaxTimes = 4;   // distinct linear-substep durations of a compo
 struct DsDev {
     phi_dtype dtype;
     int n, log_n;
-    double beta, h2;
+    double c_local, c_potential, h2;   // phase = s (c_local rho + c_potential Phi)
     // Fourier multipliers of the linear substep in FFT order (index m -> k = m/(N h)
     // for m < N/2, (m - N)/(N h) otherwise), one pair per distinct duration s_i:
     const void* ex[kDsMaxTimes];   // [N] e^{-i 4 pi^2 kx^2 s_i}
@@ -32,8 +32,8 @@ constexpr int kDsReduceBlocks = 512;
 // Pointwise update fused into the row pass that starts a linear substep.
 enum class DsRowIn {
     Plain = 0,       // x = u
-    Nonlinear = 1,   // x = v e^{i phi}, phi = tau (2 beta |v|^2 + 4 beta Phi)
-    Adjoint = 2,     // x = g e^{-i phi} + 2 tau (2 beta s + 4 beta t) v
+    Nonlinear = 1,   // x = v e^{i phi}, phi = s (c_l |v|^2 + c_p Phi)
+    Adjoint = 2,     // x = g e^{-i phi} + 2 s (c_l q + c_p t) v
 };
 // Outputs of the row pass that completes a linear substep.
 enum class DsRowOut {

@@ -31,7 +31,10 @@ class DSStepper:
 
         DSStepper(n, h, alpha=1.0, beta=1.0, tau=1e-3, dtype=torch.float64,
                   scheme="strang" | "yoshida4", potential="split" | "periodic",
-                  n_r=64, n_theta=128, tol=None, ...)
+                  c_local=None, c_potential=None, n_r=64, n_theta=128, tol=None, ...)
+
+    The nonlinear substep's phase is s (c_local |u|^2 + c_potential Phi), by
+    default c_local = 2 beta and c_potential = 4 beta (eq. 1).
 
     The remaining keyword arguments configure the potential solve (as Plan).
     Fields are complex tensors (complex128 for float64, complex64 for float32)
@@ -39,7 +42,7 @@ class DSStepper:
 
     def __init__(self, n: int, h: float, *, alpha: float = 1.0, beta: float = 1.0, tau: float = 1e-3,
                  dtype=torch.float64, device=None, scheme: str = "strang", potential: str = "split",
-                 **solve_kwargs):
+                 c_local: float | None = None, c_potential: float | None = None, **solve_kwargs):
         if not torch.cuda.is_available():
             raise RuntimeError("the DS stepper needs a ROCm GPU (torch.cuda is not available)")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
@@ -51,7 +54,9 @@ class DSStepper:
         self.alpha, self.beta, self.tau = float(alpha), float(beta), float(tau)
         self.scheme, self.potential = scheme, potential
         params = make_params(n, h, dtype=dtype, **solve_kwargs)
-        opts = B.PhiDsOptions(self.alpha, self.beta, self.tau, B.PHI_DS_SCHEMES[scheme],
+        self.c_local = 2.0 * self.beta if c_local is None else float(c_local)
+        self.c_potential = 4.0 * self.beta if c_potential is None else float(c_potential)
+        opts = B.PhiDsOptions(self.alpha, self.c_local, self.c_potential, self.tau, B.PHI_DS_SCHEMES[scheme],
                               B.PHI_DS_POTENTIALS[potential])
         self._handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):

@@ -107,6 +107,22 @@ def test_other_schemes_match_oracle_stepper(ps, scheme, pot, dtype, bar):
     st.close()
 
 
+def test_independent_phase_coefficients_match_oracle(ps):
+    """The E-E system's nonlinear substep (c_local = -chi, c_potential = -gamma)."""
+    print("case: stepper E-E coefficients 64^2", flush=True)
+    n, half, steps = 64, 8.0, 5
+    p = D.DSParams(n=n, h=2 * half / n, alpha=-1.0, tau=2e-3, n_r=32, n_theta=64, scheme="yoshida4",
+                   c_local=1.0, c_potential=-1.0)
+    st = ps.DSStepper(n, p.h, alpha=-1.0, c_local=1.0, c_potential=-1.0, tau=p.tau, dtype=torch.float64,
+                      n_r=32, n_theta=64, tol=1e-12, scheme="yoshida4")
+    x, y, _ = W.grid_2d(n, half)
+    u0 = (4 * np.exp(-(x ** 2 + y ** 2) / 4)).astype(np.complex128)
+    u = dev(u0, torch.float64)
+    st.forward(u, steps)
+    assert rel_linf(u.cpu().numpy(), D.evolve(u0, p, steps)) <= 1e-10
+    st.close()
+
+
 @pytest.mark.parametrize("scheme,pot", [("yoshida4", "split"), ("yoshida4", "periodic")])
 def test_gradient_of_other_schemes_matches_oracle(ps, scheme, pot):
     print(f"case: L4 gradient 32^2 {scheme} {pot}", flush=True)

@@ -191,15 +191,15 @@ def test_plan_creation_without_a_device_fails_with_a_status(lib):
     arr = (B.PhiParams * 2)(p, p)
     assert lib.phi_plan_batch(arr, 2, None, ctypes.byref(h)) == 5 and not h.value
     assert lib.phi_plan_batch(arr, 0, None, ctypes.byref(h)) == 1
-    opts = B.PhiDsOptions(1.0, 1.0, 1e-3, 0, 0)
+    opts = B.PhiDsOptions(1.0, 2.0, 4.0, 1e-3, 0, 0)
     assert lib.phi_ds_create(ctypes.byref(p), ctypes.byref(opts), None, ctypes.byref(h)) == 5 and not h.value
     small = B.PhiParams()
     assert lib.phi_params_default(ctypes.byref(small), 64, 0.25, B.PHI_F32) == 0
     arr2 = (B.PhiParams * 1)(small)
     assert lib.phi_plan_batch(arr2, 1, None, ctypes.byref(h)) == 2          # side below 128
-    bad = B.PhiDsOptions(float("nan"), 1.0, 1e-3, 0, 0)
+    bad = B.PhiDsOptions(float("nan"), 2.0, 4.0, 1e-3, 0, 0)
     assert lib.phi_ds_create(ctypes.byref(small), ctypes.byref(bad), None, ctypes.byref(h)) == 1
-    bad = B.PhiDsOptions(1.0, 1.0, 1e-3, 7, 0)
+    bad = B.PhiDsOptions(1.0, 2.0, 4.0, 1e-3, 7, 0)
     assert lib.phi_ds_create(ctypes.byref(small), ctypes.byref(bad), None, ctypes.byref(h)) == 1
     tiny = B.PhiParams()
     assert lib.phi_params_default(ctypes.byref(tiny), 8, 0.25, B.PHI_F64) == 0

@@ -124,6 +124,20 @@ def test_short_time_evolution_of_the_exact_lump(scheme, pot):
     assert np.linalg.norm(u - ex) / np.linalg.norm(ex) < 0.02
 
 
+def test_coefficients_default_to_the_ds_system():
+    """c_local = 2 beta and c_potential = 4 beta reproduce eq. 1's nonlinear
+    substep; setting them apart changes only that substep's phase."""
+    n, half = 16, 4.0
+    x, y, _ = W.grid_2d(n, half)
+    v = (np.exp(-(x ** 2 + y ** 2) / 2) * np.exp(0.2j * x)).astype(np.complex128)
+    base = dict(n=n, h=2 * half / n, beta=0.7, n_r=12, n_theta=24)
+    a = D.nonlinear_flow(v, D.DSParams(**base), 0.1)
+    b = D.nonlinear_flow(v, D.DSParams(c_local=1.4, c_potential=2.8, **base), 0.1)
+    assert np.array_equal(a, b)
+    c = D.nonlinear_flow(v, D.DSParams(c_local=1.4, c_potential=0.0, **base), 0.1)
+    assert np.max(np.abs(c - v * np.exp(0.1j * 1.4 * np.abs(v) ** 2))) < 1e-15
+
+
 def test_yoshida_composition_is_fourth_order():
     """A smooth field on a coarse grid keeps the step in the asymptotic regime:
     halving tau divides the error by 16 (the symmetric composition: by 4)."""
@@ -146,11 +160,13 @@ def test_yoshida_linear_part_is_the_exact_flow():
     assert np.max(np.abs(got - gaussian_free_flow(x, y, 0.2, 1.0, 1.5, -1.0))) < 1e-12
 
 
-@pytest.mark.parametrize("scheme,pot", [("yoshida4", "split"), ("strang", "periodic"), ("yoshida4", "periodic")])
-def test_gradient_of_other_schemes_matches_central_differences(scheme, pot):
+@pytest.mark.parametrize("scheme,pot,coef", [("yoshida4", "split", None), ("strang", "periodic", None),
+                                            ("yoshida4", "periodic", None), ("strang", "split", (1.0, -1.0))])
+def test_gradient_of_other_schemes_matches_central_differences(scheme, pot, coef):
     n, half = 16, 4.0
+    cl, cp = coef if coef else (None, None)
     p = D.DSParams(n=n, h=2 * half / n, alpha=-1.0, beta=1.5, tau=2e-2, n_r=12, n_theta=24, scheme=scheme,
-                   potential=pot)
+                   potential=pot, c_local=cl, c_potential=cp)
     x, y, _ = W.grid_2d(n, half)
     u0 = (np.exp(-(x ** 2 + 2 * y ** 2)) * np.exp(0.4j * y)).astype(np.complex128)
     steps = 2
@@ -178,7 +194,7 @@ def _ds_pins_hold():
                test_reverse_mode_gradient_matches_central_differences,
                test_yoshida_composition_is_fourth_order,
                lambda: test_short_time_evolution_of_the_exact_lump("yoshida4", "split"),
-               lambda: test_gradient_of_other_schemes_matches_central_differences("yoshida4", "split")):
+               lambda: test_gradient_of_other_schemes_matches_central_differences("yoshida4", "split", None)):
         try:
             fn()
             checks.append(True)
@@ -220,7 +236,7 @@ def _adj_local_only(g, v, p, t):
     ph = D.nonlinear_phase(v, p, t)
     w = v * np.exp(1j * ph)
     s = -np.imag(np.conj(g) * w)
-    return g * np.exp(-1j * ph) + 2.0 * (t * 2.0 * p.beta * s) * v
+    return g * np.exp(-1j * ph) + 2.0 * (t * p.coefficients()[0] * s) * v
 
 
 def _adjoint_without_potential_term(monkeypatch):
