@@ -57,6 +57,8 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
 
 /* phi_params.flags */
 #define PHI_COMPONENT_Y 1u   /* multiplier -ky^2/|k|^2 instead of -kx^2/|k|^2 (their sum is -1) */
+#define PHI_RADIAL_JACOBI 4u /* radial rule Gauss-Jacobi(0, 1) on [0, c] (weight r built in; the rule
+                                Sec. 2.1 names) instead of Gauss-Legendre with r in the weight */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
                                 subproblem sizes {32, 64} on the device and keep the fastest; the
                                 choice is visible in phi_plan_info.bin / .sub_nodes.  Results of
@@ -187,6 +189,8 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
 
 /* Host-only helpers used by the plan (exported for CPU tests). */
 phi_status phi_host_gauss_legendre(int32_t n, double* x, double* w);
+/* Gauss-Jacobi rule for int_{-1}^{1} f(x) (1 + x) dx, nodes ascending. */
+phi_status phi_host_gauss_jacobi01(int32_t n, double* x, double* w);
 /* Exponential-of-semicircle kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| < 1,
  * and its Fourier integral int_{-1}^{1} phi(z) cos(omega z) dz at omega[i]. */
 phi_status phi_host_es_kernel(int32_t count, const double* z, double beta, double* out);

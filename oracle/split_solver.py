@@ -84,6 +84,7 @@ class SplitParams:
     cutoff: float | None = None
     eps_split: float = 1e-16
     component: str = "xx"
+    radial: str = "legendre"    # or "jacobi": Gauss-Jacobi(0, 1), the weight r built in
 
     @property
     def half_width(self) -> float:
@@ -162,12 +163,24 @@ def i1_padded_dft_matrix(rho: np.ndarray, p: SplitParams) -> np.ndarray:
 
 
 def polar_nodes_weights(p: SplitParams):
-    """Radial Gauss-Legendre nodes/weights on [0, c] (Jacobian r folded into the
-    weight) and the azimuthal trapezoid nodes/weight (Sec. 2.1, eq. 12)."""
+    """Radial nodes/weights on [0, c] for int_0^c f(r) r dr and the azimuthal
+    trapezoid nodes/weight (Sec. 2.1, eq. 12).
+
+    "legendre": Gauss-Legendre with the Jacobian r folded into the weight,
+    r_i = c (1 + x_i)/2, weight (c/2) w_i r_i.  "jacobi": the Gauss-Jacobi rule
+    for the weight (1 + x) on [-1, 1] (the rule the paper names), which has the
+    Jacobian as its weight function: r_i = c (1 + x_i)/2, weight (c/2)^2 w_i.
+    scipy's Gauss-Jacobi routine serves as the rule."""
     _, c = split_constants(p)
-    x, w = np.polynomial.legendre.leggauss(p.n_r)
-    r = 0.5 * c * (1.0 + x)
-    w_r = 0.5 * c * w * r
+    if p.radial == "jacobi":
+        from scipy.special import roots_jacobi
+        x, w = roots_jacobi(p.n_r, 0.0, 1.0)
+        r = 0.5 * c * (1.0 + x)
+        w_r = 0.25 * c * c * w
+    else:
+        x, w = np.polynomial.legendre.leggauss(p.n_r)
+        r = 0.5 * c * (1.0 + x)
+        w_r = 0.5 * c * w * r
     theta = 2.0 * np.pi * np.arange(p.n_theta) / p.n_theta
     w_t = 2.0 * np.pi / p.n_theta
     return r, w_r, theta, w_t

@@ -781,6 +781,12 @@ phi_status phi_host_gauss_legendre(int32_t n, double* x, double* w) {
     return PHI_OK;
 }
 
+phi_status phi_host_gauss_jacobi01(int32_t n, double* x, double* w) {
+    if (n < 1 || !x || !w) return fail(nullptr, PHI_ERR_INVALID_ARG, "bad Gauss-Jacobi arguments");
+    phi::gauss_jacobi01(n, x, w);
+    return PHI_OK;
+}
+
 phi_status phi_host_es_kernel(int32_t count, const double* z, double beta, double* out) {
     if (count < 0 || (count > 0 && (!z || !out))) return fail(nullptr, PHI_ERR_INVALID_ARG, "bad arguments");
     for (int i = 0; i < count; ++i) out[i] = phi::es_kernel(z[i], beta);

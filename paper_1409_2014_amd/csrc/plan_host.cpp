@@ -97,6 +97,50 @@ void gauss_legendre(int n, double* x, double* w) {
     if (n % 2 == 1) x[n / 2] = 0.0;
 }
 
+// Gauss-Jacobi rule for the weight (1 + x) on [-1, 1] (alpha = 0, beta = 1),
+// nodes ascending.  P_n = P_n^{(0,1)} from the three-term recurrence
+//   (k+1)(2k-1) P_k = ((2k+1)(2k-1) x - 1) P_{k-1} - (k-1)(2k+1) P_{k-2},
+// P_0 = 1, P_1 = (3x - 1)/2, its derivative from
+//   (2n+1)(1 - x^2) P_n' = -n (1 + (2n+1) x) P_n + 2 n (n+1) P_{n-1},
+// Newton from the asymptotic zeros cos((k - 1/4) pi / (n + 1)), and the
+// weights 4 / ((1 - x^2) P_n'(x)^2).
+void gauss_jacobi01(int n, double* x, double* w) {
+    auto jacobi = [n](double z, double* pn, double* pn1) {
+        double p0 = 1.0, p1 = 0.5 * (3.0 * z - 1.0);
+        if (n == 1) {
+            *pn = p1;
+            *pn1 = p0;
+            return;
+        }
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = (((2.0 * k + 1.0) * (2.0 * k - 1.0) * z - 1.0) * p1 - (k - 1.0) * (2.0 * k + 1.0) * p0) /
+                              ((k + 1.0) * (2.0 * k - 1.0));
+            p0 = p1;
+            p1 = p2;
+        }
+        *pn = p1;
+        *pn1 = p0;
+    };
+    auto deriv = [n](double z, double pn, double pn1) {
+        return (-n * (1.0 + (2.0 * n + 1.0) * z) * pn + 2.0 * n * (n + 1.0) * pn1) / ((2.0 * n + 1.0) * (1.0 - z * z));
+    };
+    for (int k = 1; k <= n; ++k) {
+        double z = std::cos((k - 0.25) * kPi / (n + 1.0));
+        for (int it = 0; it < 100; ++it) {
+            double pn, pn1;
+            jacobi(z, &pn, &pn1);
+            const double dz = pn / deriv(z, pn, pn1);
+            z -= dz;
+            if (std::fabs(dz) < 1e-16 * std::max(1.0, std::fabs(z))) break;
+        }
+        double pn, pn1;
+        jacobi(z, &pn, &pn1);
+        const double d = deriv(z, pn, pn1);
+        x[n - k] = z;                       // k = 1 is the largest zero
+        w[n - k] = 4.0 / ((1.0 - z * z) * d * d);
+    }
+}
+
 double es_kernel(double z, double beta) {
     if (!(std::fabs(z) < 1.0)) return 0.0;
     return std::exp(beta * (std::sqrt(1.0 - z * z) - 1.0));
@@ -221,7 +265,9 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
         *err = fmt("tol %g outside [%g, 0.1] for this dtype", p->tol, tol_min);
         return PHI_ERR_TOL_UNREACHABLE;
     }
-    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_AUTOTUNE)) != 0) { *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG; }
+    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_AUTOTUNE | PHI_RADIAL_JACOBI)) != 0) {
+        *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG;
+    }
     if (p->bin != 0 && p->bin != 4 && p->bin != 8 && p->bin != kMaxBinSize) {
         *err = "bin must be 0, 4, 8 or 16"; return PHI_ERR_INVALID_ARG;
     }
@@ -236,6 +282,7 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->n_theta = p->n_theta;
     hp->n_nodes = p->n_r * p->n_theta;
     hp->component_y = (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
+    hp->radial_jacobi = (p->flags & PHI_RADIAL_JACOBI) ? 1 : 0;
     hp->dtype = p->dtype;
     hp->h = p->hx;
     hp->half_width = 0.5 * n * p->hx;
@@ -275,7 +322,8 @@ void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double
     // theta_j = 2 pi j / N_theta with weight 2 pi / N_theta;
     // q_ij = -w_r w_theta cos^2(theta_j) exp(-r_i^2 / sigma^2)   (sin^2 for the y component).
     std::vector<double> gx(hp.n_r), gw(hp.n_r);
-    gauss_legendre(hp.n_r, gx.data(), gw.data());
+    if (hp.radial_jacobi) gauss_jacobi01(hp.n_r, gx.data(), gw.data());
+    else gauss_legendre(hp.n_r, gx.data(), gw.data());
     const int m = hp.n_r * hp.n_theta;
     kx->resize(m);
     ky->resize(m);
@@ -283,7 +331,9 @@ void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double
     const double wt = 2.0 * kPi / hp.n_theta;
     for (int i = 0; i < hp.n_r; ++i) {
         const double r = 0.5 * hp.cutoff * (1.0 + gx[i]);
-        const double wr = 0.5 * hp.cutoff * gw[i] * r;
+        // Gauss-Jacobi(0, 1) carries the Jacobian r as its weight (1 + x);
+        // Gauss-Legendre gets it folded into the weight
+        const double wr = hp.radial_jacobi ? 0.25 * hp.cutoff * hp.cutoff * gw[i] : 0.5 * hp.cutoff * gw[i] * r;
         const double damp = std::exp(-(r * r) / (hp.sigma * hp.sigma));
         for (int j = 0; j < hp.n_theta; ++j) {
             // angle 2 pi j / N_theta evaluated as pi * (2j / N_theta) in [0, 2 pi)

@@ -27,6 +27,7 @@ struct HostPlan {
     int log_fine = 0;
     int n_r = 0, n_theta = 0, n_nodes = 0;
     int component_y = 0;
+    int radial_jacobi = 0;      // Gauss-Jacobi(0, 1) radial rule instead of Gauss-Legendre
     phi_dtype dtype = PHI_F64;
     double h = 0, half_width = 0, sigma = 0, cutoff = 0;
     // NUFFT kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1, z = offset / (w/2)
@@ -64,6 +65,8 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err);
 phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err);
 
 void gauss_legendre(int n, double* x, double* w);
+// Gauss-Jacobi rule for the weight (1 + x) on [-1, 1], nodes ascending.
+void gauss_jacobi01(int n, double* x, double* w);
 // e^{-2 pi i m / n} with the angle reduced to the first octant (FP64).
 void unit_root(long long m, long long n, double* re, double* im);
 // Twiddles of the register-resident FFT of length 2^log (layout documented in

@@ -31,7 +31,7 @@ def _dtype_code(dtype) -> int:
 def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta: int = 128,
                 tol: float | None = None, sigma: float | None = None, cutoff: float | None = None,
                 component: str = "x", pad: int = 2, bin: int = 0, sub_nodes: int = 0,
-                autotune: bool = False) -> B.PhiParams:
+                autotune: bool = False, radial: str = "legendre") -> B.PhiParams:
     code = _dtype_code(dtype)
     p = B.PhiParams()
     B.check(B.lib().phi_params_default(ctypes.byref(p), int(n), float(h), code))
@@ -42,7 +42,8 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
     p.pad = int(pad)
     p.sigma = float(sigma) if sigma else 0.0
     p.cutoff = float(cutoff) if cutoff else 0.0
-    p.flags = (B.PHI_COMPONENT_Y if component in ("y", "yy") else 0) | (B.PHI_AUTOTUNE if autotune else 0)
+    p.flags = ((B.PHI_COMPONENT_Y if component in ("y", "yy") else 0) | (B.PHI_AUTOTUNE if autotune else 0)
+               | (B.PHI_RADIAL_JACOBI if radial == "jacobi" else 0))
     p.bin = int(bin)
     p.sub_nodes = int(sub_nodes)
     return p
@@ -68,6 +69,13 @@ def host_gauss_legendre(n: int):
     x = np.empty(n)
     w = np.empty(n)
     B.check(B.lib().phi_host_gauss_legendre(int(n), _dptr(x), _dptr(w)))
+    return x, w
+
+
+def host_gauss_jacobi01(n: int):
+    x = np.empty(n)
+    w = np.empty(n)
+    B.check(B.lib().phi_host_gauss_jacobi01(int(n), _dptr(x), _dptr(w)))
     return x, w
 
 

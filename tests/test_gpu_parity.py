@@ -305,3 +305,17 @@ def test_autotuned_plan_matches_oracle(ps):
     ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=64, n_theta=128))
     assert rel_linf(got, ref) <= 1e-6
     assert rel_l2(got, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-10), (torch.float32, 1e-6)])
+def test_jacobi_radial_rule_and_the_papers_node_counts(ps, dtype, bar):
+    """The paper's own variant of the quadrature: Gauss-Jacobi radial rule and
+    60 x 60 polar nodes (Sec. 2.1), against the oracle with the same rule."""
+    print(f"case: Gauss-Jacobi 60x60 256^2 {dtype}", flush=True)
+    n, half = 256, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(13, 8, 4.0, (0.5, 1.5)))
+    tol = 1e-12 if dtype == torch.float64 else 1e-7
+    plan, rho_used, got = run_solve(ps, rho, n, 2 * half / n, dtype, n_r=60, n_theta=60, tol=tol, radial="jacobi")
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=60, n_theta=60, radial="jacobi"))
+    assert rel_linf(got, ref) <= bar
+    assert rel_l2(got, ref) <= bar

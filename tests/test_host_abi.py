@@ -207,3 +207,47 @@ def test_plan_creation_without_a_device_fails_with_a_status(lib):
     # entry points on handles that were never created
     assert lib.phi_ds_forward(ctypes.c_void_p(4321), ctypes.c_void_p(1), 1, None, None, None) == 1
     assert lib.phi_ds_destroy(None) == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 32, 64, 257, 1024])
+def test_gauss_jacobi_rule_against_golub_welsch(lib, n):
+    """The host Gauss-Jacobi(0, 1) rule against the eigenvalues of the Jacobi
+    matrix of its orthogonal polynomials (Golub-Welsch), an independent route,
+    and its defining exactness: sum_i w_i P_k(x_i) = int (1 + x) P_k(x) dx
+    (2, 2/3, then 0) for every Legendre polynomial of degree k <= 2n - 1."""
+    import paper_1409_2014_amd.solver as S
+    x, w = S.host_gauss_jacobi01(n)
+    # recurrence coefficients of the monic Jacobi(0, 1) polynomials
+    k = np.arange(n, dtype=np.float64)
+    a, b = 0.0, 1.0
+    diag = (b * b - a * a) / ((2 * k + a + b) * (2 * k + a + b + 2))
+    kk = np.arange(1, n, dtype=np.float64)
+    off = np.sqrt(4 * kk * (kk + a) * (kk + b) * (kk + a + b)
+                  / ((2 * kk + a + b) ** 2 * (2 * kk + a + b + 1) * (2 * kk + a + b - 1)))
+    ev, vec = np.linalg.eigh(np.diag(diag) + np.diag(off, 1) + np.diag(off, -1))
+    wref = 2.0 * vec[0, :] ** 2          # mu_0 = int (1 + x) dx = 2
+    assert np.all(np.diff(x) > 0)
+    assert np.max(np.abs(x - ev)) < 1e-13
+    # eigenvector weights carry an error of a few n eps; the weights near
+    # x = -1 vanish like (1 + x)
+    big = wref > 1e-6 * np.max(wref)
+    assert np.max(np.abs(w - wref)[big] / wref[big]) < 1e-10
+    degrees = range(0, 2 * n) if n <= 64 else sorted({*range(8), *range(0, 2 * n, 97), 2 * n - 2, 2 * n - 1})
+    for deg in degrees:
+        c = np.zeros(deg + 1)
+        c[deg] = 1.0
+        expect = 2.0 if deg == 0 else (2.0 / 3.0 if deg == 1 else 0.0)
+        assert abs(np.sum(w * np.polynomial.legendre.legval(x, c)) - expect) < 1e-13, deg
+
+
+def test_plan_nodes_with_the_jacobi_rule_equal_the_oracle(lib):
+    import paper_1409_2014_amd.solver as S
+    kw = dict(n=64, h=0.25, n_r=24, n_theta=48, radial="jacobi")
+    kx, ky, q = S.host_polar_nodes(**kw)
+    okx, oky, oq = O.polar_rule(O.SplitParams(n=64, h=0.25, n_r=24, n_theta=48, radial="jacobi"))
+    a = np.stack([kx, ky, q], axis=1)
+    b = np.stack([okx, oky, oq], axis=1)
+    # sort on rounded positions: angles evaluated in two ways differ in the last bit
+    a = a[np.lexsort((np.round(a[:, 1], 10), np.round(a[:, 0], 10)))]
+    b = b[np.lexsort((np.round(b[:, 1], 10), np.round(b[:, 0], 10)))]
+    assert np.max(np.abs(a - b)) < 1e-15

@@ -329,3 +329,25 @@ def test_brute_force_tiny_grid():
     parts = O.phi_parts(rho, p)
     assert np.max(np.abs(parts["i1"] - i1)) < 1e-13
     assert np.max(np.abs(parts["i2"] - i2)) < 1e-13
+
+
+@pytest.mark.parametrize("n_r", [3, 8, 21])
+def test_jacobi_radial_rule_is_exact_to_degree_2n_minus_1(n_r):
+    """The Gauss-Jacobi(0, 1) radial rule integrates int_0^c r^k r dr exactly for
+    k <= 2 n_r - 1 (one degree beyond the Legendre rule with the Jacobian in
+    its weight), and not for k = 2 n_r."""
+    p = O.SplitParams(n=64, h=0.25, n_r=n_r, n_theta=16, radial="jacobi")
+    r, w, _, _ = O.polar_nodes_weights(p)
+    _, c = O.split_constants(p)
+    exact = lambda k: c ** (k + 2) / (k + 2)
+    for k in range(0, 2 * n_r):
+        assert abs(np.sum(w * r ** k) - exact(k)) <= 1e-13 * exact(k), k
+    if n_r <= 8:     # beyond, the error constant of degree 2 n_r falls below rounding
+        assert abs(np.sum(w * r ** (2 * n_r)) - exact(2 * n_r)) > 1e-12 * exact(2 * n_r)
+
+
+def test_jacobi_and_legendre_radial_rules_converge_to_one_value():
+    rho = W.mixture_density(32, 4.0, W.draw_mixture(6, 4, 2.0, (0.6, 1.2)))
+    a = O.phi(rho, O.SplitParams(n=32, h=0.25, n_r=48, n_theta=96))
+    b = O.phi(rho, O.SplitParams(n=32, h=0.25, n_r=48, n_theta=96, radial="jacobi"))
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
