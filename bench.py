@@ -17,8 +17,10 @@ on the host cores.  Further legs (skipped with --no-extra-legs): a batch
 of 256 densities with sides drawn from {128, 256, 512, 1024} at h = 1/32
 (seed 1; autotuned node sorts), forward + transposed solve pairs at
 1024^2 over [-16, 16)^2 (mixture seed 2), 500 split steps of the DS system at
-2048^2 with the checkpointed gradient of the final L4 norm, and the standard
-periodic FFT solver (throughput, and time to accuracy against the split solver).
+2048^2 with the checkpointed gradient of the final L4 norm, the standard
+periodic FFT solver (throughput, and time to accuracy against the split
+solver), and the paper's H-E dynamics comparison at 1024^2 (fourth-order
+splitting with either potential solver against the exact solution).
 """
 from __future__ import annotations
 
@@ -47,10 +49,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_RECORD = {
     "kernel": "cols_highfreq",
     "fetch_kib": 16754.09, "write_kib": 32784.0,
-    "copy_fetch_kib": 131088.375, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "copy_fetch_kib": 131088.5, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
     "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "5653f3ef58bd5eea1bda2bb3a17721524038e8b1bd2d207def26ef0bdb86ee2a",
+    "sha256": "734066fcdb3118585f235040f8080bff646ea51de1c8d4267c2ceac3ebc0494c",
 }
 
 N = 2048
@@ -298,13 +300,25 @@ def stepper_leg(args, torch, ps, W) -> dict:
     return res
 
 
+def example1_exact(x, y):
+    """Sec. 3.1, Example 1: the potential of rho = pi e^{-pi^2 r^2} in closed form,
+    pi [-e^{-q}/2 + (x^2 - y^2) (1 - (1 + q) e^{-q}) / (2 pi^2 r^4)], q = pi^2 r^2,
+    and -pi/2 at the origin.  On the grids timed here every other point has
+    r >= 1/16, so q >= 0.038 and the bracket loses under 1e-13 to cancellation."""
+    r2 = x * x + y * y
+    q = math.pi ** 2 * r2
+    bracket = -np.expm1(-q) - q * np.exp(-q)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        aniso = np.where(r2 > 0.0, (x * x - y * y) * bracket / (2.0 * math.pi ** 2 * r2 * r2), 0.0)
+    return math.pi * (-0.5 * np.exp(-q) + aniso)
+
+
 def periodic_leg(args, torch, ps, W) -> dict:
     """The standard periodic FFT solver (the paper's baseline): solves/s on the C2
     density at 2048^2 (both data paths, graph replay), and the paper's
     time-to-accuracy comparison on Example 1 (rho = pi e^{-pi^2 r^2}): the periodic
     solver on [-32, 32)^2 at h = 1/16 against the split solver on [-8, 8)^2 at
     h = 1/4, FP64, errors against the closed form."""
-    import oracle.closed_forms as C
     res = {}
     rho = W.mixture_density(N, HALF, W.draw_mixture(SEED))
     for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
@@ -326,7 +340,7 @@ def periodic_leg(args, torch, ps, W) -> dict:
     def example1(half, h, split):
         n = int(round(2 * half / h))
         x, y, _ = W.grid_2d(n, half)
-        exact = C.phi_isotropic_gaussian(x, y, math.pi, math.pi ** 2)
+        exact = example1_exact(x, y)
         plan = ps.Plan(n, h, dtype=torch.float64, n_r=N_R, n_theta=N_THETA, tol=TOL64)
         r = torch.as_tensor(W.paper_gaussian_density(n, half), dtype=torch.float64, device="cuda")
         o = torch.empty_like(r)
@@ -349,6 +363,46 @@ def periodic_leg(args, torch, ps, W) -> dict:
     return res
 
 
+def dynamics_leg(args, torch, ps, W) -> dict:
+    """The paper's H-E case I (Sec. 3.2, Tables 7-8): Arkadiev's exact solution of
+    the DS system with alpha = 1, beta = -1 on [-64, 64)^2 at h = 1/8 (1024^2),
+    400 fourth-order split steps (dt = 0.001, 3 potential solves per step) with
+    the potential from the split solver and from the standard periodic FFT
+    solver: wall time and relative l2 errors of u and Phi at T = 0.4."""
+    half, h, steps, tau = 64.0, 0.125, 400, 1e-3
+    n = int(round(2 * half / h))
+    x, y, _ = W.grid_2d(n, half)
+
+    def lump(t):
+        return 2 * np.exp(1j * (2 * y + 4 * t)) / ((x + 1) ** 2 + (y + 4 * t) ** 2 + 1)
+
+    s_end = (x + 1) ** 2 + (y + 4 * 0.4) ** 2 + 1
+    phi_exact = -2 * ((y + 4 * 0.4) ** 2 - x * (x + 2)) / s_end ** 2
+    res = {}
+    for pot in ("split", "periodic"):
+        st = ps.DSStepper(n, h, alpha=1.0, beta=-1.0, tau=tau, dtype=torch.float64, scheme="yoshida4",
+                          potential=pot, n_r=N_R, n_theta=N_THETA, tol=TOL64)
+        u0 = torch.as_tensor(lump(0.0), dtype=torch.complex128, device="cuda").contiguous()
+        w = u0.clone()
+        st.forward(w, 3)
+        torch.cuda.synchronize()
+        u = u0.clone()
+        t0 = time.perf_counter()
+        st.forward(u, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rho = (u.real ** 2 + u.imag ** 2).contiguous()
+        plan = ps.Plan(n, h, dtype=torch.float64, n_r=N_R, n_theta=N_THETA, tol=TOL64)
+        phi = (plan.solve(rho) if pot == "split" else plan.periodic(rho)).cpu().numpy()
+        un = u.cpu().numpy()
+        res[pot] = {"ms_for_400_steps": round(1e3 * dt, 2), "solves": 3 * steps,
+                    "rel_l2_u": float(np.linalg.norm(un - lump(0.4)) / np.linalg.norm(lump(0.4))),
+                    "rel_l2_phi": float(np.linalg.norm(phi - phi_exact) / np.linalg.norm(phi_exact))}
+        st.close()
+        plan.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,9 +410,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (and the error figures that need it)")
-    ap.add_argument("--legs", default="batch,adjoint,stepper,periodic",
+    ap.add_argument("--legs", default="batch,adjoint,stepper,periodic,dynamics",
                     help="comma-separated further legs to run after the 2048^2 single solve "
-                         "(batch, adjoint, stepper, periodic; empty for none)")
+                         "(batch, adjoint, stepper, periodic, dynamics; empty for none)")
     ap.add_argument("--no-extra-legs", action="store_true", help="same as --legs ''")
     ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
                     help="replay each solve from a captured HIP graph (default) or launch it eagerly")
@@ -481,7 +535,7 @@ def main() -> int:
     plan32.close()
     plan64.close()
     legs = set() if args.no_extra_legs else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"batch", "adjoint", "stepper", "periodic"}
+    unknown = legs - {"batch", "adjoint", "stepper", "periodic", "dynamics"}
     if unknown:
         print(f"unknown legs {sorted(unknown)}", file=sys.stderr)
         return 2
@@ -495,6 +549,9 @@ def main() -> int:
     if "periodic" in legs:
         print("[bench] periodic FFT solver", file=sys.stderr, flush=True)
         result["periodic_fft"] = periodic_leg(args, torch, ps, W)
+    if "dynamics" in legs:
+        print("[bench] H-E dynamics at 1024^2", file=sys.stderr, flush=True)
+        result["he_case1_dynamics_1024"] = dynamics_leg(args, torch, ps, W)
     if not args.no_cpu_baseline:
         print("[bench] oracle leg on the host cores", file=sys.stderr, flush=True)
         ref, base = cpu_baseline(rho_used)

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBatchThreads) void kb_nodes(BatchDev B) {
     __shared__ NodeLds<R> s;
     const WorkItem w = B.nodes[blockIdx.x];
     const DevPlan P = B.members[w.member];
-    nodes_body<R, 0>(P, w.item, nullptr, nullptr, s);
+    nodes_body<R, 0, kNodeThreads>(P, w.item, nullptr, nullptr, s);
 }
 
 template <typename R, int DIR>
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBatchThreads) void kb_cols_type1(BatchDev B) {
     __shared__ cpx<R> lds_all[kBatchLds];
     const WorkItem w = B.cols1[blockIdx.x];
     const DevPlan P = B.members[w.member];
-    PHI_BATCH_LOG(P.log_fine, (cols_type1_body<R, LOG_, DIR, batch_lines(LOG_)>(P, w.item, lds_all)));
+    PHI_BATCH_LOG(P.log_fine, (cols_type1_body<R, LOG_, DIR, batch_lines(LOG_), batch_lines(LOG_)>(P, w.item, lds_all)));
 }
 
 template <typename R, int DIR>

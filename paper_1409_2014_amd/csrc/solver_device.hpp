@@ -261,18 +261,22 @@ __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, c
 // and writes its whole tile T to its own slot: no atomics.  The tiles are
 // summed onto the window by cols_type1 through a precomputed index list.
 // MODE 0: all three steps; MODE 1: interp only, out[j] = h^2 c_j (type-2 stage);
-// MODE 2: spread only, of coef (type-1 stage).
-constexpr int kNodeThreads = 256;
+// MODE 2: spread only, of coef (type-1 stage).  NTH threads per block: the
+// order of every sum is fixed by kLanesPerNode and kSpreadParts alone, so
+// blocks of any size give the same bits.
+constexpr int kNodeThreads = 256;         // batched blocks
+constexpr int kNodeThreadsSingle = 256;   // one plan's subproblems
 constexpr int kLanesPerNode = 16;
+constexpr int kSpreadParts = 2;
 constexpr int kTileMax = kMaxBinSize + kMaxKernelWidth - 1;
 
 template <typename R>
 struct NodeLds {
     cpx<R> tile[kTileMax * kTileMax];
-    R psx[kMaxNodesPerSub][kMaxKernelWidth];
-    R psy[kMaxNodesPerSub][kMaxKernelWidth];
+    R taps[kMaxNodesPerSub * 2 * kMaxKernelWidth];   // per node: w x-taps, then w y-taps
     int ox[kMaxNodesPerSub];
     int oy[kMaxNodesPerSub];
+    double qh[kMaxNodesPerSub];   // q_j h^2
     cpx<R> val[kMaxNodesPerSub];
 };
 
@@ -288,56 +292,106 @@ __device__ __forceinline__ void kahan_add(R& s, R& c, R v) {
     }
 }
 
-template <typename R, int MODE>
+// x / d for 0 <= x < 1024 and 1 <= d <= 31 as (x * ceil(2^16 / d)) >> 16: the
+// rounded-up reciprocal adds less than x / 2^16 < 1/64 to x / d, less than
+// the gap 1/d between x / d and the next integer
+__device__ __forceinline__ unsigned small_div_magic(int d) {
+    return (65536u + static_cast<unsigned>(d) - 1u) / static_cast<unsigned>(d);
+}
+__device__ __forceinline__ int small_div(int x, unsigned magic) {
+    return static_cast<int>((static_cast<unsigned>(x) * magic) >> 16);
+}
+
+template <typename R, int MODE, int NTH>
 __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx<R>* __restrict__ coef,
                                            cpx<R>* __restrict__ out, NodeLds<R>& s) {
+    static_assert(NTH % kLanesPerNode == 0 && NTH % kSpreadParts == 0, "whole node and cell groups");
+    static_assert(NTH >= kMaxNodesPerSub, "one thread per node for the node scalars");
+    static_assert(kTileMax * kTileMax < 1024 && kTileMax <= 31 && kMaxKernelWidth * kMaxKernelWidth <= 1024,
+                  "small_div covers the tile and tap indices");
+    constexpr int TPT = (kMaxNodesPerSub * 2 * kMaxKernelWidth + NTH - 1) / NTH;   // taps per thread
+    constexpr int CPT = (kTileMax * kTileMax + NTH - 1) / NTH;                     // tile cells per thread
     const int* sub = P.sub + 4 * sidx;
     const int bx = sub[0], by = sub[1], first = sub[2], count = sub[3];
     const int w = P.width, E = P.tile, q = P.patch, bin = P.bin;
+    const int w2 = 2 * w;
     const int x0 = bx * bin, y0 = by * bin;   // tile corner in window cells
-    const R* taps = static_cast<const R*>(P.taps);
-    // node data
-    for (int e = threadIdx.x; e < count * w; e += kNodeThreads) {
-        const int jj = e / w, t = e - jj * w;
-        const R* tn = taps + static_cast<size_t>(first + jj) * 2 * w;
-        s.psx[jj][t] = tn[t];
-        s.psy[jj][t] = tn[w + t];
+    const unsigned magic_e = small_div_magic(E);
+    // every global load of the block is issued before the first LDS store, so
+    // their latencies overlap: the subproblem's taps (contiguous, w2 per node),
+    // the per-node scalars, the type-2 window tile
+    const R* taps = static_cast<const R*>(P.taps) + static_cast<size_t>(first) * w2;
+    const int n_taps = count * w2;
+    R tv[TPT];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int e = threadIdx.x + k * NTH;
+        tv[k] = e < n_taps ? taps[e] : R(0);
     }
-    for (int jj = threadIdx.x; jj < count; jj += kNodeThreads) {
-        s.ox[jj] = P.cell[2 * (first + jj)] - x0;
-        s.oy[jj] = P.cell[2 * (first + jj) + 1] - y0;
-        if constexpr (MODE == 2) s.val[jj] = coef[first + jj];
+    const int jn = threadIdx.x;
+    const bool has_node = jn < count;
+    int cx = 0, cy = 0;
+    double qv = 0.0;
+    cpx<R> cv = {R(0), R(0)};
+    if (has_node) {
+        cx = P.cell[2 * (first + jn)];
+        cy = P.cell[2 * (first + jn) + 1];
+        if constexpr (MODE == 0) qv = P.q[first + jn];
+        if constexpr (MODE == 2) cv = coef[first + jn];
     }
+    cpx<R> tl[CPT];
     if constexpr (MODE != 2) {
-        // the type-2 window tile; the window side is a power of two and tiles only
-        // wrap when the window is the whole periodic fine grid
+        // the window side is a power of two and tiles only wrap when the window
+        // is the whole periodic fine grid
         const bool whole = (q == P.n_fine);
         const cpx<R>* win = static_cast<const cpx<R>*>(P.win);
-        for (int c = threadIdx.x; c < E * E; c += kNodeThreads) {
-            const int cb = c / E, ca = c - cb * E;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            const int cb = small_div(c, magic_e), ca = c - cb * E;
             int wx = x0 + ca, wy = y0 + cb;
-            bool inside = true;
+            bool inside = c < E * E;
             if (whole) {
                 wx &= q - 1;
                 wy &= q - 1;
             } else {
-                inside = wx < q && wy < q;
+                inside = inside && wx < q && wy < q;
             }
-            s.tile[c] = inside ? win[static_cast<size_t>(wy) * q + wx] : cpx<R>{R(0), R(0)};
+            tl[k] = inside ? win[static_cast<size_t>(wy) * q + wx] : cpx<R>{R(0), R(0)};
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        const int e = threadIdx.x + k * NTH;
+        if (e < n_taps) s.taps[e] = tv[k];
+    }
+    if (has_node) {
+        s.ox[jn] = cx - x0;
+        s.oy[jn] = cy - y0;
+        if constexpr (MODE == 0) s.qh[jn] = qv * P.h2;
+        if constexpr (MODE == 2) s.val[jn] = cv;
+    }
+    if constexpr (MODE != 2) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int c = threadIdx.x + k * NTH;
+            if (c < E * E) s.tile[c] = tl[k];
         }
     }
     __syncthreads();
     if constexpr (MODE != 2) {
         const int lane = threadIdx.x % kLanesPerNode;
-        for (int jj0 = 0; jj0 < count; jj0 += kNodeThreads / kLanesPerNode) {
+        const unsigned magic_w = small_div_magic(w);
+        for (int jj0 = 0; jj0 < count; jj0 += NTH / kLanesPerNode) {
             const int jj = jj0 + threadIdx.x / kLanesPerNode;
             cpx<R> acc = {R(0), R(0)};
             if (jj < count) {
                 const int ox = s.ox[jj], oy = s.oy[jj];
+                const R* tj = s.taps + jj * w2;
                 for (int t = lane; t < w * w; t += kLanesPerNode) {
-                    const int t2 = t / w;
+                    const int t2 = small_div(t, magic_w);
                     const int t1 = t - t2 * w;
-                    const R k = s.psx[jj][t1] * s.psy[jj][t2];
+                    const R k = tj[t1] * tj[w + t2];
                     const cpx<R> b = s.tile[(oy + t2) * E + ox + t1];
                     acc.x += b.x * k;
                     acc.y += b.y * k;
@@ -353,7 +407,7 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
                 if constexpr (MODE == 1) {
                     out[j] = {static_cast<R>(acc.x * P.h2), static_cast<R>(acc.y * P.h2)};
                 } else {
-                    const double scale = P.q[j] * P.h2;
+                    const double scale = s.qh[jj];
                     s.val[jj] = {static_cast<R>(acc.x * scale), static_cast<R>(acc.y * scale)};
                 }
             }
@@ -361,17 +415,17 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
     }
     if constexpr (MODE == 1) return;
     if constexpr (MODE == 0) __syncthreads();
-    // two threads per tile cell, each summing one half of the nodes (in order),
-    // then one fixed shuffle step; the node loop is unrolled and branch-free so
-    // the LDS reads of several nodes are in flight together
+    // kSpreadParts threads per tile cell, each summing one run of the nodes (in
+    // order), then a fixed shuffle tree; the node loop is unrolled and
+    // branch-free so the LDS reads of several nodes are in flight together
     cpx<R>* tile_out = static_cast<cpx<R>*>(P.tiles) + static_cast<size_t>(sidx) * E * E;
     constexpr int U = 8;
-    const int part = threadIdx.x & 1;
-    const int half_count = (count + 1) >> 1;
-    const int j_lo = part ? half_count : 0;
-    const int j_hi = part ? count : half_count;
-    for (int c = threadIdx.x >> 1; c < E * E; c += kNodeThreads / 2) {
-        const int cb = c / E, ca = c - cb * E;
+    const int part = threadIdx.x % kSpreadParts;
+    const int run = (count + kSpreadParts - 1) / kSpreadParts;
+    const int j_lo = min(count, part * run);
+    const int j_hi = min(count, j_lo + run);
+    for (int c = threadIdx.x / kSpreadParts; c < E * E; c += NTH / kSpreadParts) {
+        const int cb = small_div(c, magic_e), ca = c - cb * E;
         R sx = 0, sy = 0, kx = 0, ky = 0;
         for (int j0 = j_lo; j0 < j_hi; j0 += U) {
             R kk[U];
@@ -385,7 +439,8 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
                 const int t2 = cb - s.oy[jc];
                 const bool in = valid && static_cast<unsigned>(t1) < static_cast<unsigned>(w) &&
                                 static_cast<unsigned>(t2) < static_cast<unsigned>(w);
-                const R k = s.psx[jc][in ? t1 : 0] * s.psy[jc][in ? t2 : 0];
+                const R* tj = s.taps + jc * w2;
+                const R k = tj[in ? t1 : 0] * tj[w + (in ? t2 : 0)];
                 kk[u] = in ? k : R(0);
                 vv[u] = s.val[jc];
             }
@@ -396,8 +451,11 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
             }
         }
         R vx = sx - kx, vy = sy - ky;
-        vx += __shfl_xor(vx, 1, 2);
-        vy += __shfl_xor(vy, 1, 2);
+#pragma unroll
+        for (int off = kSpreadParts / 2; off > 0; off >>= 1) {
+            vx += __shfl_xor(vx, off, kSpreadParts);
+            vy += __shfl_xor(vy, off, kSpreadParts);
+        }
         if (part == 0) tile_out[c] = {vx, vy};
     }
 }
@@ -406,33 +464,46 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
 // cols_type1: sum the spread tiles onto one window column, FFT along y (only
 // the Q window inputs are non-zero), keep the N centred rows, times d(n2)
 // ---------------------------------------------------------------------------
-// Window cell (i1, i2) is the sum of the tile entries listed for it, in list
-// order: L = min(4, NT) lanes split the list, then a fixed shuffle tree.
-template <typename R, int LOG, int DIR, int G>
+// A block transforms COLS window columns (COLS = 1 or G).  Window cell
+// (i1, i2) is the sum of the tile entries listed for it, in list order: 4
+// lanes split the list, then a fixed shuffle tree; all threads of the block
+// share the cells of its columns, so with COLS = 1 the length of the lists
+// (set by the node count, not by N) is spread over a whole block at every
+// grid size.  Column c is staged in group c's buffer; group g transforms
+// column g % COLS (with COLS = 1 every group runs the same transform, which the
+// block's barriers need anyway) and groups g < COLS store.
+template <typename R, int LOG, int DIR, int G, int COLS>
 __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
-    constexpr int L = NT < 4 ? NT : 4;
+    constexpr int BT = NT * G;
+    constexpr int L = 4;
+    constexpr int LP = lds_group_stride(F);
+    static_assert(COLS == 1 || COLS == G, "one column per block or one per group");
+    static_assert(BT % L == 0, "the block splits into whole lane groups");
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
-    cpx<R>* lds = lds_all + g * lds_group_stride(F);
+    cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
     const int q = P.patch;
-    const int i1 = i1_base + g;
-    const bool active = i1 < q;
-    // reduced window column, staged at the start of this group's FFT buffer
-    // (q <= F entries); the FFT's first barrier orders these reads before its writes
+    // reduced window columns, staged at the start of their groups' FFT buffers
+    // (q <= F entries); the FFT's first barrier orders the groups' reads of
+    // them before its writes
     const cpx<R>* tiles = static_cast<const cpx<R>*>(P.tiles);
-    for (int i2 = tid / L; i2 < q; i2 += NT / L) {
-        const int cell = (active ? i1 : 0) * q + i2;
+    const int lane = threadIdx.x % L;
+    for (int e = threadIdx.x / L; e < COLS * q; e += BT / L) {
+        const int c = e / q;
+        const int i2 = e - c * q;
+        const int i1 = i1_base + c;
+        const int cell = (i1 < q ? i1 : 0) * q + i2;
         const int k0 = P.contrib_start[cell], k1 = P.contrib_start[cell + 1];
         R sx = 0, sy = 0, kx = 0, ky = 0;
         // batches of U entries per lane: all index loads, then all value loads,
         // then the sums in list order
         constexpr int U = 8;
-        for (int base = k0 + tid % L; base < k1; base += L * U) {
+        for (int base = k0 + lane; base < k1; base += L * U) {
             int idx[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) idx[u] = (base + u * L < k1) ? P.contrib[base + u * L] : -1;
@@ -451,17 +522,21 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
             vx += __shfl_xor(vx, off, L);
             vy += __shfl_xor(vy, off, L);
         }
-        if (tid % L == 0) lds[i2] = {vx, vy};
+        if (lane == 0) lds_all[c * LP + i2] = {vx, vy};
     }
     __syncthreads();
+    const int c = g % COLS;
+    const int i1 = i1_base + c;
+    const bool active = i1 < q;
+    const cpx<R>* staged = lds_all + c * LP;
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int i2 = posmod_dev(tid + NT * i - P.patch_lo, F);
-        v[i] = (active && i2 < q) ? lds[i2] : cpx<R>{R(0), R(0)};
+        v[i] = (active && i2 < q) ? staged[i2] : cpx<R>{R(0), R(0)};
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    if (active) {
+    if (active && g < COLS) {
         cpx<R>* u = static_cast<cpx<R>*>(P.u);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {

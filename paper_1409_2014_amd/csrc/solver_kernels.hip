@@ -52,25 +52,26 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
     cols_highfreq_body<R, LOG, DIR, G>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
+// one window column per block: the Q columns are few, so at small N blocks of
+// several columns would leave most of the chip idle on this critical path
 template <typename R, int LOG, int DIR>
-__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type2(DevPlan P) {
-    constexpr int G = lines_per_block<LOG>();
-    __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    cols_type2_body<R, LOG, DIR, G>(P, blockIdx.x * G, lds_all);
+__global__ __launch_bounds__(FftShape<LOG>::NT) void k_cols_type2(DevPlan P) {
+    __shared__ cpx<R> lds_all[lds_group_stride(1 << LOG)];
+    cols_type2_body<R, LOG, DIR, 1>(P, blockIdx.x, lds_all);
 }
 
 template <typename R, int MODE>
-__global__ __launch_bounds__(kNodeThreads) void k_nodes(DevPlan P, const cpx<R>* __restrict__ coef,
+__global__ __launch_bounds__(kNodeThreadsSingle) void k_nodes(DevPlan P, const cpx<R>* __restrict__ coef,
                                                         cpx<R>* __restrict__ out) {
     __shared__ NodeLds<R> s;
-    nodes_body<R, MODE>(P, blockIdx.x, coef, out, s);
+    nodes_body<R, MODE, kNodeThreadsSingle>(P, blockIdx.x, coef, out, s);
 }
 
 template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type1(DevPlan P) {
     constexpr int G = lines_per_block<LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    cols_type1_body<R, LOG, DIR, G>(P, blockIdx.x * G, lds_all);
+    cols_type1_body<R, LOG, DIR, G, 1>(P, blockIdx.x, lds_all);
 }
 
 template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2>
@@ -120,17 +121,16 @@ hipError_t launch_cols_highfreq(const DevPlan& P, int dir, hipStream_t s) {
 
 template <typename R, int LOG>
 hipError_t launch_cols_type2(const DevPlan& P, int dir, hipStream_t s) {
-    constexpr int G = lines_per_block<LOG>();
-    const int blocks = (P.patch + G - 1) / G;
-    if (dir < 0) hipLaunchKernelGGL((k_cols_type2<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
-    else hipLaunchKernelGGL((k_cols_type2<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
+    const int blocks = P.patch;
+    if (dir < 0) hipLaunchKernelGGL((k_cols_type2<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT), 0, s, P);
+    else hipLaunchKernelGGL((k_cols_type2<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT), 0, s, P);
     return hipGetLastError();
 }
 
 template <typename R, int LOG>
 hipError_t launch_cols_type1(const DevPlan& P, int dir, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
-    const int blocks = (P.patch + G - 1) / G;
+    const int blocks = P.patch;   // one window column per block
     if (dir < 0) hipLaunchKernelGGL((k_cols_type1<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
     else hipLaunchKernelGGL((k_cols_type1<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
     return hipGetLastError();
@@ -207,7 +207,7 @@ hipError_t run_rows_inverse(const DevPlan& P, void* out, int dir, int use_i1, in
 
 template <typename R, int MODE>
 hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t s) {
-    hipLaunchKernelGGL((k_nodes<R, MODE>), dim3(P.n_sub), dim3(kNodeThreads), 0, s, P,
+    hipLaunchKernelGGL((k_nodes<R, MODE>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
                        static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
     return hipGetLastError();
 }
