@@ -57,6 +57,11 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
 
 /* phi_params.flags */
 #define PHI_COMPONENT_Y 1u   /* multiplier -ky^2/|k|^2 instead of -kx^2/|k|^2 (their sum is -1) */
+#define PHI_COMPONENT_XY 8u  /* multiplier -kx ky/|k|^2: the mixed second derivative of the inverse
+                                Laplacian, with -kx^2/|k|^2 and -ky^2/|k|^2 the whole tensor
+                                -k_i k_j/|k|^2 (Sec. 2.1, Remark: the split needs only the
+                                multiplier's values; this one is also bounded, even, and degree-0
+                                homogeneous, so I1 stays smooth at k = 0).  Not with PHI_COMPONENT_Y. */
 #define PHI_RADIAL_JACOBI 4u /* radial rule Gauss-Jacobi(0, 1) on [0, c] (weight r built in; the rule
                                 Sec. 2.1 names) instead of Gauss-Legendre with r in the weight */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
@@ -77,7 +82,7 @@ typedef struct {
     double sigma;          /* partition width (<= 0: sqrt(ln 1e16) / (2 pi (kappa-1) L))       */
     double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
     phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
-    uint32_t flags;        /* PHI_COMPONENT_Y | PHI_AUTOTUNE                                     */
+    uint32_t flags;        /* PHI_COMPONENT_Y or PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI */
     int32_t bin;           /* bin side of the node sort in fine-grid cells: 4, 8 or 16 (0: 4)    */
     int32_t sub_nodes;     /* most nodes per spreading / interpolation block, 8..64 (0: 64)      */
 } phi_params;

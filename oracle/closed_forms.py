@@ -65,6 +65,22 @@ def phi_isotropic_gaussian(x: np.ndarray, y: np.ndarray, amplitude: float = 1.0,
     return amplitude * (-0.5 * np.exp(-q) + aniso)
 
 
+def phi_xy_isotropic_gaussian(x: np.ndarray, y: np.ndarray, amplitude: float = 1.0,
+                              a: float = 1.0) -> np.ndarray:
+    """Phi_xy (multiplier -kx ky/|k|^2) for rho = amplitude e^{-a r^2}:
+
+        Phi_xy = amplitude x y (1 - (1 + a r^2) e^{-a r^2}) / (a r^4),  0 at r = 0.
+
+    -kx ky/|k|^2 = -sin(2 phi_k)/2 is the cos(2 phi_k) part of -kx^2/|k|^2 turned
+    by 45 degrees, and the transform of an isotropic density commutes with
+    rotations, so the (x^2 - y^2) term of phi_isotropic_gaussian becomes 2 x y."""
+    r2 = x * x + y * y
+    q = a * r2
+    bracket = _one_minus_one_plus_q_exp(q)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return amplitude * np.where(r2 > 0.0, x * y * bracket / (a * r2 * r2), 0.0)
+
+
 def phi_arkadiev(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     """Sec. 3.1, Example 2: Phi = -2 (y^2 - (x+1)^2 + 1) / ((x+1)^2 + y^2 + 1)^2."""
     s = (x + 1.0) ** 2 + y * y + 1.0
@@ -82,7 +98,10 @@ def phi_axis_gaussian(xr: np.ndarray, yr: np.ndarray, a: float, b: float,
         Phi_xx = -a b int_0^inf e^{-X^2/(a^2+v) - Y^2/(b^2+v)}
                  / sqrt((a^2+v)(b^2+v)) [1/(2(a^2+v)) - X^2/(a^2+v)^2] dv
 
-    ("yy": swap the roles of (X, a) and (Y, b) in the bracket).  The integral is
+    ("yy": swap the roles of (X, a) and (Y, b) in the bracket).  In general the
+    multiplier -k_i k_j/|k|^2 maps through k_i k_j <-> -(1/(4 pi^2)) d_i d_j of
+    e^{-X^2/A^2 - Y^2/B^2} to the bracket delta_ij/(2 A_i^2) - X_i X_j/(A_i^2 A_j^2),
+    so "xy" has the bracket -X Y/((a^2+v)(b^2+v)).  The integral is
     taken with v = e^u and the trapezoidal rule on u in [umin, umax]: the
     integrand decays exponentially in both directions of u, so the rule
     converges geometrically (a step of 1/8 is converged to rounding).  The
@@ -100,8 +119,12 @@ def phi_axis_gaussian(xr: np.ndarray, yr: np.ndarray, a: float, b: float,
     expo = np.exp(-xf * xf / av - yf * yf / bv)
     if component == "xx":
         bracket = 1.0 / (2.0 * av) - xf * xf / (av * av)
-    else:
+    elif component == "yy":
         bracket = 1.0 / (2.0 * bv) - yf * yf / (bv * bv)
+    elif component == "xy":
+        bracket = -xf * yf / (av * bv)
+    else:
+        raise ValueError(f"unknown component {component}")
     integrand = expo / np.sqrt(av * bv) * bracket * v[None, :]   # dv = v du
     total = step * integrand.sum(axis=1)
     return (-a * b * total).reshape(shape)

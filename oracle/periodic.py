@@ -18,15 +18,21 @@ __all__ = ["periodic_multiplier", "phi_periodic"]
 
 
 def periodic_multiplier(n: int, h: float, component: str = "xx") -> np.ndarray:
-    """-kx^2/|k|^2 (or -ky^2/|k|^2) on the n x n Fourier grid of the box, 0 at k = 0;
-    axis 1 is x."""
+    """-kx^2/|k|^2 (or -ky^2/|k|^2, or -kx ky/|k|^2) on the n x n Fourier grid of
+    the box, 0 at k = 0; axis 1 is x.  The mixed multiplier is odd in each of kx,
+    ky; on the Nyquist lines (index n/2) one DFT bin stands for +k and -k, and
+    the bin takes the mean of the multiplier over them, 0 (also at the corner)."""
     k = np.fft.fftfreq(n, d=h)
-    kx2 = (k ** 2)[None, :]
-    ky2 = (k ** 2)[:, None]
-    k2 = kx2 + ky2
-    num = kx2 if component == "xx" else ky2
+    kx = k[None, :]
+    ky = k[:, None]
+    k2 = kx * kx + ky * ky
+    num = {"xx": kx * kx + 0.0 * ky, "yy": ky * ky + 0.0 * kx, "xy": kx * ky}[component]
     with np.errstate(divide="ignore", invalid="ignore"):
-        return np.where(k2 > 0.0, -num / k2, 0.0)
+        mult = np.where(k2 > 0.0, -num / k2, 0.0)
+    if component == "xy":
+        mult[n // 2, :] = 0.0
+        mult[:, n // 2] = 0.0
+    return mult
 
 
 def phi_periodic(rho: np.ndarray, h: float, component: str = "xx") -> np.ndarray:

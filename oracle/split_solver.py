@@ -73,7 +73,11 @@ class SplitParams:
     sigma    partition width; cutoff  disk radius c (None -> default reading)
     eps_split   target size of the neglected tails (defines the defaults)
     component   "xx": multiplier -kx^2/|k|^2 (the DS potential, eq. 4);
-                "yy": -ky^2/|k|^2 (its companion; the two sum to -1)
+                "yy": -ky^2/|k|^2 (its companion; the two sum to -1);
+                "xy": -kx ky/|k|^2 (the mixed one; with the other two the whole
+                tensor -k_i k_j/|k|^2, another potential the Remark of Sec. 2.1
+                covers: bounded, even and of degree 0, so the split carries over
+                with only the multiplier's values changed)
     """
     n: int
     h: float
@@ -115,7 +119,7 @@ def highfreq_multiplier(kx: np.ndarray, ky: np.ndarray, sigma: float,
     The integrand of I1 (Sec. 2.1, eq. 9) divided by rho_hat.  1 - e^{-s} is
     formed as -expm1(-s) so that it keeps full relative accuracy near k = 0."""
     k2 = kx * kx + ky * ky
-    num = kx * kx if component == "xx" else ky * ky
+    num = {"xx": kx * kx, "yy": ky * ky, "xy": kx * ky}[component]
     out = np.zeros_like(k2)
     nz = k2 > 0.0
     out[nz] = -(num[nz] / k2[nz]) * (-np.expm1(-k2[nz] / sigma ** 2))
@@ -129,6 +133,22 @@ def _padded_frequencies(p: SplitParams) -> tuple[np.ndarray, np.ndarray]:
     return kx, ky
 
 
+def padded_multiplier(p: SplitParams) -> np.ndarray:
+    """g1 on the padded DFT grid.  The mixed multiplier is odd in each of kx,
+    ky, and on the Nyquist lines (index kappa N / 2) one DFT bin stands for +k
+    and -k; the bin takes the mean of the multiplier over them, which is 0 (also
+    at the corner, where numpy's negative representatives alone would give
+    -1/2)."""
+    sigma, _ = split_constants(p)
+    kx, ky = _padded_frequencies(p)
+    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    if p.component == "xy":
+        nyq = (p.kappa * p.n) // 2
+        g1[nyq, :] = 0.0
+        g1[:, nyq] = 0.0
+    return g1
+
+
 def i1_padded_fft(rho: np.ndarray, p: SplitParams) -> np.ndarray:
     """I1 on the grid (Sec. 2.1, eq. 9 by the trapezoidal rule on the padded box).
 
@@ -137,27 +157,23 @@ def i1_padded_fft(rho: np.ndarray, p: SplitParams) -> np.ndarray:
     involve x_n - x_n', so the density sits at the corner of the padded array:
         I1_n = Re[(kappa N)^-2 sum_m g1(k_m) S_m e^{+2 pi i m.n/(kappa N)}],
         S_m  = sum_n P_n e^{-2 pi i m.n/(kappa N)},  P = zero-padded rho."""
-    sigma, _ = split_constants(p)
     m_side = p.kappa * p.n
     padded = np.zeros((m_side, m_side), dtype=np.float64)
     padded[: p.n, : p.n] = rho
     s_hat = np.fft.fft2(padded)                      # S_m (unnormalised DFT)
-    kx, ky = _padded_frequencies(p)
-    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    g1 = padded_multiplier(p)
     full = np.fft.ifft2(g1 * s_hat)                  # includes (kappa N)^-2
     return full[: p.n, : p.n].real.copy()
 
 
 def i1_padded_dft_matrix(rho: np.ndarray, p: SplitParams) -> np.ndarray:
     """Same sum as i1_padded_fft written with explicit DFT matrices (small N only)."""
-    sigma, _ = split_constants(p)
     m_side = p.kappa * p.n
     m = np.arange(m_side)
     n = np.arange(p.n)
     fwd = np.exp(-2j * np.pi * np.outer(m, n) / m_side)    # [m][n]
     s_hat = fwd @ rho @ fwd.T                               # S[m_y][m_x]
-    kx, ky = _padded_frequencies(p)
-    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    g1 = padded_multiplier(p)
     inv = np.exp(+2j * np.pi * np.outer(n, m) / m_side)    # [n][m]
     return (inv @ (g1 * s_hat) @ inv.T).real / m_side ** 2
 
@@ -193,14 +209,14 @@ def polar_rule(p: SplitParams):
     (c/2) w_i r_i (the Jacobian r of eq. 11 folded in); azimuthal trapezoid
     theta_j = 2 pi j / N_theta with weight 2 pi / N_theta.  The I2 weight is
         q_ij = -omega_i omega_j cos^2(theta_j) p(k_ij)      ("xx")
-    (sin^2 for "yy").  Returns flattened arrays kx, ky, q of length N_r N_theta
+    (sin^2 for "yy", cos sin for "xy": the multiplier on the unit circle).  Returns flattened arrays kx, ky, q of length N_r N_theta
     in (radial-major, angle-minor) order."""
     sigma, _ = split_constants(p)
     r, w_r, theta, w_t = polar_nodes_weights(p)
     rr, tt = np.meshgrid(r, theta, indexing="ij")
     kx = rr * np.cos(tt)
     ky = rr * np.sin(tt)
-    ang = np.cos(tt) ** 2 if p.component == "xx" else np.sin(tt) ** 2
+    ang = {"xx": np.cos(tt) ** 2, "yy": np.sin(tt) ** 2, "xy": np.cos(tt) * np.sin(tt)}[p.component]
     q = -(w_r[:, None] * w_t) * ang * np.exp(-(rr ** 2) / sigma ** 2)
     return kx.ravel(), ky.ravel(), q.ravel()
 
@@ -264,12 +280,10 @@ def phi_transpose(g: np.ndarray, p: SplitParams) -> np.ndarray:
            E1[n][j] = e^{+2 pi i k_j.x_n}  ->  A2^T = Re(E2^T . diag(q) . E1^T).
     For a complex matrix C acting on real vectors, (Re C)^T = Re(C^T)."""
     g = np.asarray(g, dtype=np.float64)
-    sigma, _ = split_constants(p)
     m_side = p.kappa * p.n
     padded = np.zeros((m_side, m_side), dtype=np.float64)
     padded[: p.n, : p.n] = g
-    kx, ky = _padded_frequencies(p)
-    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    g1 = padded_multiplier(p)
     a1t = np.fft.fft2(g1 * np.fft.ifft2(padded))[: p.n, : p.n].real
 
     nkx, nky, q = polar_rule(p)

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libphisolve.so")
 PHI_F64 = 0
 PHI_F32 = 1
 PHI_COMPONENT_Y = 1
+PHI_COMPONENT_XY = 8
 PHI_AUTOTUNE = 2
 PHI_RADIAL_JACOBI = 4
 

@@ -60,13 +60,15 @@ __global__ __launch_bounds__(kBatchThreads) void kb_rows_forward(BatchDev B, con
     PHI_BATCH_LOG(P.log_fine, (rows_forward_body<R, LOG_, DIR, batch_lines(LOG_)>(P, rho, w.item, lds_all)));
 }
 
-template <typename R, int DIR>
+// MIXED: the launch over the I1 columns of the members with the mixed
+// multiplier (a list of its own, so the other members' code is unchanged)
+template <typename R, int DIR, bool MIXED>
 __global__ __launch_bounds__(kBatchThreads) void kb_cols(BatchDev B) {
     __shared__ cpx<R> lds_all[kBatchLds];
-    const WorkItem w = B.cols[xcd_logical_block(blockIdx.x, gridDim.x)];
+    const WorkItem w = (MIXED ? B.cols_mixed : B.cols)[xcd_logical_block(blockIdx.x, gridDim.x)];
     const DevPlan P = B.members[w.member];
     if (w.kind == 0) {
-        PHI_BATCH_LOG(P.log_fine, (cols_highfreq_body<R, LOG_, DIR, batch_lines(LOG_)>(P, w.item, lds_all)));
+        PHI_BATCH_LOG(P.log_fine, (cols_highfreq_body<R, LOG_, DIR, batch_lines(LOG_), MIXED>(P, w.item, lds_all)));
     } else {
         PHI_BATCH_LOG(P.log_fine, (cols_type2_body<R, LOG_, DIR, batch_lines(LOG_)>(P, w.item, lds_all)));
     }
@@ -120,7 +122,9 @@ hipError_t enqueue_batch_dir(const BatchDev& B, const void* in, void* out, hipSt
     PHI_LAUNCH_B("rows_forward", B.n_rows,
                  hipLaunchKernelGGL((kb_rows_forward<R, DIR>), dim3(B.n_rows), blk, 0, s, B,
                                     static_cast<const R*>(in)));
-    PHI_LAUNCH_B("cols", B.n_cols, hipLaunchKernelGGL((kb_cols<R, DIR>), dim3(B.n_cols), blk, 0, s, B));
+    PHI_LAUNCH_B("cols", B.n_cols, hipLaunchKernelGGL((kb_cols<R, DIR, false>), dim3(B.n_cols), blk, 0, s, B));
+    PHI_LAUNCH_B("cols_mixed", B.n_cols_mixed,
+                 hipLaunchKernelGGL((kb_cols<R, DIR, true>), dim3(B.n_cols_mixed), blk, 0, s, B));
     PHI_LAUNCH_B("nodes", B.n_nodes, hipLaunchKernelGGL((kb_nodes<R>), dim3(B.n_nodes), blk, 0, s, B));
     PHI_LAUNCH_B("cols_type1", B.n_cols1,
                  hipLaunchKernelGGL((kb_cols_type1<R, -DIR>), dim3(B.n_cols1), blk, 0, s, B));

@@ -11,8 +11,9 @@
 //                      column-major workspace (the plan's I1 half-spectrum
 //                      buffer), the pair's two entries adjacent.
 //   per_cols           per column m: FFT along y, times -kx^2/|k|^2 / N^2 (the
-//                      ratio of integer squares m^2 / (m^2 + m'^2), exact in the
-//                      data precision), inverse FFT, in place.
+//                      ratio of integers m^2 / (m^2 + m'^2), exact in the data
+//                      precision; m'^2 or m m' for the y and mixed components),
+//                      inverse FFT, in place.
 //   per_rows_inverse   per pair of rows: the Hermitian extensions of both half
 //                      spectra combined as X_a + i X_b, one inverse FFT:
 //                      Phi_a = Re, Phi_b = Im.
@@ -69,7 +70,8 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * pairs_per_block<R, LOG>())) vo
     }
 }
 
-template <typename R, int LOG, bool COMPY>
+// COMP: 0 -kx^2/|k|^2, 1 -ky^2/|k|^2, 2 -kx ky/|k|^2
+template <typename R, int LOG, int COMP>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_per_cols(DevPlan P) {
     using Sh = FftShape<LOG>;
     constexpr int N = Sh::F;
@@ -97,7 +99,11 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
         const R my2 = static_cast<R>(ps * ps);
         const R den = mx2 + my2;
         const bool pos = den > R(0);
-        R f = -(COMPY ? my2 : mx2) * recip(pos ? den : R(1)) * scale;
+        // the mixed numerator is odd in each index; a bin on a Nyquist line stands
+        // for +m and -m and takes the multiplier's mean over them, 0
+        const bool nyq = (mc == N / 2) || (ps == -N / 2);
+        const R num = COMP == 2 ? (nyq ? R(0) : static_cast<R>(mc * ps)) : COMP == 1 ? my2 : mx2;
+        R f = -num * recip(pos ? den : R(1)) * scale;
         f = pos ? f : R(0);
         v[i] = cscale(v[i], f);
     }
@@ -164,10 +170,12 @@ hipError_t periodic_log(const DevPlan& P, const void* in, void* out, hipStream_t
     if ((e = mark_kernel(timer, "per_rows_forward", true, s)) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_cols", false, s)) != hipSuccess) return e;
     const int col_blocks = (N / 2 + 1 + GC - 1) / GC;
-    if (P.component_y)
-        hipLaunchKernelGGL((k_per_cols<R, LOG, true>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
+    if (P.component == 2)
+        hipLaunchKernelGGL((k_per_cols<R, LOG, 2>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
+    else if (P.component == 1)
+        hipLaunchKernelGGL((k_per_cols<R, LOG, 1>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
     else
-        hipLaunchKernelGGL((k_per_cols<R, LOG, false>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
+        hipLaunchKernelGGL((k_per_cols<R, LOG, 0>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_cols", true, s)) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_rows_inverse", false, s)) != hipSuccess) return e;

@@ -189,7 +189,8 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->patch_lo = hp.patch_lo;
     d->width = hp.width;
     d->n_nodes = hp.n_nodes;
-    d->component_y = hp.component_y;
+    d->component = hp.component;
+    d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));
     d->h2 = hp.h * hp.h;
     d->inv_f2 = 1.0 / (f * f);
@@ -550,12 +551,12 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             return plan->sets[plan->member_set[a]].n > plan->sets[plan->member_set[b]].n;
         });
-        std::vector<phi::WorkItem> rows, cols, nodes, cols1;
+        std::vector<phi::WorkItem> rows, cols, cols_mixed, nodes, cols1;
         for (int i : order) {
             const phi::HostPlan& hp = plan->sets[plan->member_set[i]];
             const int g = phi::batch_lines(hp.log_fine);
             push_items(&rows, i, 0, hp.n, g);
-            push_items(&cols, i, 0, hp.n + 1, g);
+            push_items(hp.component == 2 ? &cols_mixed : &cols, i, 0, hp.n + 1, g);
             push_items(&cols, i, 1, hp.patch, g);
             push_items(&nodes, i, 0, hp.n_sub, 1);
             push_items(&cols1, i, 0, hp.patch, g);
@@ -570,6 +571,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         const Part p_off = L.take(sizeof(int64_t) * (count + 1));
         const Part p_rows = L.take(sizeof(phi::WorkItem) * rows.size());
         const Part p_cols = L.take(sizeof(phi::WorkItem) * cols.size());
+        const Part p_cols_mixed = L.take(sizeof(phi::WorkItem) * cols_mixed.size());
         const Part p_nodes = L.take(sizeof(phi::WorkItem) * nodes.size());
         const Part p_cols1 = L.take(sizeof(phi::WorkItem) * cols1.size());
         plan->block_bytes = L.cursor;
@@ -597,6 +599,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         if (e == hipSuccess) e = up(p_off, plan->offsets.data());
         if (e == hipSuccess) e = up(p_rows, rows.data());
         if (e == hipSuccess) e = up(p_cols, cols.data());
+        if (e == hipSuccess) e = up(p_cols_mixed, cols_mixed.data());
         if (e == hipSuccess) e = up(p_nodes, nodes.data());
         if (e == hipSuccess) e = up(p_cols1, cols1.data());
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -611,10 +614,12 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         b.offsets = reinterpret_cast<const int64_t*>(base + p_off.off);
         b.rows = reinterpret_cast<const phi::WorkItem*>(base + p_rows.off);
         b.cols = reinterpret_cast<const phi::WorkItem*>(base + p_cols.off);
+        b.cols_mixed = reinterpret_cast<const phi::WorkItem*>(base + p_cols_mixed.off);
         b.nodes = reinterpret_cast<const phi::WorkItem*>(base + p_nodes.off);
         b.cols1 = reinterpret_cast<const phi::WorkItem*>(base + p_cols1.off);
         b.n_rows = static_cast<int>(rows.size());
         b.n_cols = static_cast<int>(cols.size());
+        b.n_cols_mixed = static_cast<int>(cols_mixed.size());
         b.n_nodes = static_cast<int>(nodes.size());
         b.n_cols1 = static_cast<int>(cols1.size());
         plan->host = plan->sets[plan->member_set[0]];

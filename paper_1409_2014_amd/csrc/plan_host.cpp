@@ -265,8 +265,11 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
         *err = fmt("tol %g outside [%g, 0.1] for this dtype", p->tol, tol_min);
         return PHI_ERR_TOL_UNREACHABLE;
     }
-    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_AUTOTUNE | PHI_RADIAL_JACOBI)) != 0) {
+    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI)) != 0) {
         *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG;
+    }
+    if ((p->flags & PHI_COMPONENT_Y) && (p->flags & PHI_COMPONENT_XY)) {
+        *err = "PHI_COMPONENT_Y and PHI_COMPONENT_XY exclude each other"; return PHI_ERR_INVALID_ARG;
     }
     if (p->bin != 0 && p->bin != 4 && p->bin != 8 && p->bin != kMaxBinSize) {
         *err = "bin must be 0, 4, 8 or 16"; return PHI_ERR_INVALID_ARG;
@@ -281,7 +284,7 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->n_r = p->n_r;
     hp->n_theta = p->n_theta;
     hp->n_nodes = p->n_r * p->n_theta;
-    hp->component_y = (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
+    hp->component = (p->flags & PHI_COMPONENT_XY) ? 2 : (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
     hp->radial_jacobi = (p->flags & PHI_RADIAL_JACOBI) ? 1 : 0;
     hp->dtype = p->dtype;
     hp->h = p->hx;
@@ -320,7 +323,8 @@ void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double
     // Sec. 2.1, eq. 12: radial Gauss rule on [0, c] (r_i = c (1 + x_i)/2, weight
     // (c/2) w_i r_i with the polar Jacobian folded in), azimuthal trapezoid
     // theta_j = 2 pi j / N_theta with weight 2 pi / N_theta;
-    // q_ij = -w_r w_theta cos^2(theta_j) exp(-r_i^2 / sigma^2)   (sin^2 for the y component).
+    // q_ij = -w_r w_theta cos^2(theta_j) exp(-r_i^2 / sigma^2)   (sin^2 for the y component,
+    // cos sin for the mixed one: the multiplier's value on the unit circle).
     std::vector<double> gx(hp.n_r), gw(hp.n_r);
     if (hp.radial_jacobi) gauss_jacobi01(hp.n_r, gx.data(), gw.data());
     else gauss_legendre(hp.n_r, gx.data(), gw.data());
@@ -339,7 +343,7 @@ void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double
             // angle 2 pi j / N_theta evaluated as pi * (2j / N_theta) in [0, 2 pi)
             const double th = kPi * (2.0 * j / hp.n_theta);
             const double cs = std::cos(th), sn = std::sin(th);
-            const double ang = hp.component_y ? sn * sn : cs * cs;
+            const double ang = hp.component == 2 ? cs * sn : hp.component == 1 ? sn * sn : cs * cs;
             const int idx = i * hp.n_theta + j;
             (*kx)[idx] = r * cs;
             (*ky)[idx] = r * sn;

@@ -26,7 +26,7 @@ struct HostPlan {
     int n_fine = 0;       // FFT side 2N (kappa = 2, NUFFT oversampling 2)
     int log_fine = 0;
     int n_r = 0, n_theta = 0, n_nodes = 0;
-    int component_y = 0;
+    int component = 0;          // multiplier -k_a k_b/|k|^2: 0 (a,b) = (x,x), 1 (y,y), 2 (x,y)
     int radial_jacobi = 0;      // Gauss-Jacobi(0, 1) radial rule instead of Gauss-Legendre
     phi_dtype dtype = PHI_F64;
     double h = 0, half_width = 0, sigma = 0, cutoff = 0;

@@ -145,7 +145,9 @@ __device__ __forceinline__ R recip(R x) {
 // register layout position tid + NT i holds a grid row only for i < 4
 // (p < N/2) and i >= 12 (p >= F - N/2), so the other inputs are compile-time
 // zeros and the inverse transform's outputs there are never formed.
-template <typename R, int LOG, int DIR, int G>
+// MIXED: the multiplier -kx ky/|k|^2 (a separate instantiation, so that the DS
+// multiplier's code is unchanged by it).
+template <typename R, int LOG, int DIR, int G, bool MIXED>
 __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
@@ -179,19 +181,33 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
 #pragma unroll
         for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
     }
-    // g1 = -(k_a^2/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with
-    // 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a}, B = 1 - e^{-b} (all terms >= 0);
-    // branch-free, g1(0) = 0
+    // g1 = -(k_a k_b/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with a = kx^2/sigma^2,
+    // b = ky^2/sigma^2 and 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a},
+    // B = 1 - e^{-b} (all terms >= 0); branch-free per point, g1(0) = 0.  The
+    // numerator is a or b, or for the mixed component (kx/sigma)(ky/sigma) with
+    // the signed frequency index of the point.
+    // The mixed numerator is odd in each frequency, and a bin on a Nyquist line
+    // (|index| = F/2) stands for +k and -k: it takes the mean of the multiplier
+    // over them, 0 (also at the corner).
     const int mc = active ? m1 : N;
     const R a = static_cast<R>(P.gx[2 * mc]);
     const R A = static_cast<R>(P.gx[2 * mc + 1]);
     const R scale = static_cast<R>(P.inv_f2);
-    const bool ycomp = P.component_y != 0;
+    const bool ycomp = P.component == 1;
+    const R fs = static_cast<R>(P.freq_scale);
+    const R fx = (mc == N) ? R(0) : static_cast<R>(mc) * fs;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const R b = gb[i].x;
         const R B = gb[i].y;
-        const R num = ycomp ? b : a;
+        R num;
+        if constexpr (MIXED) {
+            const int p = tid + NT * i;           // frequency index along y, FFT order
+            const int ms = (p < N) ? p : p - F;   // p = N (Nyquist) -> -N
+            num = (p == N) ? R(0) : fx * (static_cast<R>(ms) * fs);
+        } else {
+            num = ycomp ? b : a;
+        }
         const R den = a + b;
         const bool pos = den > R(0);
         R gfac = -(num * recip(pos ? den : R(1))) * (A + B - A * B) * scale;

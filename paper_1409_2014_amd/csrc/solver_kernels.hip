@@ -45,11 +45,11 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
     rows_forward_body<R, LOG, DIR, G>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
-template <typename R, int LOG, int DIR>
+template <typename R, int LOG, int DIR, bool MIXED>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P) {
     constexpr int G = lines_per_block<LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    cols_highfreq_body<R, LOG, DIR, G>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
+    cols_highfreq_body<R, LOG, DIR, G, MIXED>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
 // one window column per block: the Q columns are few, so at small N blocks of
@@ -110,7 +110,8 @@ hipError_t launch_cols_highfreq_dir(const DevPlan& P, hipStream_t s) {
     constexpr int block = FftShape<LOG>::NT * G;
     const int items = (P.n + 1 + G - 1) / G;
     const int grid = items;   // one work item per block
-    hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR>), dim3(grid), dim3(block), 0, s, P);
+    if (P.component == 2) hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P);
+    else hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P);
     return hipGetLastError();
 }
 

@@ -13,7 +13,9 @@ namespace phi {
 struct DevPlan {
     phi_dtype dtype;
     int n, n_fine, log_fine;
-    int patch, patch_lo, width, n_nodes, component_y;
+    int patch, patch_lo, width, n_nodes;
+    int component;          // 0: -kx^2/|k|^2, 1: -ky^2/|k|^2, 2: -kx ky/|k|^2
+    double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index
     int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
     double h2, inv_f2;
     // FP64 tables
@@ -103,9 +105,10 @@ struct BatchDev {
     const int64_t* offsets = nullptr;
     const WorkItem* rows = nullptr;    // rows_forward and rows_inverse
     const WorkItem* cols = nullptr;    // I1 columns and type-2 window columns
+    const WorkItem* cols_mixed = nullptr;  // I1 columns of the members with the mixed multiplier
     const WorkItem* nodes = nullptr;   // subproblems
     const WorkItem* cols1 = nullptr;   // type-1 window columns
-    int n_rows = 0, n_cols = 0, n_nodes = 0, n_cols1 = 0;
+    int n_rows = 0, n_cols = 0, n_cols_mixed = 0, n_nodes = 0, n_cols1 = 0;
 };
 
 // Enqueue one solve (adjoint = 0) or transposed solve (adjoint = 1) of every

@@ -42,7 +42,12 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
     p.pad = int(pad)
     p.sigma = float(sigma) if sigma else 0.0
     p.cutoff = float(cutoff) if cutoff else 0.0
-    p.flags = ((B.PHI_COMPONENT_Y if component in ("y", "yy") else 0) | (B.PHI_AUTOTUNE if autotune else 0)
+    comp_flags = {"x": 0, "xx": 0, "y": B.PHI_COMPONENT_Y, "yy": B.PHI_COMPONENT_Y, "xy": B.PHI_COMPONENT_XY}
+    if component not in comp_flags:
+        raise ValueError(f"component must be one of {sorted(comp_flags)}, got {component!r}")
+    if radial not in ("legendre", "jacobi"):
+        raise ValueError(f"radial must be 'legendre' or 'jacobi', got {radial!r}")
+    p.flags = (comp_flags[component] | (B.PHI_AUTOTUNE if autotune else 0)
                | (B.PHI_RADIAL_JACOBI if radial == "jacobi" else 0))
     p.bin = int(bin)
     p.sub_nodes = int(sub_nodes)
@@ -111,8 +116,10 @@ class Plan:
     Plan(n, h, dtype=torch.float32|float64, n_r=64, n_theta=128, tol=None,
          sigma=None, cutoff=None, component="x", bin=0, sub_nodes=0, autotune=False)
 
-    bin / sub_nodes set the node sort (0: 4 cells, 64 nodes); autotune=True
-    times the candidates on the device at plan time and keeps the fastest."""
+    component selects the multiplier: "x" -kx^2/|k|^2 (the DS potential), "y"
+    -ky^2/|k|^2, "xy" -kx ky/|k|^2.  bin / sub_nodes set the node sort (0: 4
+    cells, 64 nodes); autotune=True times the candidates on the device at plan
+    time and keeps the fastest."""
 
     def __init__(self, n: int, h: float, *, dtype=torch.float64, device=None, **kwargs):
         if not torch.cuda.is_available():

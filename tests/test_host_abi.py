@@ -81,7 +81,7 @@ def test_es_transform_against_adaptive_quadrature(lib):
 
 def test_plan_nodes_equal_the_oracle_rule(lib):
     import paper_1409_2014_amd.solver as S
-    for comp, ocomp in (("x", "xx"), ("y", "yy")):
+    for comp, ocomp in (("x", "xx"), ("y", "yy"), ("xy", "xy")):
         kx, ky, q = S.host_polar_nodes(n=64, h=0.25, n_r=32, n_theta=64, component=comp)
         okx, oky, oq = O.polar_rule(O.SplitParams(n=64, h=0.25, n_r=32, n_theta=64, component=ocomp))
         a = np.stack([kx, ky, q], 1)
@@ -128,6 +128,16 @@ def test_invalid_parameters_return_documented_codes(lib, kwargs, status):
     with pytest.raises(B.PhiError) as exc:
         S.describe(**kwargs)
     assert exc.value.status == status
+
+
+def test_component_flags_exclude_each_other(lib):
+    import paper_1409_2014_amd.solver as S
+    p = S.make_params(64, 0.25, component="xy")
+    p.flags |= B.PHI_COMPONENT_Y
+    info = B.PhiPlanInfo()
+    assert lib.phi_describe(ctypes.byref(p), ctypes.byref(info)) == 1
+    with pytest.raises(ValueError):
+        S.make_params(64, 0.25, component="yx")
 
 
 def test_null_and_destroyed_plans_are_rejected(lib):
