@@ -64,6 +64,12 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
                                 homogeneous, so I1 stays smooth at k = 0).  Not with PHI_COMPONENT_Y. */
 #define PHI_RADIAL_JACOBI 4u /* radial rule Gauss-Jacobi(0, 1) on [0, c] (weight r built in; the rule
                                 Sec. 2.1 names) instead of Gauss-Legendre with r in the weight */
+#define PHI_KERNEL_GAUSSIAN 16u /* NUFFT spreading kernel: the truncated Gaussian of Greengard-Lee
+                                gridding (the NUFFT Sec. 2.1 uses), psi(t) = exp(-(3 pi / (4 M)) t^2)
+                                over w = 2M fine-grid cells, M = ceil(1.5 ln(1/tol) / pi), with the
+                                Gaussian's Fourier transform as deconvolution, instead of the
+                                exponential of semicircle.  Needs bin + w - 1 <= 31 (tol >= 5e-13
+                                at bin 4); other cases return PHI_ERR_UNSUPPORTED. */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
                                 subproblem sizes {32, 64} on the device and keep the fastest; the
                                 choice is visible in phi_plan_info.bin / .sub_nodes.  Results of
@@ -82,7 +88,8 @@ typedef struct {
     double sigma;          /* partition width (<= 0: sqrt(ln 1e16) / (2 pi (kappa-1) L))       */
     double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
     phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
-    uint32_t flags;        /* PHI_COMPONENT_Y or PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI */
+    uint32_t flags;        /* PHI_COMPONENT_Y or PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI
+                              | PHI_KERNEL_GAUSSIAN                                                */
     int32_t bin;           /* bin side of the node sort in fine-grid cells: 4, 8 or 16 (0: 4)    */
     int32_t sub_nodes;     /* most nodes per spreading / interpolation block, 8..64 (0: 64)      */
 } phi_params;
@@ -101,7 +108,7 @@ typedef struct {
     int32_t tile;          /* spread tile side bin + w - 1                       */
     int32_t n_sub;         /* node blocks (runs of <= sub_nodes nodes of one bin) */
     int32_t sub_nodes;     /* most nodes per node block                          */
-    double h, half_width, sigma, cutoff, beta;
+    double h, half_width, sigma, cutoff, beta;   /* beta: ES shape, or the Gaussian's 3 pi / (4 M) */
     size_t device_bytes;   /* tables + workspace allocated by phi_plan           */
     int64_t n_contrib;     /* tile entries summed onto the fine-grid window      */
 } phi_plan_info;

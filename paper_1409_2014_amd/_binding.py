@@ -14,6 +14,7 @@ PHI_COMPONENT_Y = 1
 PHI_COMPONENT_XY = 8
 PHI_AUTOTUNE = 2
 PHI_RADIAL_JACOBI = 4
+PHI_KERNEL_GAUSSIAN = 16
 
 STATUS_NAMES = {
     0: "PHI_OK", 1: "PHI_ERR_INVALID_ARG", 2: "PHI_ERR_UNSUPPORTED", 3: "PHI_ERR_TOL_UNREACHABLE",

@@ -74,12 +74,12 @@ __global__ __launch_bounds__(kBatchThreads) void kb_cols(BatchDev B) {
     }
 }
 
-template <typename R>
+template <typename R, int WMAX>
 __global__ __launch_bounds__(kBatchThreads) void kb_nodes(BatchDev B) {
-    __shared__ NodeLds<R> s;
+    __shared__ NodeLds<R, WMAX> s;
     const WorkItem w = B.nodes[blockIdx.x];
     const DevPlan P = B.members[w.member];
-    nodes_body<R, 0, kNodeThreads>(P, w.item, nullptr, nullptr, s);
+    nodes_body<R, 0, kNodeThreads, WMAX>(P, w.item, nullptr, nullptr, s);
 }
 
 template <typename R, int DIR>
@@ -125,7 +125,10 @@ hipError_t enqueue_batch_dir(const BatchDev& B, const void* in, void* out, hipSt
     PHI_LAUNCH_B("cols", B.n_cols, hipLaunchKernelGGL((kb_cols<R, DIR, false>), dim3(B.n_cols), blk, 0, s, B));
     PHI_LAUNCH_B("cols_mixed", B.n_cols_mixed,
                  hipLaunchKernelGGL((kb_cols<R, DIR, true>), dim3(B.n_cols_mixed), blk, 0, s, B));
-    PHI_LAUNCH_B("nodes", B.n_nodes, hipLaunchKernelGGL((kb_nodes<R>), dim3(B.n_nodes), blk, 0, s, B));
+    if (B.wide_kernel)
+        PHI_LAUNCH_B("nodes", B.n_nodes, hipLaunchKernelGGL((kb_nodes<R, kMaxKernelWidth>), dim3(B.n_nodes), blk, 0, s, B));
+    else
+        PHI_LAUNCH_B("nodes", B.n_nodes, hipLaunchKernelGGL((kb_nodes<R, kMaxEsWidth>), dim3(B.n_nodes), blk, 0, s, B));
     PHI_LAUNCH_B("cols_type1", B.n_cols1,
                  hipLaunchKernelGGL((kb_cols_type1<R, -DIR>), dim3(B.n_cols1), blk, 0, s, B));
     PHI_LAUNCH_B("rows_inverse", B.n_rows,

@@ -324,6 +324,7 @@ phi_status autotune(const phi_params* p, hipStream_t s, phi_params* best) {
     for (int b : kBins) {
         for (int sn : kSubs) {
             if (e != hipSuccess || st != PHI_OK) break;
+            if (b + probe.width - 1 > phi::kMaxTile) continue;   // tile too large for this kernel
             phi_params cand = *best;
             cand.bin = b;
             cand.sub_nodes = sn;
@@ -620,6 +621,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         b.n_rows = static_cast<int>(rows.size());
         b.n_cols = static_cast<int>(cols.size());
         b.n_cols_mixed = static_cast<int>(cols_mixed.size());
+        for (const phi::HostPlan& hp : plan->sets) b.wide_kernel |= (hp.width > phi::kMaxEsWidth) ? 1 : 0;
         b.n_nodes = static_cast<int>(nodes.size());
         b.n_cols1 = static_cast<int>(cols1.size());
         plan->host = plan->sets[plan->member_set[0]];

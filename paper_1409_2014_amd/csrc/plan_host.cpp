@@ -265,7 +265,8 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
         *err = fmt("tol %g outside [%g, 0.1] for this dtype", p->tol, tol_min);
         return PHI_ERR_TOL_UNREACHABLE;
     }
-    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI)) != 0) {
+    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI |
+                      PHI_KERNEL_GAUSSIAN)) != 0) {
         *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG;
     }
     if ((p->flags & PHI_COMPONENT_Y) && (p->flags & PHI_COMPONENT_XY)) {
@@ -286,6 +287,7 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->n_nodes = p->n_r * p->n_theta;
     hp->component = (p->flags & PHI_COMPONENT_XY) ? 2 : (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
     hp->radial_jacobi = (p->flags & PHI_RADIAL_JACOBI) ? 1 : 0;
+    hp->gaussian_kernel = (p->flags & PHI_KERNEL_GAUSSIAN) ? 1 : 0;
     hp->dtype = p->dtype;
     hp->h = p->hx;
     hp->half_width = 0.5 * n * p->hx;
@@ -299,9 +301,18 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     // exponential-of-semicircle kernel at oversampling 2: w = ceil(log10 1/tol) + 1,
     // beta = 2.30 w).
     int w = static_cast<int>(std::ceil(std::log10(1.0 / p->tol) - 1e-9)) + 1;
-    w = std::max(2, std::min(kMaxKernelWidth, w));
-    hp->width = w;
+    w = std::max(2, std::min(kMaxEsWidth, w));
     hp->beta = 2.30 * w;
+    if (hp->gaussian_kernel) {
+        // Greengard-Lee gridding at oversampling R = 2: spreading half-width M
+        // cells with aliasing error about e^{-pi M (R-1)/(R-1/2)} = e^{-2 pi M/3},
+        // so M = ceil(1.5 ln(1/tol) / pi); in cell units the Gaussian is
+        // exp(-pi (R - 1/2)/(R M) t^2) = exp(-(3 pi/(4 M)) t^2).
+        const int m = std::max(2, static_cast<int>(std::ceil(1.5 * std::log(1.0 / p->tol) / kPi - 1e-9)));
+        w = 2 * m;
+        hp->beta = 0.75 * kPi / m;
+    }
+    hp->width = w;
 
     // Window of fine-grid cells touched by the kernel taps of the nodes.  The
     // nodes lie in |k| <= c, i.e. within n_fine h c cells of the origin.
@@ -314,6 +325,10 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->patch_lo = -q / 2;
     // bins never exceed the window (which is a power of two >= 16)
     hp->bin = std::min(p->bin > 0 ? p->bin : kBinSize, q);
+    if (w > kMaxKernelWidth || hp->bin + w - 1 > kMaxTile) {
+        *err = fmt("kernel width %g with bin side %g exceeds the spread tile (bin + w - 1 <= 31)", w, hp->bin);
+        return PHI_ERR_UNSUPPORTED;
+    }
     hp->sub_nodes = p->sub_nodes > 0 ? p->sub_nodes : kMaxNodesPerSub;
     return PHI_OK;
 }
@@ -400,8 +415,11 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
         // psi(u - l) for the w taps l = l0 .. l0 + w - 1
         const double l0x = std::ceil(ux[j] - half_w), l0y = std::ceil(uy[j] - half_w);
         for (int t = 0; t < w; ++t) {
-            hp->taps[(static_cast<size_t>(i) * 2 + 0) * w + t] = es_kernel((ux[j] - (l0x + t)) / half_w, hp->beta);
-            hp->taps[(static_cast<size_t>(i) * 2 + 1) * w + t] = es_kernel((uy[j] - (l0y + t)) / half_w, hp->beta);
+            const double dx = ux[j] - (l0x + t), dy = uy[j] - (l0y + t);
+            hp->taps[(static_cast<size_t>(i) * 2 + 0) * w + t] =
+                hp->gaussian_kernel ? std::exp(-hp->beta * dx * dx) : es_kernel(dx / half_w, hp->beta);
+            hp->taps[(static_cast<size_t>(i) * 2 + 1) * w + t] =
+                hp->gaussian_kernel ? std::exp(-hp->beta * dy * dy) : es_kernel(dy / half_w, hp->beta);
         }
     }
     // subproblems: runs of at most sub_nodes nodes of one bin
@@ -473,7 +491,17 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
     const double a_rad = half_w * 2.0 * kPi / nf;
     for (int i = 0; i < n; ++i) {
         const int np = i - n / 2;
-        const double ph = a_rad * es_transform(np * a_rad, hp->beta);
+        double ph;
+        if (hp->gaussian_kernel) {
+            // psi(x) = exp(-x^2 / (4 tau)) in radians, tau = Delta^2 / (4 beta), has
+            // psi_hat(k) = sqrt(4 pi tau) e^{-k^2 tau} (the truncation at |t| = w/2
+            // is part of the kernel's error)
+            const double delta = 2.0 * kPi / nf;
+            const double tau = delta * delta / (4.0 * hp->beta);
+            ph = std::sqrt(4.0 * kPi * tau) * std::exp(-static_cast<double>(np) * np * tau);
+        } else {
+            ph = a_rad * es_transform(np * a_rad, hp->beta);
+        }
         hp->deconv[i] = 2.0 * kPi / (nf * ph);
     }
 

@@ -15,7 +15,9 @@ namespace phi {
 
 constexpr int kMaxLogFine = 13;        // fine grid up to 8192 (N up to 4096)
 constexpr int kMinLogFine = 4;         // fine grid from 16 (N from 8)
-constexpr int kMaxKernelWidth = 16;
+constexpr int kMaxKernelWidth = 28;   // widest kernel: ES up to 16, the Gaussian up to 28
+constexpr int kMaxEsWidth = 16;       // widest ES kernel (node blocks for it need less LDS)
+constexpr int kMaxTile = 31;          // largest spread tile side bin + w - 1
 constexpr int kBinSize = 4;            // default bin side in fine-grid cells (measured best or equal)
 constexpr int kMaxBinSize = 16;        // largest bin side
 constexpr int kMaxNodesPerSub = 64;    // most nodes per interp / spread subproblem
@@ -28,9 +30,11 @@ struct HostPlan {
     int n_r = 0, n_theta = 0, n_nodes = 0;
     int component = 0;          // multiplier -k_a k_b/|k|^2: 0 (a,b) = (x,x), 1 (y,y), 2 (x,y)
     int radial_jacobi = 0;      // Gauss-Jacobi(0, 1) radial rule instead of Gauss-Legendre
+    int gaussian_kernel = 0;    // Greengard-Lee Gaussian gridding instead of the ES kernel
     phi_dtype dtype = PHI_F64;
     double h = 0, half_width = 0, sigma = 0, cutoff = 0;
-    // NUFFT kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1, z = offset / (w/2)
+    // NUFFT kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1, z = offset / (w/2);
+    // with gaussian_kernel, psi(t) = exp(-beta t^2), t = offset in cells, |t| < w/2
     int width = 0;
     double beta = 0;
     // fine-grid window touched by the nodes' kernel taps: [patch_lo, patch_lo + patch)

@@ -284,12 +284,14 @@ constexpr int kNodeThreads = 256;         // batched blocks
 constexpr int kNodeThreadsSingle = 256;   // one plan's subproblems
 constexpr int kLanesPerNode = 16;
 constexpr int kSpreadParts = 2;
-constexpr int kTileMax = kMaxBinSize + kMaxKernelWidth - 1;
+constexpr int kTileMax = kMaxTile;
 
-template <typename R>
+// WMAX: the widest kernel the block serves (kMaxEsWidth, or kMaxKernelWidth for
+// the Gaussian), which sizes the tap store
+template <typename R, int WMAX>
 struct NodeLds {
     cpx<R> tile[kTileMax * kTileMax];
-    R taps[kMaxNodesPerSub * 2 * kMaxKernelWidth];   // per node: w x-taps, then w y-taps
+    R taps[kMaxNodesPerSub * 2 * WMAX];   // per node: w x-taps, then w y-taps
     int ox[kMaxNodesPerSub];
     int oy[kMaxNodesPerSub];
     double qh[kMaxNodesPerSub];   // q_j h^2
@@ -318,14 +320,14 @@ __device__ __forceinline__ int small_div(int x, unsigned magic) {
     return static_cast<int>((static_cast<unsigned>(x) * magic) >> 16);
 }
 
-template <typename R, int MODE, int NTH>
+template <typename R, int MODE, int NTH, int WMAX>
 __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx<R>* __restrict__ coef,
-                                           cpx<R>* __restrict__ out, NodeLds<R>& s) {
+                                           cpx<R>* __restrict__ out, NodeLds<R, WMAX>& s) {
     static_assert(NTH % kLanesPerNode == 0 && NTH % kSpreadParts == 0, "whole node and cell groups");
     static_assert(NTH >= kMaxNodesPerSub, "one thread per node for the node scalars");
-    static_assert(kTileMax * kTileMax < 1024 && kTileMax <= 31 && kMaxKernelWidth * kMaxKernelWidth <= 1024,
+    static_assert(kTileMax * kTileMax < 1024 && kTileMax <= 31 && WMAX * WMAX <= 1024 && WMAX <= kMaxKernelWidth,
                   "small_div covers the tile and tap indices");
-    constexpr int TPT = (kMaxNodesPerSub * 2 * kMaxKernelWidth + NTH - 1) / NTH;   // taps per thread
+    constexpr int TPT = (kMaxNodesPerSub * 2 * WMAX + NTH - 1) / NTH;   // taps per thread
     constexpr int CPT = (kTileMax * kTileMax + NTH - 1) / NTH;                     // tile cells per thread
     const int* sub = P.sub + 4 * sidx;
     const int bx = sub[0], by = sub[1], first = sub[2], count = sub[3];

@@ -60,11 +60,11 @@ __global__ __launch_bounds__(FftShape<LOG>::NT) void k_cols_type2(DevPlan P) {
     cols_type2_body<R, LOG, DIR, 1>(P, blockIdx.x, lds_all);
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int WMAX>
 __global__ __launch_bounds__(kNodeThreadsSingle) void k_nodes(DevPlan P, const cpx<R>* __restrict__ coef,
                                                         cpx<R>* __restrict__ out) {
-    __shared__ NodeLds<R> s;
-    nodes_body<R, MODE, kNodeThreadsSingle>(P, blockIdx.x, coef, out, s);
+    __shared__ NodeLds<R, WMAX> s;
+    nodes_body<R, MODE, kNodeThreadsSingle, WMAX>(P, blockIdx.x, coef, out, s);
 }
 
 template <typename R, int LOG, int DIR>
@@ -208,8 +208,12 @@ hipError_t run_rows_inverse(const DevPlan& P, void* out, int dir, int use_i1, in
 
 template <typename R, int MODE>
 hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t s) {
-    hipLaunchKernelGGL((k_nodes<R, MODE>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
-                       static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
+    if (P.width > kMaxEsWidth)
+        hipLaunchKernelGGL((k_nodes<R, MODE, kMaxKernelWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
+                           static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
+    else
+        hipLaunchKernelGGL((k_nodes<R, MODE, kMaxEsWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
+                           static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
     return hipGetLastError();
 }
 

@@ -109,6 +109,7 @@ struct BatchDev {
     const WorkItem* nodes = nullptr;   // subproblems
     const WorkItem* cols1 = nullptr;   // type-1 window columns
     int n_rows = 0, n_cols = 0, n_cols_mixed = 0, n_nodes = 0, n_cols1 = 0;
+    int wide_kernel = 0;               // some member's kernel is wider than kMaxEsWidth
 };
 
 // Enqueue one solve (adjoint = 0) or transposed solve (adjoint = 1) of every

@@ -31,7 +31,7 @@ def _dtype_code(dtype) -> int:
 def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta: int = 128,
                 tol: float | None = None, sigma: float | None = None, cutoff: float | None = None,
                 component: str = "x", pad: int = 2, bin: int = 0, sub_nodes: int = 0,
-                autotune: bool = False, radial: str = "legendre") -> B.PhiParams:
+                autotune: bool = False, radial: str = "legendre", kernel: str = "es") -> B.PhiParams:
     code = _dtype_code(dtype)
     p = B.PhiParams()
     B.check(B.lib().phi_params_default(ctypes.byref(p), int(n), float(h), code))
@@ -47,8 +47,11 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
         raise ValueError(f"component must be one of {sorted(comp_flags)}, got {component!r}")
     if radial not in ("legendre", "jacobi"):
         raise ValueError(f"radial must be 'legendre' or 'jacobi', got {radial!r}")
+    if kernel not in ("es", "gaussian"):
+        raise ValueError(f"kernel must be 'es' or 'gaussian', got {kernel!r}")
     p.flags = (comp_flags[component] | (B.PHI_AUTOTUNE if autotune else 0)
-               | (B.PHI_RADIAL_JACOBI if radial == "jacobi" else 0))
+               | (B.PHI_RADIAL_JACOBI if radial == "jacobi" else 0)
+               | (B.PHI_KERNEL_GAUSSIAN if kernel == "gaussian" else 0))
     p.bin = int(bin)
     p.sub_nodes = int(sub_nodes)
     return p
@@ -117,7 +120,8 @@ class Plan:
          sigma=None, cutoff=None, component="x", bin=0, sub_nodes=0, autotune=False)
 
     component selects the multiplier: "x" -kx^2/|k|^2 (the DS potential), "y"
-    -ky^2/|k|^2, "xy" -kx ky/|k|^2.  bin / sub_nodes set the node sort (0: 4
+    -ky^2/|k|^2, "xy" -kx ky/|k|^2; radial "legendre" or "jacobi" the radial
+    rule; kernel "es" or "gaussian" (Greengard-Lee gridding) the NUFFT kernel.  bin / sub_nodes set the node sort (0: 4
     cells, 64 nodes); autotune=True times the candidates on the device at plan
     time and keeps the fastest."""
 

@@ -72,13 +72,14 @@ def test_highfreq_and_lowfreq_parts_fp64(ps):
     assert np.max(np.abs(i2 - parts["i2"])) <= 1e-11 * scale
 
 
+@pytest.mark.parametrize("kernel", ["es", "gaussian"])
 @pytest.mark.parametrize("dtype,tol,bar", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-7, 1e-5),
                                            (torch.float64, 1e-6, 1e-5)])
-def test_type2_stage_against_direct_sums(ps, dtype, tol, bar):
-    print(f"case: type2 {dtype} tol={tol}", flush=True)
+def test_type2_stage_against_direct_sums(ps, dtype, tol, bar, kernel):
+    print(f"case: type2 {dtype} tol={tol} kernel={kernel}", flush=True)
     n, half = 256, 8.0
     rho = np.random.default_rng(21).standard_normal((n, n))
-    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol)
+    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol, kernel=kernel)
     r = to_dev(rho, dtype)
     got = plan.type2(r).cpu().numpy().astype(np.complex128)
     kx, ky, _ = plan.nodes()
@@ -87,11 +88,12 @@ def test_type2_stage_against_direct_sums(ps, dtype, tol, bar):
     assert rel_l2(got, ref) <= bar
 
 
+@pytest.mark.parametrize("kernel", ["es", "gaussian"])
 @pytest.mark.parametrize("dtype,tol,bar", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-7, 1e-5)])
-def test_type1_stage_against_direct_sums(ps, dtype, tol, bar):
-    print(f"case: type1 {dtype}", flush=True)
+def test_type1_stage_against_direct_sums(ps, dtype, tol, bar, kernel):
+    print(f"case: type1 {dtype} kernel={kernel}", flush=True)
     n, half = 256, 8.0
-    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol)
+    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol, kernel=kernel)
     m = plan.info["n_nodes"]
     rng = np.random.default_rng(22)
     coef = rng.standard_normal(m) + 1j * rng.standard_normal(m)
@@ -319,3 +321,28 @@ def test_jacobi_radial_rule_and_the_papers_node_counts(ps, dtype, bar):
     ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=60, n_theta=60, radial="jacobi"))
     assert rel_linf(got, ref) <= bar
     assert rel_l2(got, ref) <= bar
+
+
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-10), (torch.float32, 1e-6)])
+def test_the_papers_exact_variant(ps, dtype, bar):
+    """Everything as the paper states it (Sec. 2.1): Gauss-Jacobi radial rule,
+    60 x 60 polar nodes and Greengard-Lee Gaussian gridding for both NUFFTs,
+    against the oracle with the same quadrature; and Example 1 on [-8, 8)^2 at
+    h = 1/8 against its closed form (Table 2 prints 1.55E-10 there)."""
+    print(f"case: paper variant 256^2 {dtype}", flush=True)
+    n, half = 256, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(14, 8, 4.0, (0.5, 1.5)))
+    tol = 1e-12 if dtype == torch.float64 else 1e-7
+    kw = dict(n_r=60, n_theta=60, tol=tol, radial="jacobi", kernel="gaussian")
+    plan, rho_used, got = run_solve(ps, rho, n, 2 * half / n, dtype, **kw)
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=60, n_theta=60, radial="jacobi"))
+    assert rel_linf(got, ref) <= bar
+    assert rel_l2(got, ref) <= bar
+    if dtype == torch.float64:
+        n = 128
+        x, y, _ = W.grid_2d(n, half)
+        plan, _, got = run_solve(ps, W.paper_gaussian_density(n, half), n, 2 * half / n, dtype, **kw)
+        ex = O.closed_forms.phi_isotropic_gaussian(x, y, math.pi, math.pi ** 2)
+        err = rel_linf(got, ex)
+        print(f"  Example 1, L = 8, h = 1/8: {err:.3e}", flush=True)
+        assert abs(err - 1.55e-10) <= 0.01 * 1.55e-10

@@ -104,6 +104,25 @@ def test_describe_defaults_small_case(lib):
     assert d["kernel_width"] == 8 and d["patch"] == 64 and d["n_nodes"] == 8192
 
 
+def test_describe_gaussian_gridding(lib):
+    """Greengard-Lee gridding at oversampling 2: half-width M = ceil(1.5 ln(1/tol)/pi)
+    cells, Gaussian exp(-(3 pi/(4 M)) t^2); the wider kernel widens the window."""
+    import paper_1409_2014_amd.solver as S
+    for tol, m in ((1e-12, 14), (1e-7, 8), (1e-3, 4)):
+        d = S.describe(n=256, h=1 / 16, tol=tol, kernel="gaussian")
+        assert d["kernel_width"] == 2 * m == 2 * math.ceil(1.5 * math.log(1 / tol) / math.pi)
+        assert abs(d["beta"] - 0.75 * math.pi / m) < 1e-15
+        assert d["tile"] == d["bin"] + 2 * m - 1
+        # the window holds every tap: n_fine h c + M cells from the origin
+        assert d["patch"] // 2 >= math.ceil(2 * 256 / 16 * d["cutoff"] + m) + 1
+    with pytest.raises(B.PhiError) as exc:
+        S.describe(n=256, h=1 / 16, tol=1e-14, kernel="gaussian")
+    assert exc.value.status == 2
+    with pytest.raises(B.PhiError) as exc:
+        S.describe(n=256, h=1 / 16, tol=1e-12, kernel="gaussian", bin=8)
+    assert exc.value.status == 2
+
+
 def test_describe_small_grid_uses_whole_fine_grid(lib):
     import paper_1409_2014_amd.solver as S
     d = S.describe(n=16, h=1.0)
