@@ -346,3 +346,43 @@ def test_the_papers_exact_variant(ps, dtype, bar):
         err = rel_linf(got, ex)
         print(f"  Example 1, L = 8, h = 1/8: {err:.3e}", flush=True)
         assert abs(err - 1.55e-10) <= 0.01 * 1.55e-10
+
+
+# --------------------------------------------------------------------------
+# the largest grid the plans take: 4096^2 (fine grid 8192)
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def max_case():
+    """A mixture density at N = 4096 over [-16, 16)^2, rounded to FP32 so that
+    both data paths see the same input, and the oracle at 256 sampled points
+    (I1 by the padded FFT everywhere, I2 by direct sums evaluated at the
+    samples only)."""
+    n, half = 4096, 16.0
+    h = 2 * half / n
+    rho = W.mixture_density(n, half, W.draw_mixture(0)).astype(np.float32).astype(np.float64)
+    p = O.SplitParams(n=n, h=h, n_r=64, n_theta=128)
+    idx = np.random.default_rng(17).integers(0, n, size=(256, 2))
+    i1 = O.i1_padded_fft(rho, p)[idx[:, 0], idx[:, 1]]
+    kx, ky, q = O.polar_rule(p)
+    xs = O.grid_points(p)
+    rho_hat = O.type2_direct(rho, h, xs, kx, ky)
+    phase = np.exp(2j * np.pi * (np.outer(xs[idx[:, 1]], kx) + np.outer(xs[idx[:, 0]], ky)))
+    i2 = (phase @ (q * rho_hat)).real
+    return rho, idx, i1 + i2
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_largest_grid_against_sampled_oracle(ps, max_case, dtype):
+    print(f"case: 4096x4096 {dtype}", flush=True)
+    rho, idx, ref = max_case
+    n = rho.shape[0]
+    tol = 1e-12 if dtype == torch.float64 else 1e-7
+    plan, _, got = run_solve(ps, rho, n, 32.0 / n, dtype, tol=tol)
+    assert plan.info["n_fine"] == 8192
+    g = got[idx[:, 0], idx[:, 1]]
+    bar = 1e-10 if dtype == torch.float64 else 1e-6
+    err = float(np.max(np.abs(g - ref)) / np.max(np.abs(got)))
+    print(f"  sampled rel err {err:.3e}", flush=True)
+    assert err <= bar
+    plan.close()

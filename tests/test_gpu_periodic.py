@@ -31,7 +31,7 @@ def rel_linf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("n", [16, 32, 128, 512, 2048])
+@pytest.mark.parametrize("n", [16, 32, 128, 512, 2048, 4096])
 @pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-12), (torch.float32, 1e-6)])
 def test_periodic_solver_matches_oracle(ps, n, dtype, bar):
     print(f"case: periodic {n}^2 {dtype}", flush=True)

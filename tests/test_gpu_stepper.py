@@ -107,6 +107,25 @@ def test_other_schemes_match_oracle_stepper(ps, scheme, pot, dtype, bar):
     st.close()
 
 
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-10), (torch.float32, 1e-5)])
+def test_largest_grid_step_matches_oracle(ps, dtype, bar):
+    """One Strang step at the largest side the stepper takes (4096, transforms of
+    length 4096 along both axes), with the periodic potential so that the
+    oracle step stays a few full-grid FFTs."""
+    print(f"case: stepper 4096^2 1 step periodic {dtype}", flush=True)
+    n, half = 4096, 32.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.0, tau=1e-2, n_r=32, n_theta=64, potential="periodic")
+    st = ps.DSStepper(n, p.h, alpha=1.0, beta=1.0, tau=p.tau, dtype=dtype, n_r=32, n_theta=64, tol=TOL[dtype],
+                      potential="periodic")
+    u = dev(initial(n, half, kx=0.5, ky=0.25), dtype)
+    u_used = u.cpu().numpy().astype(np.complex128)
+    st.forward(u, 1)
+    err = rel_linf(u.cpu().numpy(), D.evolve(u_used, p, 1))
+    print(f"rel L-inf after 1 step: {err:.3e}", flush=True)
+    assert err <= bar
+    st.close()
+
+
 def test_independent_phase_coefficients_match_oracle(ps):
     """The E-E system's nonlinear substep (c_local = -chi, c_potential = -gamma)."""
     print("case: stepper E-E coefficients 64^2", flush=True)
