@@ -52,7 +52,7 @@ TRAFFIC_RECORD = {
     "copy_fetch_kib": 131088.5, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
     "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "734066fcdb3118585f235040f8080bff646ea51de1c8d4267c2ceac3ebc0494c",
+    "sha256": "3bdf10f260f5ec4ae1c0f36fcc219adf9e6d0a86e9cab5b6605edf05f28bd052",
 }
 
 N = 2048
