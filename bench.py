@@ -11,7 +11,7 @@ A step is one potential solve Phi = I1 + I2 (every kernel of the chain) with
 rho already resident in device memory.  `value` is FP32 solves/s over K timed
 steps; the same line carries the FP64 rate, the FP32/FP64 ratio, the rate of
 forward + transposed solve pairs, the relative errors of both data paths
-against the FP64 oracle, the dominant kernel's HBM roofline figure (HIP events
+against the FP64 oracle, the dominant kernel's ALU and HBM roofline figures (HIP events
 recorded around every kernel on its launch stream) and the oracle's own rate
 on the host cores.  Further legs (skipped with --no-extra-legs): a batch
 of 256 densities with sides drawn from {128, 256, 512, 1024} at h = 1/32
@@ -39,6 +39,12 @@ if ROOT not in sys.path:
 
 METRIC = "Φ solves/s at 2048² grid: FP32 vs FP64 at rel-err 1e-6; fwd+bwd solves/s"
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak of MI355X from its unit counts: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops (FMA) x 2.4 GHz = 78.64 TFLOP/s, FP32 and FP64 alike, for code without
+# packed FP32 instructions (this build turns them off).  The published FP32
+# figure, 157.3 TFLOP/s, counts packed FP32 (two FMAs per lane).
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+VALU_PEAK_PUBLISHED_F32 = 157.3
 
 # HBM traffic of the dominant kernel (FP32 cols_highfreq, 2048^2) from two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch, mean over the
@@ -79,6 +85,16 @@ def kernel_bytes(info: dict, real_bytes: int) -> dict:
         "cols_type1": tiles + info["n_contrib"] * 4 + (q * q + 1) * 4 + n * q * sc,
         "rows_inverse": spec + n * q * sc + n * n * sr,
     }
+
+
+def kernel_flops(info: dict) -> dict:
+    """Algorithmic flops of one launch of each FFT kernel, by the conventional
+    count of 5 F log2 F real flops per complex F-point transform (a count of the
+    transform, not of the pruned code, which does less)."""
+    n, q, f = info["n"], info["patch"], info["n_fine"]
+    fft = 5 * f * math.log2(f)
+    return {"rows_forward": n * fft, "cols_highfreq": 2 * (n + 1) * fft, "rows_inverse": n * fft,
+            "cols_type2": q * fft, "cols_type1": q * fft}
 
 
 def solve_alg_bytes(n: int, real_bytes: int) -> int:
@@ -497,6 +513,11 @@ def main() -> int:
     kernels = event_kernels(lambda: plan32.solve_timed(rho32_dev, out32), k, nbytes)
     dominant = max(kernels, key=lambda name: kernels[name]["avg_us"])
     achieved = kernels[dominant]["gbs"]
+    flops32 = kernel_flops(plan32.info)
+    for name, kv in kernels.items():
+        if name in flops32:
+            kv["tflops"] = round(flops32[name] / (kv["avg_us"] * 1e-6) / 1e12, 2)
+    alu_achieved = round(flops32[dominant] / (kernels[dominant]["avg_us"] * 1e-6) / 1e12, 2)
     alg32, alg64 = solve_alg_bytes(N, 4), solve_alg_bytes(N, 8)
 
     result = {
@@ -528,9 +549,19 @@ def main() -> int:
         "time_split_f32": time_split(kernels),
         "node_sort": {"bin": plan32.info["bin"], "sub_nodes": plan32.info["sub_nodes"],
                       "n_sub": plan32.info["n_sub"]},
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(dominant)},
+        # the FFT kernels are bound by their vector ALU work (the counters show
+        # 1.0x their algorithmic HBM bytes at a fifth of the bandwidth, and the
+        # VALU busy for half the time): the roofline is the ALU one, with the
+        # HBM figure of the same kernel beside it
+        "roofline": {"bound": "alu", "kernel": dominant, "achieved": alu_achieved,
+                     "peak": round(VALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s",
+                     "frac": round(alu_achieved / VALU_PEAK_TFLOPS, 4),
+                     "traffic": recorded_traffic(dominant),
+                     "flops_per_launch": flops32[dominant],
+                     "published_peak": VALU_PEAK_PUBLISHED_F32,
+                     "frac_of_published": round(alu_achieved / VALU_PEAK_PUBLISHED_F32, 4),
+                     "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4)}},
     }
     plan32.close()
     plan64.close()
