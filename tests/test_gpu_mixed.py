@@ -130,3 +130,28 @@ def test_batch_with_mixed_members_matches_single_plans(ps, dtype):
         assert rel_linf(got[i], ref) <= BARS[dtype], f"member {i}"
         single.close()
     bp.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_with_gaussian_gridding_members(ps, dtype):
+    """Members with the Gaussian gridding kernel (wider taps, window 128) next to
+    ES members: the batch's node blocks take the wide tap store; every member
+    equals its single-plan solve bit for bit and the oracle within the bar."""
+    print(f"case: batch with Gaussian gridding members {dtype}", flush=True)
+    specs = [(256, "gaussian", 7), (512, "es", 8), (128, "gaussian", 9)]
+    members, params = [], []
+    for n, kernel, seed in specs:
+        half = n / 64.0
+        members.append(W.mixture_density(n, half, W.draw_mixture(seed, 8, 0.375 * half, (0.5 * half / 16, 2 * half / 16))))
+        params.append(dict(n=n, h=2 * half / n, n_r=64, n_theta=128, tol=TOLS[dtype], kernel=kernel))
+    bp = ps.BatchPlan(params, dtype=dtype)
+    packed = bp.pack(members)
+    got = [g.cpu().numpy() for g in bp.unpack(bp.solve(packed))]
+    used = [g.double().cpu().numpy() for g in bp.unpack(packed)]
+    for i, kw in enumerate(params):
+        single = ps.Plan(kw["n"], kw["h"], dtype=dtype, n_r=64, n_theta=128, tol=kw["tol"], kernel=kw["kernel"])
+        assert np.array_equal(got[i], single.solve(dev(used[i], dtype)).cpu().numpy()), f"member {i}"
+        ref = O.phi(used[i], O.SplitParams(n=kw["n"], h=kw["h"], n_r=64, n_theta=128))
+        assert rel_linf(got[i], ref) <= BARS[dtype], f"member {i}"
+        single.close()
+    bp.close()

@@ -92,3 +92,34 @@ def test_periodic_argument_errors(ps):
     with pytest.raises(B.PhiError, match="PHI_ERR_UNSUPPORTED"):
         bp._call(B.lib().phi_solve_periodic, src, None)
     bp.close()
+
+
+def test_periodic_graph_replay_matches_eager(ps):
+    """The periodic solve captured into a HIP graph gives the eager result on
+    every replay, with other eager work on the plan between replays."""
+    print("case: periodic graph replay 1024^2 FP32", flush=True)
+    n, half = 1024, 16.0
+    rho = W.mixture_density(n, half, W.draw_mixture(21, 8, 6.0, (0.5, 1.5)))
+    other = W.mixture_density(n, half, W.draw_mixture(22, 8, 6.0, (0.5, 1.5)))
+    plan = ps.Plan(n, 2 * half / n, dtype=torch.float32, n_r=16, n_theta=32)
+    r = torch.as_tensor(rho, dtype=torch.float32, device="cuda")
+    o = torch.as_tensor(other, dtype=torch.float32, device="cuda")
+    eager = plan.periodic(r).cpu().numpy()
+    out = torch.empty_like(r)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.periodic(r, out)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.periodic(r, out)
+    for rep in range(4):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), eager), f"replay {rep}"
+        plan.periodic(o)
+        plan.solve(o)
+        torch.cuda.synchronize()
+    plan.close()
