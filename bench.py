@@ -158,9 +158,25 @@ def cpu_baseline(rho_used: np.ndarray):
         blas = [d for d in threadpool_info() if d.get("user_api") == "blas"]
         if blas:
             threads = int(max(d.get("num_threads", 1) for d in blas))
+    # the small FP64 case (exp(-r^2), 64^2 over [-8, 8)^2, 32 x 64 nodes) on one core
+    small = {}
+    try:
+        from threadpoolctl import threadpool_limits
+        import workloads as W
+        rho_small = W.gaussian_density(64, 8.0)
+        p_small = O.SplitParams(n=64, h=0.25, n_r=32, n_theta=64)
+        with threadpool_limits(limits=1):
+            O.phi(rho_small, p_small)
+            reps, t1 = 0, time.perf_counter()
+            while reps < 20 or time.perf_counter() - t1 < 1.0:
+                O.phi(rho_small, p_small)
+                reps += 1
+            small = {"small_64_one_core_ms": round(1e3 * (time.perf_counter() - t1) / reps, 3)}
+    except ImportError:          # pragma: no cover
+        pass
     return ref, {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
                  "sample": f"{runs} FP64 oracle solve(s) of the same 2048^2 density, {dt:.2f} s each ("
-                           f"{len(os.sched_getaffinity(0))} host cores visible)"}
+                           f"{len(os.sched_getaffinity(0))} host cores visible)", **small}
 
 
 def time_split(kernels: dict) -> dict:
