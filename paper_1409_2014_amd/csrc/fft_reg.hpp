@@ -60,7 +60,8 @@ __device__ __forceinline__ cpx<R> mul_i(cpx<R> a) {
     else return {a.y, -a.x};
 }
 
-// In-register DFT of length RAD (1, 2, 4, 8, 16) by even/odd splitting:
+// In-register DFT of length RAD (1, 2, 4, 8; 16 is specialised below) by
+// even/odd splitting:
 // v[k] <- sum_j v[j] e^{DIR 2 pi i j k / RAD}.
 template <int RAD, typename R, int DIR>
 struct RegDft {
@@ -93,6 +94,80 @@ struct RegDft {
 template <typename R, int DIR>
 struct RegDft<1, R, DIR> {
     __device__ __forceinline__ static void run(cpx<R>*) {}
+};
+
+// Length-4 DFT in place: 16 real additions, the factor DIR i folded into them.
+template <typename R, int DIR>
+__device__ __forceinline__ void dft4(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {
+    const cpx<R> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
+    const cpx<R> t3 = mul_i<R, DIR>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+// x times e^{DIR 2 pi i a / 16}: the eighth roots of unity (a even) as a
+// swap or the sum / difference of the parts times 1/sqrt(2); general angles as
+// two products and two fused multiply-adds.
+template <typename R, int DIR, int A>
+__device__ __forceinline__ cpx<R> rot16(cpx<R> x) {
+    constexpr int a = A & 15;
+    if constexpr (a == 0) {
+        return x;
+    } else if constexpr (a == 4) {
+        return mul_i<R, DIR>(x);
+    } else if constexpr (a == 8) {
+        return {-x.x, -x.y};
+    } else if constexpr (a == 12) {
+        return mul_i<R, -DIR>(x);
+    } else if constexpr (a == 2 || a == 6 || a == 10 || a == 14) {
+        const R r = root16<R, 1>(2).x;                      // 1/sqrt(2)
+        // (x.x + i x.y)(c + i s) with c, s = +-r
+        constexpr int cs = (a == 2 || a == 14) ? 1 : -1;      // sign of the cosine
+        constexpr int sn = ((a == 2 || a == 6) ? 1 : -1) * DIR; // sign of the sine
+        const R re = cs > 0 ? (sn > 0 ? x.x - x.y : x.x + x.y) : (sn > 0 ? -x.x - x.y : -x.x + x.y);
+        const R im = cs > 0 ? (sn > 0 ? x.x + x.y : x.y - x.x) : (sn > 0 ? x.x - x.y : -x.x - x.y);
+        return {r * re, r * im};
+    } else if constexpr (a < 8) {
+        return cmul(x, root16<R, DIR>(a));
+    } else {
+        const cpx<R> w = root16<R, DIR>(a - 8);
+        return cmul(x, cpx<R>{-w.x, -w.y});
+    }
+}
+
+// Length 16 as 4 x 4 (n = 4 n1 + n2, k = k1 + 4 k2): DFT4 over n1 for each n2,
+// twiddles W16^{n2 k1}, DFT4 over n2 for each k1.  Of the nine twiddles one is
+// a swap (W^4) and four are eighth roots (W^2, W^6), so it takes 128 real
+// additions and four general complex products, against ten products in the
+// radix-2 splitting.
+template <typename R, int DIR>
+struct RegDft<16, R, DIR> {
+    __device__ __forceinline__ static void run(cpx<R>* v) {
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) dft4<R, DIR>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+        // v[n2 + 4 k1] now holds the inner transform y[n2][k1]
+        v[5] = rot16<R, DIR, 1>(v[5]);
+        v[9] = rot16<R, DIR, 2>(v[9]);
+        v[13] = rot16<R, DIR, 3>(v[13]);
+        v[6] = rot16<R, DIR, 2>(v[6]);
+        v[10] = rot16<R, DIR, 4>(v[10]);
+        v[14] = rot16<R, DIR, 6>(v[14]);
+        v[7] = rot16<R, DIR, 3>(v[7]);
+        v[11] = rot16<R, DIR, 6>(v[11]);
+        v[15] = rot16<R, DIR, 9>(v[15]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) dft4<R, DIR>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 register block
+        cpx<R> t[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t[i] = v[i];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
+    }
 };
 
 template <int LOG>
