@@ -98,13 +98,12 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
         const int ps = (p < N / 2) ? p : p - N;
         const R my2 = static_cast<R>(ps * ps);
         const R den = mx2 + my2;
-        const bool pos = den > R(0);
         // the mixed numerator is odd in each index; a bin on a Nyquist line stands
         // for +m and -m and takes the multiplier's mean over them, 0
         const bool nyq = (mc == N / 2) || (ps == -N / 2);
         const R num = COMP == 2 ? (nyq ? R(0) : static_cast<R>(mc * ps)) : COMP == 1 ? my2 : mx2;
-        R f = -num * recip(pos ? den : R(1)) * scale;
-        f = pos ? f : R(0);
+        // den = 0 only at m = m' = 0, where num = 0: the quotient is 0 there
+        const R f = -num * recip(den + tiny_normal<R>()) * scale;
         v[i] = cscale(v[i], f);
     }
     fft_reg<R, LOG, 1>(v, lds, tw, tid);
