@@ -126,6 +126,29 @@ def test_largest_grid_step_matches_oracle(ps, dtype, bar):
     st.close()
 
 
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
+def test_large_phases_match_oracle(ps, dtype, bar):
+    """Nonlinear phases from 0 up to about 1.03 rad, so that the rotation takes
+    both its short-series branch (|phase| <= pi/4) and the library branch, and
+    the series is exercised where its higher terms matter."""
+    print(f"case: stepper 64^2 large phases {dtype}", flush=True)
+    n, half, steps = 64, 4.0, 2
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.0, tau=0.2, n_r=32, n_theta=64, c_local=2.0,
+                   c_potential=1.0)
+    st = ps.DSStepper(n, p.h, alpha=1.0, tau=p.tau, c_local=2.0, c_potential=1.0, dtype=dtype, n_r=32,
+                      n_theta=64, tol=TOL[dtype])
+    u0 = 1.8 * initial(n, half, kx=0.5, ky=0.2)
+    phase = D.nonlinear_phase(u0, p, p.tau)
+    assert np.max(np.abs(phase)) > 1.0 and np.min(np.abs(phase)) < 0.1
+    u = dev(u0, dtype)
+    u_used = u.cpu().numpy().astype(np.complex128)
+    st.forward(u, steps)
+    err = rel_linf(u.cpu().numpy(), D.evolve(u_used, p, steps))
+    print(f"rel L-inf after {steps} steps: {err:.3e}", flush=True)
+    assert err <= bar
+    st.close()
+
+
 def test_independent_phase_coefficients_match_oracle(ps):
     """The E-E system's nonlinear substep (c_local = -chi, c_potential = -gamma)."""
     print("case: stepper E-E coefficients 64^2", flush=True)
