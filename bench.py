@@ -41,7 +41,7 @@ METRIC = "Φ solves/s at 2048² grid: FP32 vs FP64 at rel-err 1e-6; fwd+bwd solv
 HBM_PEAK_GBS = 8000.0
 # Vector ALU peak of MI355X from its unit counts: 256 CUs x 4 SIMDs x 16 lanes x
 # 2 flops (FMA) x 2.4 GHz = 78.64 TFLOP/s, FP32 and FP64 alike, for code without
-# packed FP32 instructions (this build turns them off).  The published FP32
+# packed FP32 instructions (the kernels are compiled without them).  The published FP32
 # figure, 157.3 TFLOP/s, counts packed FP32 (two FMAs per lane).
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 VALU_PEAK_PUBLISHED_F32 = 157.3
@@ -452,8 +452,8 @@ def main() -> int:
                     help="also run one plain 256 MiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is not sharded "
-              "across GPUs in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve runs on one GPU "
+              "and is not sharded across GPUs", file=sys.stderr)
         return 2
 
     import torch
