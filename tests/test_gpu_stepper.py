@@ -301,3 +301,74 @@ def test_stepper_argument_errors(ps):
     with pytest.raises(ValueError):
         st.forward(g.to(torch.complex64), 1)
     st.close()
+
+
+# --------------------------------------------------------------------------
+# the full stepper workload: 2048^2 over [-32, 32)^2, u0 = exp(-(x^2 + 2 y^2)),
+# alpha = beta = 1, tau = 1e-3, 500 Strang steps, checkpoints every 50
+# --------------------------------------------------------------------------
+
+def full_initial():
+    x, y, _ = W.grid_2d(2048, 32.0)
+    return np.exp(-(x ** 2 + 2 * y ** 2)).astype(np.complex128)
+
+
+def test_full_size_steps_match_oracle(ps):
+    """Two steps at the full size, in the configuration the benchmark times,
+    against the oracle stepper (split potential by direct sums)."""
+    print("case: stepper 2048^2 2 steps FP64 vs oracle", flush=True)
+    n, half = 2048, 32.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.0, tau=1e-3, n_r=64, n_theta=128)
+    st = ps.DSStepper(n, p.h, alpha=1.0, beta=1.0, tau=p.tau, dtype=torch.float64, tol=1e-12)
+    u = dev(full_initial(), torch.float64)
+    u_used = u.cpu().numpy()
+    st.forward(u, 2)
+    err = rel_linf(u.cpu().numpy(), D.evolve(u_used, p, 2))
+    print(f"rel L-inf after 2 steps: {err:.3e}", flush=True)
+    assert err <= 1e-10
+    st.close()
+
+
+@pytest.mark.parametrize("dtype,mass_bar", [(torch.float64, 1e-12), (torch.float32, 1e-4)])
+def test_full_size_run_invariants(ps, dtype, mass_bar):
+    """500 steps at the full size: mass conservation; the checkpointed loss and
+    gradient do not depend on the checkpoint interval beyond rounding; and, in
+    FP64, the gradient against a central difference of the loss along one
+    random direction."""
+    print(f"case: stepper 2048^2 500 steps invariants {dtype}", flush=True)
+    n, half, steps = 2048, 32.0, 500
+    st = ps.DSStepper(n, 2 * half / n, alpha=1.0, beta=1.0, tau=1e-3, dtype=dtype, tol=TOL[dtype])
+    u0 = dev(full_initial(), dtype)
+    w = u0.clone()
+    m0 = float(st.moments(w)[0])
+    st.forward(w, steps)
+    drift = abs(float(st.moments(w)[0]) - m0) / m0
+    print(f"mass drift over {steps} steps: {drift:.3e}", flush=True)
+    assert drift <= mass_bar
+    loss50, g50, counts = st.loss_and_grad(u0, steps, checkpoint_every=50)
+    assert counts["forward_solves"] == 500 and counts["recomputed_solves"] == 450
+    assert counts["adjoint_solves"] == 500
+    loss100, g100, _ = st.loss_and_grad(u0, steps, checkpoint_every=100)
+    # the runs merge the linear substeps of consecutive steps except across
+    # segment ends, which differ between the intervals and from the plain
+    # forward run: equal to rounding
+    lbar, gbar = (1e-12, 1e-9) if dtype == torch.float64 else (1e-5, 1e-3)
+    assert abs(float(loss50) - float(loss100)) <= lbar * float(loss50)
+    assert rel_linf(g100.cpu().numpy(), g50.cpu().numpy()) <= gbar
+    assert abs(float(loss50) - float(st.moments(w)[1])) <= lbar * float(loss50)
+    if dtype == torch.float64:
+        rng = np.random.default_rng(77)
+        d = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        dd = dev(d, dtype)
+        eps = 1e-4
+
+        def loss(u):
+            v = u.clone()
+            st.forward(v, steps)
+            return float(st.moments(v)[1])
+
+        fd = (loss(u0 + eps * dd) - loss(u0 - eps * dd)) / (2 * eps)
+        dot = float(np.sum(np.real(np.conj(g50.cpu().numpy()) * d)))
+        print(f"FD {fd:.10e} adjoint {dot:.10e}", flush=True)
+        assert abs(fd - dot) <= 1e-6 * abs(dot)
+    st.close()
