@@ -142,6 +142,22 @@ def test_tiny_grid_brute_size(ps):
     assert rel_linf(got, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("n_r,n_theta,sub_nodes", [(5, 6, 8), (7, 10, 9), (1, 2, 64)])
+def test_odd_node_counts_and_ragged_subproblems(ps, n_r, n_theta, sub_nodes):
+    """Node counts that are not multiples of 4 (no x <-> y symmetry of the node
+    set; N_theta even keeps it closed under k -> -k), a single radial node, and
+    subproblem sizes that leave ragged last runs in every bin."""
+    print(f"case: 64x64 n_r={n_r} n_theta={n_theta} sub_nodes={sub_nodes}", flush=True)
+    n, half = 64, 8.0
+    rho = W.mixture_density(n, half, W.draw_mixture(41, 6, 3.0, (0.6, 1.5)))
+    plan, rho_used, got = run_solve(ps, rho, n, 2 * half / n, torch.float64, n_r=n_r, n_theta=n_theta, tol=1e-12,
+                                    sub_nodes=sub_nodes)
+    ref = O.phi(rho_used, O.SplitParams(n=n, h=2 * half / n, n_r=n_r, n_theta=n_theta))
+    assert rel_linf(got, ref) <= 1e-10
+    assert rel_l2(got, ref) <= 1e-10
+    plan.close()
+
+
 def test_zero_density_gives_zero(ps):
     plan = ps.Plan(128, 0.125, dtype=torch.float32)
     out = plan.solve(torch.zeros(128, 128, dtype=torch.float32, device="cuda"))
