@@ -174,15 +174,6 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
     const bool active = m1 <= N;
     // idle lanes load column N and never store: no branch around the loads
     cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : N) * P.col_stride;
-    // (b, 1 - e^{-b}) of the 16 rows this thread multiplies; in FP32 fetched
-    // before the transform so that their latency is hidden by it (in FP64 the
-    // registers are needed by the transform itself)
-    const cpx<R>* gyr = static_cast<const cpx<R>*>(P.gyr);
-    cpx<R> gb[16];
-    if constexpr (sizeof(R) == 4) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
-    }
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -190,10 +181,13 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
         else v[i] = {R(0), R(0)};
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    if constexpr (sizeof(R) != 4) {
+    // (b, 1 - e^{-b}) of the 16 rows this thread multiplies, fetched only now:
+    // held through the transform they would take 32 more registers and, in
+    // FP32, cut the resident blocks per CU from four to three
+    const cpx<R>* gyr = static_cast<const cpx<R>*>(P.gyr);
+    cpx<R> gb[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
-    }
+    for (int i = 0; i < 16; ++i) gb[i] = gyr[tid + NT * i];
     // g1 = -(k_a k_b/|k|^2) (1 - e^{-|k|^2/sigma^2}) / F^2 with a = kx^2/sigma^2,
     // b = ky^2/sigma^2 and 1 - e^{-(a+b)} = A + B - A B, A = 1 - e^{-a},
     // B = 1 - e^{-b} (all terms >= 0); branch-free per point, g1(0) = 0.  The
