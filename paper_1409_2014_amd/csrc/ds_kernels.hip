@@ -89,20 +89,35 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * ds_rows_per_block<R, LOG>())) 
     const size_t base = static_cast<size_t>(row0 + g) * N;
     const R tau = ntau, cl = static_cast<R>(D.c_local), cp = static_cast<R>(D.c_potential);
     cpx<R> a[16];
+    if constexpr (MODE == static_cast<int>(DsRowIn::Adjoint)) {
+        // adjoint of the nonlinear substep: g e^{-i phi} + 2 tau (c_l q + c_p t) v.
+        // Five inputs and a sine/cosine per point: all 16 points at once need more
+        // registers than a SIMD holds for two waves (FP64) or four (FP32), so the
+        // points go four at a time through a loop that is not unrolled, each result
+        // parked in this thread's own slots of the transform buffer (read back by
+        // the same thread only, before the transform's first barrier).
+#pragma unroll 1
+        for (int c = 0; c < 16; c += 4) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const size_t idx = base + tid + NT * i;
-        const cpx<R> xv = x[idx];
-        if constexpr (MODE == static_cast<int>(DsRowIn::Plain)) {
-            a[i] = xv;
-        } else if constexpr (MODE == static_cast<int>(DsRowIn::Nonlinear)) {
-            a[i] = cmul(xv, nonlinear_rotation(xv, pot[idx], tau, cl, cp));
-        } else {
-            // adjoint of the nonlinear substep: g e^{-i phi} + 2 tau (c_l q + c_p t) v
-            const cpx<R> vv = v[idx];
-            const cpx<R> e = nonlinear_rotation(vv, pot[idx], tau, cl, cp);
-            const R r = R(2) * tau * (cl * s[idx] + cp * t[idx]);
-            a[i] = {xv.x * e.x + xv.y * e.y + r * vv.x, xv.y * e.x - xv.x * e.y + r * vv.y};
+            for (int j = 0; j < 4; ++j) {
+                const size_t idx = base + tid + NT * (c + j);
+                const cpx<R> xv = x[idx];
+                const cpx<R> vv = v[idx];
+                const cpx<R> e = nonlinear_rotation(vv, pot[idx], tau, cl, cp);
+                const R r = R(2) * tau * (cl * s[idx] + cp * t[idx]);
+                lds[lds_pad(tid + NT * (c + j))] = {xv.x * e.x + xv.y * e.y + r * vv.x,
+                                                    xv.y * e.x - xv.x * e.y + r * vv.y};
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = lds[lds_pad(tid + NT * i)];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const size_t idx = base + tid + NT * i;
+            const cpx<R> xv = x[idx];
+            if constexpr (MODE == static_cast<int>(DsRowIn::Plain)) a[i] = xv;
+            else a[i] = cmul(xv, nonlinear_rotation(xv, pot[idx], tau, cl, cp));
         }
     }
     fft_reg<R, LOG, -1>(a, lds, tw, tid);

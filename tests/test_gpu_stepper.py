@@ -128,9 +128,9 @@ def test_largest_grid_step_matches_oracle(ps, dtype, bar):
 
 @pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
 def test_large_phases_match_oracle(ps, dtype, bar):
-    """Nonlinear phases from 0 up to about 1.03 rad, so that the rotation takes
-    both its short-series branch (|phase| <= pi/4) and the library branch, and
-    the series is exercised where its higher terms matter."""
+    """Nonlinear phases from 0 up to about 1.03 rad: beyond pi/4, so that the
+    rotation's argument reduction leaves quadrant 0, with the polynomials
+    exercised near the ends of their interval."""
     print(f"case: stepper 64^2 large phases {dtype}", flush=True)
     n, half, steps = 64, 4.0, 2
     p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.0, tau=0.2, n_r=32, n_theta=64, c_local=2.0,
@@ -145,6 +145,36 @@ def test_large_phases_match_oracle(ps, dtype, bar):
     st.forward(u, steps)
     err = rel_linf(u.cpu().numpy(), D.evolve(u_used, p, steps))
     print(f"rel L-inf after {steps} steps: {err:.3e}", flush=True)
+    assert err <= bar
+    st.close()
+
+
+@pytest.mark.parametrize("c_local,c_potential,bar", [(300.0, 1.0, 1e-10), (-300.0, -1.0, 1e-10),
+                                                      (4.0e6, 1.0, 1e-7)])
+def test_phases_over_many_quadrants_match_oracle(ps, c_local, c_potential, bar):
+    """FP64 nonlinear phases up to about +-200 rad (a hundred quadrants of the
+    sine/cosine argument reduction, either sign), and a field whose phases run
+    from near 0 through 1e5-1.5e6 up to about 2.6e6 rad.  One step.  The third
+    bar allows for the phase itself, a product of FP64 numbers near 1e6,
+    differing by a few units in its last place (about 1e-9) between the two
+    sides."""
+    print(f"case: stepper 64^2 phases c_local={c_local} c_potential={c_potential}", flush=True)
+    n, half = 64, 4.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.0, tau=0.2, n_r=32, n_theta=64, c_local=c_local,
+                   c_potential=c_potential)
+    st = ps.DSStepper(n, p.h, alpha=1.0, tau=p.tau, c_local=c_local, c_potential=c_potential,
+                      dtype=torch.float64, n_r=32, n_theta=64, tol=1e-12)
+    u0 = 1.8 * initial(n, half, kx=0.5, ky=0.2)
+    phase = np.abs(D.nonlinear_phase(u0, p, p.tau))
+    if abs(c_local) < 1e3:
+        assert 100.0 < np.max(phase) < 300.0
+    else:
+        assert np.max(phase) > 2.0e6 and np.any((phase > 1e5) & (phase < 1.5e6))
+    u = dev(u0, torch.float64)
+    u_used = u.cpu().numpy().astype(np.complex128)
+    st.forward(u, 1)
+    err = rel_linf(u.cpu().numpy(), D.evolve(u_used, p, 1))
+    print(f"rel L-inf after one step: {err:.3e}", flush=True)
     assert err <= bar
     st.close()
 
