@@ -113,6 +113,14 @@ def _stream_handle(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _check_disjoint(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """The library reads its input while other kernels of the same call write
+    the output, so the two must not share memory."""
+    s0, d0 = src.data_ptr(), dst.data_ptr()
+    if s0 < d0 + dst.numel() * dst.element_size() and d0 < s0 + src.numel() * src.element_size():
+        raise ValueError("input and output must not overlap")
+
+
 class Plan:
     """A solve plan on one GPU (tables + workspace live on the device).
 
@@ -157,13 +165,19 @@ class Plan:
             pass
 
     # -- helpers --------------------------------------------------------------
-    def _check_grid(self, t: torch.Tensor, name: str) -> torch.Tensor:
+    def _check_grid(self, t: torch.Tensor, name: str, output: bool = False) -> torch.Tensor:
         if t.device != self.device or t.dtype != self.dtype or tuple(t.shape) != (self.n, self.n):
             raise ValueError(f"{name} must be a {self.n}x{self.n} {self.dtype} tensor on {self.device}, "
                              f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+        if output:
+            # written in place: a contiguous copy would leave the caller's tensor untouched
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+            return t
         return t.contiguous()
 
     def _call(self, fn, src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+        _check_disjoint(src, dst)
         with torch.cuda.device(self.device):
             B.check(fn(self._handle, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                        _stream_handle(self.device)), self._handle)
@@ -172,7 +186,7 @@ class Plan:
     def _grid_out(self, out):
         if out is None:
             return torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
-        return self._check_grid(out, "out")
+        return self._check_grid(out, "out", output=True)
 
     # -- entry points ---------------------------------------------------------
     def solve(self, rho: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -217,7 +231,8 @@ class Plan:
         names = (ctypes.c_char_p * cap)()
         count = ctypes.c_int32(0)
         src = self._check_grid(src, "input")
-        out = self._check_grid(out, "out")
+        out = self._check_grid(out, "out", output=True)
+        _check_disjoint(src, out)
         with torch.cuda.device(self.device):
             B.check(B.lib().phi_solve_timed(self._handle, ctypes.c_void_p(src.data_ptr()),
                                             ctypes.c_void_p(out.data_ptr()), int(bool(adjoint)),
@@ -299,16 +314,21 @@ class BatchPlan:
         """Views of the members' n_i x n_i grids in a packed tensor."""
         return [packed[self.offsets[i]:self.offsets[i + 1]].view(n, n) for i, n in enumerate(self.sizes)]
 
-    def _check_packed(self, t: torch.Tensor, name: str) -> torch.Tensor:
+    def _check_packed(self, t: torch.Tensor, name: str, output: bool = False) -> torch.Tensor:
         if t.device != self.device or t.dtype != self.dtype or t.numel() != self.total:
             raise ValueError(f"{name} must be a packed {self.dtype} tensor of {self.total} elements on "
                              f"{self.device}, got {tuple(t.shape)} {t.dtype} on {t.device}")
+        if output:
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+            return t
         return t.contiguous()
 
     def _call(self, fn, src, out):
         src = self._check_packed(src, "input")
         out = (torch.empty(self.total, dtype=self.dtype, device=self.device) if out is None
-               else self._check_packed(out, "out"))
+               else self._check_packed(out, "out", output=True))
+        _check_disjoint(src, out)
         with torch.cuda.device(self.device):
             B.check(fn(self._handle, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                        _stream_handle(self.device)), self._handle)
@@ -326,7 +346,8 @@ class BatchPlan:
         names = (ctypes.c_char_p * cap)()
         count = ctypes.c_int32(0)
         src = self._check_packed(src, "input")
-        out = self._check_packed(out, "out")
+        out = self._check_packed(out, "out", output=True)
+        _check_disjoint(src, out)
         with torch.cuda.device(self.device):
             B.check(B.lib().phi_solve_timed(self._handle, ctypes.c_void_p(src.data_ptr()),
                                             ctypes.c_void_p(out.data_ptr()), int(bool(adjoint)),

@@ -248,6 +248,37 @@ def test_repeated_solves_are_bitwise_identical(ps, dtype):
     assert np.array_equal(c, d)
 
 
+def test_output_and_overlap_rules(ps):
+    """The binding writes results into `out` itself: a non-contiguous `out`
+    (which a copy would leave untouched) and an `out` sharing memory with the
+    input are refused; a non-contiguous input is copied and solves as usual."""
+    print("case: output and overlap rules 128^2 FP64", flush=True)
+    n = 128
+    rho = W.mixture_density(n, 8.0, W.draw_mixture(8, 5, 3.0, (0.5, 1.5)))
+    plan = ps.Plan(n, 16.0 / n, dtype=torch.float64)
+    r = to_dev(rho, torch.float64)
+    ref = plan.solve(r).cpu().numpy()
+    wide = torch.zeros((n, 2 * n), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError, match="contiguous"):
+        plan.solve(r, wide[:, :n])
+    with pytest.raises(ValueError, match="overlap"):
+        plan.solve(r, r)
+    with pytest.raises(ValueError, match="overlap"):
+        plan.solve_adjoint(r, r)
+    wide[:, 1::2] = r
+    assert np.array_equal(plan.solve(wide[:, 1::2]).cpu().numpy(), ref)
+    assert float(wide[:, ::2].abs().max()) == 0.0
+    plan.close()
+    bp = ps.BatchPlan([dict(n=128, h=1 / 16), dict(n=256, h=1 / 16)], dtype=torch.float32)
+    src = torch.zeros(bp.total, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError, match="overlap"):
+        bp.solve(src, src)
+    two = torch.zeros(2 * bp.total, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError, match="contiguous"):
+        bp.solve(src, two[::2])
+    bp.close()
+
+
 def test_autograd_backward_is_the_adjoint(ps):
     n, half = 128, 8.0
     rho = W.mixture_density(n, half, W.draw_mixture(9, 8, 3.0, (0.5, 1.5)))
