@@ -94,6 +94,22 @@ def test_batch_members_match_oracle_and_single_plans(ps, dtype):
     bp.close()
 
 
+@pytest.mark.parametrize("n,dtype", [(128, torch.float64), (2048, torch.float32)])
+def test_one_member_batch_equals_single_plan(ps, n, dtype):
+    """The degenerate batch of one member (the smallest and the largest side a
+    batch takes): forward and transposed solves equal the single plan's bits."""
+    members = member_list(1, seed=21, sizes=[n])
+    print(f"case: one-member batch N={n} {dtype}", flush=True)
+    bp = ps.BatchPlan(batch_params(members, dtype), dtype=dtype)
+    packed = bp.pack([members[0][2]])
+    used = [t.double().cpu().numpy() for t in bp.unpack(packed)]
+    fwd = bp.unpack(bp.solve(packed))[0].cpu().numpy()
+    back = bp.unpack(bp.solve_adjoint(packed))[0].cpu().numpy()
+    assert np.array_equal(fwd, single_solves(ps, members, dtype, inputs=used)[0])
+    assert np.array_equal(back, single_solves(ps, members, dtype, adjoint=True, inputs=used)[0])
+    bp.close()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_adjoint_matches_single_plans_and_oracle(ps, dtype):
     sizes = [128, 512, 256, 128]
