@@ -248,6 +248,28 @@ def test_checkpointed_gradient_matches_oracle_reverse_pass(ps, dtype, bar):
     st.close()
 
 
+@pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-13), (torch.float32, 1e-6)])
+def test_zero_steps(ps, dtype, bar):
+    """The degenerate run of zero steps: the forward leaves the field bit for
+    bit, and the loss and gradient are those of the field itself
+    (J = h^2 sum |u0|^4, dJ/du0 = 4 h^2 |u0|^2 u0), with no solves counted."""
+    print(f"case: stepper zero steps 32^2 {dtype}", flush=True)
+    n, half = 32, 4.0
+    p = D.DSParams(n=n, h=2 * half / n, alpha=1.0, beta=1.0, tau=1e-2, n_r=16, n_theta=32)
+    st = ps.DSStepper(n, p.h, alpha=1.0, beta=1.0, tau=p.tau, dtype=dtype, n_r=16, n_theta=32, tol=TOL[dtype])
+    u = dev(initial(n, half, ky=0.4), dtype)
+    before = u.clone()
+    st.forward(u, 0)
+    assert torch.equal(u, before)
+    u_used = u.cpu().numpy().astype(np.complex128)
+    loss, g, counts = st.loss_and_grad(u, 0, checkpoint_every=4)
+    assert counts == {"forward_solves": 0, "recomputed_solves": 0, "adjoint_solves": 0}
+    ref_loss, ref_g = D.loss_l4_gradient(u_used, p, 0)
+    assert abs(float(loss) - ref_loss) / ref_loss <= bar
+    assert rel_linf(g.cpu().numpy(), ref_g) <= bar
+    st.close()
+
+
 def test_gradient_against_central_differences(ps):
     print("case: L4 gradient FD 64^2 FP64", flush=True)
     n, half, steps = 64, 4.0, 5
