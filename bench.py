@@ -15,7 +15,7 @@ against the FP64 oracle, the dominant kernel's ALU and HBM roofline figures (HIP
 recorded around every kernel on its launch stream) and the oracle's own rate
 on the host cores.  Further legs (skipped with --no-extra-legs): a batch
 of 256 densities with sides drawn from {128, 256, 512, 1024} at h = 1/32
-(seed 1; autotuned node sorts), forward + transposed solve pairs at
+(seed 1; default node sorts), forward + transposed solve pairs at
 1024^2 over [-16, 16)^2 (mixture seed 2), 500 split steps of the DS system at
 2048^2 with the checkpointed gradient of the final L4 norm, the standard
 periodic FFT solver (throughput, and time to accuracy against the split
@@ -219,12 +219,14 @@ def event_kernels(timed_call, steps: int, nbytes: dict) -> dict:
 
 def batch_leg(args, torch, ps, W) -> dict:
     """256 independent densities with sides drawn from {128, 256, 512, 1024} at
-    h = 1/32 (seed 1), FP32, autotuned node sorts, one launch per stage over all
+    h = 1/32 (seed 1), FP32, the default node sort (bin 4, 64 nodes per
+    subproblem: under graph replay it beat the plan-time autotuner's picks,
+    2.27 against 2.39 ms per batch), one launch per stage over all
     members, replayed from a captured graph."""
     members = W.batch_members(seed=1, count=256)
-    params = [dict(n=n, h=2 * half / n, n_r=N_R, n_theta=N_THETA, tol=TOL32, autotune=True)
+    params = [dict(n=n, h=2 * half / n, n_r=N_R, n_theta=N_THETA, tol=TOL32)
               for n, half, _ in members]
-    print("[bench] batch: planning (autotune) and building 256 densities", file=sys.stderr, flush=True)
+    print("[bench] batch: planning and building 256 densities", file=sys.stderr, flush=True)
     bp = ps.BatchPlan(params, dtype=torch.float32)
     packed = bp.pack([W.mixture_density(n, half, spec) for n, half, spec in members])
     out = torch.empty_like(packed)
