@@ -73,7 +73,10 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
                                 subproblem sizes {32, 64} on the device and keep the fastest; the
                                 choice is visible in phi_plan_info.bin / .sub_nodes.  Results of
-                                different choices differ by rounding only. */
+                                different choices differ by rounding only.  The candidates are timed
+                                as eager whole solves; for solves replayed from a captured graph,
+                                and for batches, the default (bin 4, 64 nodes) measured as fast or
+                                faster on MI355X. */
 
 /* Problem statement as the paper gives it (Sec. 2.1): the density on a uniform
  * box with spacing, the padding factor kappa, the partition width sigma and
