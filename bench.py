@@ -55,10 +55,10 @@ VALU_PEAK_PUBLISHED_F32 = 157.3
 TRAFFIC_RECORD = {
     "kernel": "cols_highfreq",
     "fetch_kib": 16750.1, "write_kib": 32784.0,
-    "copy_fetch_kib": 131088.6, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "copy_fetch_kib": 131088.8, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
     "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "d2e4b95823534a23ff752a3d5c30c9bc5b92f15c8878df5c2a0870468b5c98f1",
+    "sha256": "840e21fffd7d67c7fd61d14fce3913d97903fc1d07c4d3fd49d365ef01668752",
 }
 
 N = 2048

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -190,6 +191,13 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->width = hp.width;
     d->n_nodes = hp.n_nodes;
     d->component = hp.component;
+    // The two branches of a solve share the GPU, and the one enqueued first is
+    // served first: the node-side chain (the same few small kernels at every N)
+    // unless the high-frequency columns carry more than 1.5 times the work they
+    // have in a 2048^2 FP32 solve (N F log2 F times the element size), where
+    // they are the longer branch (FP64 at 2048^2, both precisions at 4096^2).
+    const double col_work = hp.n * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
+    d->highfreq_first = col_work > 1.5 * (2048.0 * 4096.0 * 12.0 * 4.0) ? 1 : 0;
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));
     d->h2 = hp.h * hp.h;

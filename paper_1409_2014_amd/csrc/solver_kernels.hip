@@ -245,11 +245,14 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
                 PHI_TRY(hipEventRecord(ss.fork, s));
                 PHI_TRY(hipStreamWaitEvent(side, ss.fork, 0));
             }
+            // the branch enqueued first is served first by the dispatcher (the
+            // plan picks it by the size of the column work)
+            if (P.highfreq_first) PHI_STEP("cols_highfreq", s, (run_cols_highfreq<R>(P, dir, s)));
             PHI_STEP("cols_type2", side, (run_cols_type2<R>(P, dir, side)));
             PHI_STEP("nodes", side, (run_nodes<R, 0>(P, nullptr, nullptr, side)));
             PHI_STEP("cols_type1", side, (run_cols_type1<R>(P, -dir, side)));
             if (ss.side) PHI_TRY(hipEventRecord(ss.join, side));
-            PHI_STEP("cols_highfreq", s, (run_cols_highfreq<R>(P, dir, s)));
+            if (!P.highfreq_first) PHI_STEP("cols_highfreq", s, (run_cols_highfreq<R>(P, dir, s)));
             if (ss.side) PHI_TRY(hipStreamWaitEvent(s, ss.join, 0));
             PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
             return hipSuccess;

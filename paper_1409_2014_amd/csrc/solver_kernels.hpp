@@ -15,6 +15,7 @@ struct DevPlan {
     int n, n_fine, log_fine;
     int patch, patch_lo, width, n_nodes;
     int component;          // 0: -kx^2/|k|^2, 1: -ky^2/|k|^2, 2: -kx ky/|k|^2
+    int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
     double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index
     int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
     double h2, inv_f2;
