@@ -9,7 +9,8 @@ nodes, NUFFT tolerance 1e-7 (FP32 data path) and 1e-12 (FP64 data path).
 
 A step is one potential solve Phi = I1 + I2 (every kernel of the chain) with
 rho already resident in device memory.  `value` is FP32 solves/s over K timed
-steps; the same line carries the FP64 rate, the FP32/FP64 ratio, the rate of
+steps, each timed leg preceded by W untimed steps and then by untimed replays
+for WARM_SECONDS of wall time (`warmup_s`); the same line carries the FP64 rate, the FP32/FP64 ratio, the rate of
 forward + transposed solve pairs, the relative errors of both data paths
 against the FP64 oracle, the dominant kernel's ALU and HBM roofline figures (HIP events
 recorded around every kernel on its launch stream) and the oracle's own rate
@@ -122,7 +123,26 @@ def recorded_traffic(kernel: str):
     return round((fetch + write) * 1024)
 
 
+# Untimed replays before every timed leg, by wall time rather than by count: a
+# short timed region (the default --steps of a quick run is a few ms of work)
+# otherwise starts before the GPU's clocks have settled, and reads slow.
+WARM_SECONDS = 0.3
+
+
+def warm(fn, torch, seconds: float = WARM_SECONDS) -> None:
+    """Run fn until `seconds` of wall time have passed (at least once), then synchronise."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            break
+
+
 def timed_rate(fn, steps: int, torch) -> float:
+    warm(fn, torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -545,6 +565,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": k,
         "warmup": args.warmup,
+        "warmup_s": WARM_SECONDS,
         "ms_per_step": 1e3 * t32 / k,
         "higher_is_better": True,
         "scaling": "weak",

@@ -390,11 +390,14 @@ phi_status run(phi_plan_t plan, phi::Stage stage, const void* in, void* out, int
     return PHI_OK;
 }
 
-// Field-wise equality (the struct's padding bytes are not compared).
+// Field-wise equality of every field of phi_params (the struct's padding
+// bytes are not compared); members that differ only in their node sort get
+// table sets of their own.
 bool same_params(const phi_params& a, const phi_params& b) {
     return a.nx == b.nx && a.ny == b.ny && a.hx == b.hx && a.hy == b.hy && a.n_r == b.n_r &&
            a.n_theta == b.n_theta && a.tol == b.tol && a.pad == b.pad && a.sigma == b.sigma &&
-           a.cutoff == b.cutoff && a.dtype == b.dtype && a.flags == b.flags;
+           a.cutoff == b.cutoff && a.dtype == b.dtype && a.flags == b.flags && a.bin == b.bin &&
+           a.sub_nodes == b.sub_nodes;
 }
 
 // Work items of one member and stage: first row / column / subproblem of each

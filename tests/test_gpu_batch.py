@@ -127,7 +127,10 @@ def test_batch_adjoint_matches_single_plans_and_oracle(ps, dtype):
     for i, (n, half, _) in enumerate(members):
         assert np.array_equal(got[i], single[i]), f"member {i} (N={n})"
         ref = O.phi_transpose(used[i], O.SplitParams(n=n, h=2 * half / n, n_r=64, n_theta=128))
-        assert rel_linf(got[i], ref) <= 10 * BARS[dtype], f"member {i} N={n}"
+        e_inf, e_2 = rel_linf(got[i], ref), rel_l2(got[i], ref)
+        print(f"  member {i} N={n}: rel L-inf {e_inf:.3e}, L2 {e_2:.3e}", flush=True)
+        assert e_2 <= BARS[dtype], f"member {i} N={n}"
+        assert e_inf <= BARS[dtype], f"member {i} N={n}"
     bp.close()
 
 
@@ -163,6 +166,29 @@ def test_full_uneven_batch_fp32(ps):
         assert rel_linf(got[i], ref) <= 1e-6, f"member {i} N={n}"
         assert rel_l2(got[i], ref) <= 1e-6, f"member {i} N={n}"
     assert checked == {128: 4, 256: 4, 512: 4, 1024: 4}
+    bp.close()
+
+
+def test_members_differing_only_in_node_sort_keep_their_own(ps):
+    """Two members with equal parameters except the requested node sort: each
+    keeps its own bin side and subproblem size, and each equals the single plan
+    of its own parameters bit for bit."""
+    sizes = [256, 256, 256]
+    members = member_list(len(sizes), seed=4, sizes=sizes)
+    sort = [(4, 64), (8, 32), (4, 64)]
+    print("case: batch members differing in node sort", flush=True)
+    dtype = torch.float32
+    params = [dict(p, bin=b, sub_nodes=sn) for p, (b, sn) in zip(batch_params(members, dtype), sort)]
+    bp = ps.BatchPlan(params, dtype=dtype)
+    for i, (b, sn) in enumerate(sort):
+        info = bp.member_info(i)
+        assert (info["bin"], info["sub_nodes"]) == (b, sn), f"member {i}"
+    packed = bp.pack([m[2] for m in members])
+    got = [g.cpu().numpy() for g in bp.unpack(bp.solve(packed))]
+    used = [g.double().cpu().numpy() for g in bp.unpack(packed)]
+    single = single_solves(ps, members, dtype, inputs=used, sort=sort)
+    for i in range(len(members)):
+        assert np.array_equal(got[i], single[i]), f"member {i}"
     bp.close()
 
 

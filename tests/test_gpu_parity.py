@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded inputs.  Bars: rel L-inf and L2 <= 1e-10 (FP64 data path) and
 <= 1e-6 (FP32 data path, oracle run on the FP32-rounded input promoted to
-FP64); each NUFFT stage alone within 10x its tolerance in relative l2."""
+FP64); each NUFFT stage alone within 10x its tolerance in relative l2, on a
+smooth density and on white noise."""
 import math
 
 import numpy as np
@@ -72,38 +73,63 @@ def test_highfreq_and_lowfreq_parts_fp64(ps):
     assert np.max(np.abs(i2 - parts["i2"])) <= 1e-11 * scale
 
 
+# Stage bars: 10 tol in relative l2 (the NUFFT tolerance is a relative l2 target
+# for each transform), on two inputs.  "smooth": the mixture density of the
+# workloads (for type 1: the coefficients a_j = q_j rho_hat_j of that density,
+# the values the solve spreads).  "noise": independent standard normal grid
+# values (type 2) or coefficients (type 1).  Measured on MI355X: FP32 at tol
+# 1e-7 gives 0.5e-7 .. 3e-7 (smooth) and 2.4e-7 .. 4.3e-7 (noise); FP64 at tol
+# 1e-12 stays below 2.6e-12.
+STAGE_CASES = [(torch.float64, 1e-12, "smooth", 1e-11), (torch.float64, 1e-12, "noise", 1e-11),
+               (torch.float64, 1e-6, "noise", 1e-5), (torch.float32, 1e-7, "smooth", 1e-6),
+               (torch.float32, 1e-7, "noise", 1e-6)]
+
+
+def stage_density(kind, n, half):
+    if kind == "noise":
+        return np.random.default_rng(21).standard_normal((n, n))
+    return W.mixture_density(n, half, W.draw_mixture(23, 8, 0.375 * half, (0.5, 2.0)))
+
+
 @pytest.mark.parametrize("kernel", ["es", "gaussian"])
-@pytest.mark.parametrize("dtype,tol,bar", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-7, 1e-5),
-                                           (torch.float64, 1e-6, 1e-5)])
-def test_type2_stage_against_direct_sums(ps, dtype, tol, bar, kernel):
-    print(f"case: type2 {dtype} tol={tol} kernel={kernel}", flush=True)
+@pytest.mark.parametrize("dtype,tol,kind,bar", STAGE_CASES)
+def test_type2_stage_against_direct_sums(ps, dtype, tol, kind, bar, kernel):
+    print(f"case: type2 {dtype} tol={tol} {kind} kernel={kernel}", flush=True)
     n, half = 256, 8.0
-    rho = np.random.default_rng(21).standard_normal((n, n))
+    rho = stage_density(kind, n, half)
     plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol, kernel=kernel)
     r = to_dev(rho, dtype)
     got = plan.type2(r).cpu().numpy().astype(np.complex128)
     kx, ky, _ = plan.nodes()
     ref = O.type2_direct(r.double().cpu().numpy(), 2 * half / n, O.grid_points(O.SplitParams(n, 2 * half / n, 1, 2)),
                          kx, ky)
-    assert rel_l2(got, ref) <= bar
+    err = rel_l2(got, ref)
+    print(f"  rel l2 {err:.3e} (bar {bar:.0e})", flush=True)
+    assert err <= bar
 
 
 @pytest.mark.parametrize("kernel", ["es", "gaussian"])
-@pytest.mark.parametrize("dtype,tol,bar", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-7, 1e-5)])
-def test_type1_stage_against_direct_sums(ps, dtype, tol, bar, kernel):
-    print(f"case: type1 {dtype} kernel={kernel}", flush=True)
+@pytest.mark.parametrize("dtype,tol,kind,bar", [c for c in STAGE_CASES if c[1] != 1e-6])
+def test_type1_stage_against_direct_sums(ps, dtype, tol, kind, bar, kernel):
+    print(f"case: type1 {dtype} {kind} kernel={kernel}", flush=True)
     n, half = 256, 8.0
-    plan = ps.Plan(n, 2 * half / n, dtype=dtype, tol=tol, kernel=kernel)
+    h = 2 * half / n
+    plan = ps.Plan(n, h, dtype=dtype, tol=tol, kernel=kernel)
     m = plan.info["n_nodes"]
-    rng = np.random.default_rng(22)
-    coef = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    kx, ky, q = plan.nodes()
+    xs = O.grid_points(O.SplitParams(n, h, 1, 2))
+    if kind == "noise":
+        rng = np.random.default_rng(22)
+        coef = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    else:
+        coef = q * O.type2_direct(stage_density("smooth", n, half), h, xs, kx, ky)
     cdt = torch.complex128 if dtype == torch.float64 else torch.complex64
     c = torch.as_tensor(coef, dtype=cdt, device="cuda")
     got = plan.type1(c).double().cpu().numpy()
-    kx, ky, _ = plan.nodes()
-    xs = O.grid_points(O.SplitParams(n, 2 * half / n, 1, 2))
     ref = O.type1_direct(c.cpu().numpy().astype(np.complex128), xs, kx, ky).real
-    assert rel_l2(got, ref) <= bar
+    err = rel_l2(got, ref)
+    print(f"  rel l2 {err:.3e} (bar {bar:.0e})", flush=True)
+    assert err <= bar
 
 
 # --------------------------------------------------------------------------
@@ -371,11 +397,15 @@ def test_jacobi_radial_rule_and_the_papers_node_counts(ps, dtype, bar):
 
 
 @pytest.mark.parametrize("dtype,bar", [(torch.float64, 1e-10), (torch.float32, 1e-6)])
-def test_the_papers_exact_variant(ps, dtype, bar):
+def test_the_papers_exact_variant(ps, dtype, bar, golden):
     """Everything as the paper states it (Sec. 2.1): Gauss-Jacobi radial rule,
     60 x 60 polar nodes and Greengard-Lee Gaussian gridding for both NUFFTs,
     against the oracle with the same quadrature; and Example 1 on [-8, 8)^2 at
-    h = 1/8 against its closed form (Table 2 prints 1.55E-10 there)."""
+    h = 1/8 against its closed form: the error must reproduce the value Table 2
+    prints for that grid (read from the golden table) within 2 %, the band the
+    oracle's own pin uses, and equal the oracle's error on the same grid and
+    rule to within 0.1 % of it (the GPU and oracle results differ by rounding,
+    about 1e-14, against an error of 1.6e-10)."""
     print(f"case: paper variant 256^2 {dtype}", flush=True)
     n, half = 256, 8.0
     rho = W.mixture_density(n, half, W.draw_mixture(14, 8, 4.0, (0.5, 1.5)))
@@ -391,8 +421,14 @@ def test_the_papers_exact_variant(ps, dtype, bar):
         plan, _, got = run_solve(ps, W.paper_gaussian_density(n, half), n, 2 * half / n, dtype, **kw)
         ex = O.closed_forms.phi_isotropic_gaussian(x, y, math.pi, math.pi ** 2)
         err = rel_linf(got, ex)
-        print(f"  Example 1, L = 8, h = 1/8: {err:.3e}", flush=True)
-        assert abs(err - 1.55e-10) <= 0.01 * 1.55e-10
+        printed = [row[2] for row in golden("table2_gaussian_nufft.txt") if row[0] == 8 and row[1] == 0.125]
+        assert len(printed) == 1
+        p = O.SplitParams(n=n, h=2 * half / n, n_r=60, n_theta=60, radial="jacobi")
+        err_oracle = rel_linf(O.phi(W.paper_gaussian_density(n, half), p), ex)
+        print(f"  Example 1, L = 8, h = 1/8: {err:.4e} (oracle {err_oracle:.4e}, Table 2 {printed[0]:.2e})",
+              flush=True)
+        assert abs(err - printed[0]) <= 0.02 * printed[0]
+        assert abs(err - err_oracle) <= 1e-3 * err_oracle
 
 
 # --------------------------------------------------------------------------
