@@ -155,6 +155,22 @@ phi_status phi_batch_member_info(phi_plan_t plan, int32_t member, phi_plan_info*
 /* Phi = A rho (Sec. 2.1, eq. 8: I1 + I2).  rho, phi: N x N device arrays. */
 phi_status phi_solve(phi_plan_t plan, const void* rho, void* phi, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same solve as
+ * phi_solve, with the same kernels and the same results bit for bit, whose
+ * workspace is a static device array of the library (80 MiB, one copy per
+ * device, held until the process ends) instead of the plan's own.  It calls no
+ * allocating routine; the plan itself is made beforehand by phi_plan.
+ * rho, phi: N x N device arrays as for phi_solve (caller-owned).
+ * Single plans only (PHI_ERR_UNSUPPORTED on a batch plan).  A plan whose
+ * workspace exceeds the scratch (beyond N = 2048 at the default node counts)
+ * returns PHI_ERR_UNSUPPORTED with the sizes in phi_last_error; nothing is
+ * enqueued then.  Every call on one device shares that device's scratch and
+ * leaves its contents behind: calls that overlap in time on one device (on
+ * different streams, or from different threads) race and give wrong results;
+ * order them on one stream. */
+phi_status phi_solve_noalloc(phi_plan_t plan, const void* rho, void* phi, void* stream);
+
 /* g_rho = A^T g_phi: the transposed chain (every transform direction reversed:
  * the grid-to-node NUFFT becomes the transpose of the node-to-grid one and vice
  * versa, the diagonal multipliers are their own transposes).  Used for the

@@ -85,6 +85,7 @@ def _declare(lib):
         "phi_batch_layout": (st, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
         "phi_batch_member_info": (st, [_P, ctypes.c_int32, ctypes.POINTER(PhiPlanInfo)]),
         "phi_solve": (st, [_P, _P, _P, _P]),
+        "phi_solve_noalloc": (st, [_P, _P, _P, _P]),
         "phi_solve_adjoint": (st, [_P, _P, _P, _P]),
         "phi_solve_highfreq": (st, [_P, _P, _P, _P]),
         "phi_solve_lowfreq": (st, [_P, _P, _P, _P]),
@@ -143,7 +144,7 @@ def exported_symbols():
     return [
         "phi_params_default", "phi_describe", "phi_plan", "phi_plan_batch", "phi_batch_layout",
         "phi_batch_member_info",
-        "phi_solve", "phi_solve_adjoint",
+        "phi_solve", "phi_solve_noalloc", "phi_solve_adjoint",
         "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1", "phi_solve_periodic",
         "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre", "phi_host_gauss_jacobi01",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",

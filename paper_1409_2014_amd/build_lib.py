@@ -48,7 +48,8 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for src, compiler in (("plan_host.cpp", "gxx"), ("phi_api.cpp", "gxx"), ("ds_api.cpp", "gxx"),
                           ("solver_kernels.hip", "hipcc"), ("batch_kernels.hip", "hipcc"),
-                          ("ds_kernels.hip", "hipcc"), ("periodic_kernels.hip", "hipcc")):
+                          ("ds_kernels.hip", "hipcc"), ("periodic_kernels.hip", "hipcc"),
+                          ("scratch.hip", "hipcc")):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         path = os.path.join(CSRC, src)
         if compiler == "gxx":

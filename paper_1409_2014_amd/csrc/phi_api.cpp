@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -179,6 +180,16 @@ hipError_t upload_tables(const phi::HostPlan& hp, const TableParts& t, char* bas
     return e;
 }
 
+// Points the workspace of the device view into the memory at `base`.
+void point_work(char* base, const WorkParts& w, phi::DevPlan* d) {
+    d->xt = base + w.xt.off;
+    d->tt = base + w.tt.off;
+    d->win = base + w.win.off;
+    d->pts = base + w.pts.off;
+    d->tiles = base + w.tiles.off;
+    d->u = base + w.u.off;
+}
+
 void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableParts& t,
               const WorkParts& w, phi::DevPlan* d) {
     const double f = hp.n_fine;
@@ -219,12 +230,7 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->twr_count = static_cast<int>(hp.twr.size() / 2);
     d->twn = base + t.twn.off;
     d->twn_count = static_cast<int>(hp.twn.size() / 2);
-    d->xt = base + w.xt.off;
-    d->tt = base + w.tt.off;
-    d->win = base + w.win.off;
-    d->pts = base + w.pts.off;
-    d->tiles = base + w.tiles.off;
-    d->u = base + w.u.off;
+    point_work(base, w, d);
 }
 
 phi_status create_streams(phi_plan_t plan) {
@@ -725,6 +731,35 @@ phi_status phi_plan_nodes(phi_plan_t plan, double* kx, double* ky, double* q) {
 
 phi_status phi_solve(phi_plan_t plan, const void* rho, void* phi_out, void* stream) {
     return run(plan, phi::Stage::Solve, rho, phi_out, 0, stream);
+}
+
+phi_status phi_solve_noalloc(phi_plan_t plan, const void* rho, void* phi_out, void* stream) {
+    phi_status st = check_plan(plan);
+    if (st != PHI_OK) return st;
+    if (!rho || !phi_out) return fail(plan, PHI_ERR_INVALID_ARG, "NULL data pointer");
+    if (rho == phi_out) return fail(plan, PHI_ERR_INVALID_ARG, "input and output must not alias");
+    if (plan->n_members > 0) return fail(plan, PHI_ERR_UNSUPPORTED, "phi_solve_noalloc takes single plans only");
+    st = check_device(plan);
+    if (st != PHI_OK) return st;
+    // the same workspace layout as the plan's own, placed in the static scratch
+    const size_t es = plan->host.dtype == PHI_F32 ? 4 : 8;
+    Layout L;
+    const WorkParts wp = layout_work(plan->host, es, L);
+    if (L.cursor > phi::scratch_capacity()) {
+        char msg[200];
+        std::snprintf(msg, sizeof(msg),
+                      "phi_solve_noalloc: this plan needs %zu bytes of scratch; the static scratch holds %zu",
+                      L.cursor, phi::scratch_capacity());
+        return fail(plan, PHI_ERR_UNSUPPORTED, msg);
+    }
+    void* base = nullptr;
+    hipError_t e = phi::scratch_region(plan->device, &base);
+    if (e != hipSuccess) return device_fail(plan, e, "static scratch address");
+    phi::DevPlan d = plan->dev;
+    point_work(static_cast<char*>(base), wp, &d);
+    e = phi::enqueue(d, plan->streams, phi::Stage::Solve, rho, phi_out, 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
+    return PHI_OK;
 }
 
 phi_status phi_solve_adjoint(phi_plan_t plan, const void* g_phi, void* g_rho, void* stream) {

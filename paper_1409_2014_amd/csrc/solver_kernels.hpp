@@ -113,6 +113,12 @@ struct BatchDev {
     int wide_kernel = 0;               // some member's kernel is wider than kMaxEsWidth
 };
 
+// The static device scratch of phi_solve_noalloc: its size in bytes, and its
+// address on `device`, which must be the current device (looked up on the
+// first call per device and kept).
+size_t scratch_capacity();
+hipError_t scratch_region(int device, void** ptr);
+
 // Enqueue one solve (adjoint = 0) or transposed solve (adjoint = 1) of every
 // member on stream s: five launches in stream order.
 hipError_t enqueue_batch(const BatchDev& B, const void* in, void* out, int adjoint, hipStream_t s,
