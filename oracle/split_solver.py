@@ -25,7 +25,8 @@ exactly these direct sums.
 
 Readings of points the paper leaves open (each is listed in the design notes):
   * 2 pi convention of eqs. 4-5 throughout; the Fourier grid of I1 is
-    k_m = m / (kappa N h), m in FFT order (-M/2 .. M/2-1).
+    k_m = m / (M h), m in FFT order (-M/2 .. M/2-1), on the padded box of
+    side M = kappa N (or any M >= 2N given as pad_side; kappa = M / N).
   * the grid holds N points x_n = -L + n h, n = 0..N-1 (periodic box).
   * g1(0) = 0, its limit (Sec. 2.1: the I1 integrand vanishes at the origin).
   * sigma = sqrt(lambda) / (2 pi (kappa-1) L), lambda = ln(1/eps_s): the
@@ -70,6 +71,9 @@ class SplitParams:
     n        grid points per side (even), spacing h, box [-L, L)^2 with L = n h / 2
     n_r      radial Gauss nodes;  n_theta  azimuthal trapezoid nodes
     kappa    zero-padding factor of the I1 box (Sec. 2.1: kappa >= 2)
+    pad_side side M of the zero-padded I1 box in grid points (None: kappa n).
+             Sec. 2.1 pads the box by a factor kappa >= 2; any M >= 2n is such
+             a box, with kappa = M / n, which also fixes the default sigma
     sigma    partition width; cutoff  disk radius c (None -> default reading)
     eps_split   target size of the neglected tails (defines the defaults)
     component   "xx": multiplier -kx^2/|k|^2 (the DS potential, eq. 4);
@@ -89,10 +93,24 @@ class SplitParams:
     eps_split: float = 1e-16
     component: str = "xx"
     radial: str = "legendre"    # or "jacobi": Gauss-Jacobi(0, 1), the weight r built in
+    pad_side: int | None = None
 
     @property
     def half_width(self) -> float:
         return 0.5 * self.n * self.h
+
+    @property
+    def padded_side(self) -> int:
+        """Side M of the zero-padded I1 box (Sec. 2.1 asks for kappa >= 2)."""
+        m = self.kappa * self.n if self.pad_side is None else int(self.pad_side)
+        if m < 2 * self.n:
+            raise ValueError(f"the padded box must be at least twice the grid (kappa >= 2): {m} < 2 * {self.n}")
+        return m
+
+    @property
+    def kappa_eff(self) -> float:
+        """The padding factor of the box actually used, M / n."""
+        return self.padded_side / self.n
 
 
 def split_constants(p: SplitParams) -> tuple[float, float]:
@@ -100,7 +118,7 @@ def split_constants(p: SplitParams) -> tuple[float, float]:
     lam = math.log(1.0 / p.eps_split)
     sigma = p.sigma
     if sigma is None:
-        sigma = math.sqrt(lam) / (2.0 * math.pi * (p.kappa - 1) * p.half_width)
+        sigma = math.sqrt(lam) / (2.0 * math.pi * (p.kappa_eff - 1) * p.half_width)
     c = p.cutoff
     if c is None:
         c = math.sqrt(lam) * sigma
@@ -127,15 +145,15 @@ def highfreq_multiplier(kx: np.ndarray, ky: np.ndarray, sigma: float,
 
 
 def _padded_frequencies(p: SplitParams) -> tuple[np.ndarray, np.ndarray]:
-    m_side = p.kappa * p.n
-    k = np.fft.fftfreq(m_side, d=p.h)           # k_m = m / (kappa N h)
+    m_side = p.padded_side
+    k = np.fft.fftfreq(m_side, d=p.h)           # k_m = m / (M h)
     ky, kx = np.meshgrid(k, k, indexing="ij")
     return kx, ky
 
 
 def padded_multiplier(p: SplitParams) -> np.ndarray:
     """g1 on the padded DFT grid.  The mixed multiplier is odd in each of kx,
-    ky, and on the Nyquist lines (index kappa N / 2) one DFT bin stands for +k
+    ky, and on the Nyquist lines (index M / 2) one DFT bin stands for +k
     and -k; the bin takes the mean of the multiplier over them, which is 0 (also
     at the corner, where numpy's negative representatives alone would give
     -1/2)."""
@@ -143,7 +161,7 @@ def padded_multiplier(p: SplitParams) -> np.ndarray:
     kx, ky = _padded_frequencies(p)
     g1 = highfreq_multiplier(kx, ky, sigma, p.component)
     if p.component == "xy":
-        nyq = (p.kappa * p.n) // 2
+        nyq = p.padded_side // 2
         g1[nyq, :] = 0.0
         g1[:, nyq] = 0.0
     return g1
@@ -153,22 +171,23 @@ def i1_padded_fft(rho: np.ndarray, p: SplitParams) -> np.ndarray:
     """I1 on the grid (Sec. 2.1, eq. 9 by the trapezoidal rule on the padded box).
 
     rho_hat(k_m) ~ h^2 sum_n rho_n e^{-2 pi i k_m.x_n} (trapezoid on B_p), the k
-    integral ~ (Delta k)^2 sum_m with Delta k = 1/(kappa N h); the phases only
-    involve x_n - x_n', so the density sits at the corner of the padded array:
-        I1_n = Re[(kappa N)^-2 sum_m g1(k_m) S_m e^{+2 pi i m.n/(kappa N)}],
-        S_m  = sum_n P_n e^{-2 pi i m.n/(kappa N)},  P = zero-padded rho."""
-    m_side = p.kappa * p.n
+    integral ~ (Delta k)^2 sum_m with Delta k = 1/(M h) (M = kappa N the padded
+    side); the phases only involve x_n - x_n', so the density sits at the corner
+    of the padded array:
+        I1_n = Re[M^-2 sum_m g1(k_m) S_m e^{+2 pi i m.n/M}],
+        S_m  = sum_n P_n e^{-2 pi i m.n/M},  P = zero-padded rho."""
+    m_side = p.padded_side
     padded = np.zeros((m_side, m_side), dtype=np.float64)
     padded[: p.n, : p.n] = rho
     s_hat = np.fft.fft2(padded)                      # S_m (unnormalised DFT)
     g1 = padded_multiplier(p)
-    full = np.fft.ifft2(g1 * s_hat)                  # includes (kappa N)^-2
+    full = np.fft.ifft2(g1 * s_hat)                  # includes M^-2
     return full[: p.n, : p.n].real.copy()
 
 
 def i1_padded_dft_matrix(rho: np.ndarray, p: SplitParams) -> np.ndarray:
     """Same sum as i1_padded_fft written with explicit DFT matrices (small N only)."""
-    m_side = p.kappa * p.n
+    m_side = p.padded_side
     m = np.arange(m_side)
     n = np.arange(p.n)
     fwd = np.exp(-2j * np.pi * np.outer(m, n) / m_side)    # [m][n]
@@ -280,7 +299,7 @@ def phi_transpose(g: np.ndarray, p: SplitParams) -> np.ndarray:
            E1[n][j] = e^{+2 pi i k_j.x_n}  ->  A2^T = Re(E2^T . diag(q) . E1^T).
     For a complex matrix C acting on real vectors, (Re C)^T = Re(C^T)."""
     g = np.asarray(g, dtype=np.float64)
-    m_side = p.kappa * p.n
+    m_side = p.padded_side
     padded = np.zeros((m_side, m_side), dtype=np.float64)
     padded[: p.n, : p.n] = g
     g1 = padded_multiplier(p)

@@ -271,8 +271,10 @@ def test_quadrature_convergence():
 # Library steps and brute force
 # --------------------------------------------------------------------------
 
-def test_padded_fft_equals_explicit_dft():
-    p = O.SplitParams(n=16, h=0.5, n_r=8, n_theta=16)
+@pytest.mark.parametrize("pad_side", [None, 40, 48])
+def test_padded_fft_equals_explicit_dft(pad_side):
+    # boxes of 2N (default), 2.5N and 3N points
+    p = O.SplitParams(n=16, h=0.5, n_r=8, n_theta=16, pad_side=pad_side)
     rho = np.random.default_rng(2).standard_normal((16, 16))
     assert np.max(np.abs(O.i1_padded_fft(rho, p) - O.i1_padded_dft_matrix(rho, p))) < 1e-13
 
@@ -351,3 +353,47 @@ def test_jacobi_and_legendre_radial_rules_converge_to_one_value():
     a = O.phi(rho, O.SplitParams(n=32, h=0.25, n_r=48, n_theta=96))
     b = O.phi(rho, O.SplitParams(n=32, h=0.25, n_r=48, n_theta=96, radial="jacobi"))
     assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
+
+
+# --------------------------------------------------------------------------
+# The padded box of I1 (Sec. 2.1: a box kappa >= 2 times the grid's)
+# --------------------------------------------------------------------------
+
+def test_padded_box_side_does_not_change_the_potential():
+    """Any padded side M >= 2N is a box of Sec. 2.1 (kappa = M / N, with sigma
+    and c following it): on a grid fine enough that the grid error is at
+    rounding level (Example 1 at h = 1/16, Table 2), boxes of 2N, the next power
+    of two and 3N give the same potential to rounding, and each equals the
+    closed form to 1e-14.  N = 192 is not a power of two."""
+    half, h = 6.0, 1 / 16
+    n = int(round(2 * half / h))
+    x, y, _ = W.grid_2d(n, half)
+    rho = W.paper_gaussian_density(n, half)
+    exact = C.phi_isotropic_gaussian(x, y, math.pi, math.pi ** 2)
+    out = {}
+    for m in (2 * n, 512, 3 * n):
+        p = O.SplitParams(n=n, h=h, n_r=64, n_theta=128, pad_side=m)
+        assert p.kappa_eff == m / n
+        out[m] = O.phi(rho, p)
+        assert rel_linf(out[m], exact) <= 1e-14, m
+    assert rel_linf(out[512], out[2 * n]) <= 2e-15
+    assert rel_linf(out[3 * n], out[2 * n]) <= 2e-15
+    with pytest.raises(ValueError):
+        O.SplitParams(n=n, h=h, n_r=8, n_theta=8, pad_side=2 * n - 2).padded_side
+
+
+@pytest.mark.parametrize("half", [6.0, 12.0])
+def test_example1_on_grids_of_other_sides_reproduces_table2(golden, half):
+    """Table 2 shows the error of Example 1 depends on h alone (the same values at
+    L = 8, 16 and, in Table 3, 32): at h = 1/8 on boxes of other sides, N = 96
+    and 192 points (not powers of two), padded to 2N and to the next power of
+    two, the error reproduces the printed 1.56E-10 within 2 %."""
+    printed = [r[2] for r in golden("table2_gaussian_nufft.txt") if r[0] == 8 and r[1] == 0.125][0]
+    h = 0.125
+    n = int(round(2 * half / h))
+    x, y, _ = W.grid_2d(n, half)
+    rho = W.paper_gaussian_density(n, half)
+    exact = C.phi_isotropic_gaussian(x, y, math.pi, math.pi ** 2)
+    for m in (2 * n, 1 << (2 * n - 1).bit_length()):
+        err = rel_linf(O.phi(rho, O.SplitParams(n=n, h=h, n_r=64, n_theta=128, pad_side=m)), exact)
+        assert abs(err - printed) <= 0.02 * printed, (n, m, err)
