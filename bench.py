@@ -74,7 +74,7 @@ def kernel_bytes(info: dict, real_bytes: int) -> dict:
     read and write at least (inputs once, outputs once), from the plan's sizes."""
     n, q, m, w = info["n"], info["patch"], info["n_nodes"], info["kernel_width"]
     sr, sc = real_bytes, 2 * real_bytes
-    spec = (n + 1) * n * sc            # I1 half spectrum, N+1 columns of N values
+    spec = (info["n_fine"] // 2 + 1) * n * sc   # I1 half spectrum, F/2+1 columns of N values
     tiles = info["n_sub"] * info["tile"] ** 2 * sc
     return {
         "rows_forward": n * n * sr + spec + q * n * sc,
@@ -94,7 +94,7 @@ def kernel_flops(info: dict) -> dict:
     transform, not of the pruned code, which does less)."""
     n, q, f = info["n"], info["patch"], info["n_fine"]
     fft = 5 * f * math.log2(f)
-    return {"rows_forward": n * fft, "cols_highfreq": 2 * (n + 1) * fft, "rows_inverse": n * fft,
+    return {"rows_forward": n * fft, "cols_highfreq": 2 * (f // 2 + 1) * fft, "rows_inverse": n * fft,
             "cols_type2": q * fft, "cols_type1": q * fft}
 
 

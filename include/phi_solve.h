@@ -82,13 +82,17 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
  * box with spacing, the padding factor kappa, the partition width sigma and
  * disk radius c, the polar node counts and the NUFFT accuracy. */
 typedef struct {
-    int32_t nx, ny;        /* grid points per side; must be equal, a power of two, 8..4096      */
+    int32_t nx, ny;        /* grid points per side; must be equal, even and >= 8 (Sec. 3); the
+                              padded side F below must not exceed 8192                         */
     double hx, hy;         /* spacings; must be equal and > 0; box side = n h, centred at 0     */
     int32_t n_r;           /* radial Gauss-Legendre nodes, 1..1024                              */
     int32_t n_theta;       /* azimuthal trapezoid nodes, even, 2..4096                          */
     double tol;            /* NUFFT relative accuracy: F64 [1e-15, 1e-1], F32 [1e-7, 1e-1]      */
-    int32_t pad;           /* zero-padding factor kappa of the I1 box; only 2 is supported      */
-    double sigma;          /* partition width (<= 0: sqrt(ln 1e16) / (2 pi (kappa-1) L))       */
+    int32_t pad;           /* zero-padding factor kappa of the I1 box, 2..8 (0: 2).  The padded
+                              box (Sec. 2.1, kappa >= 2) has the side F = the smallest power of
+                              two >= kappa N; F is also the NUFFT fine grid (oversampling F/N)  */
+    double sigma;          /* partition width (<= 0: sqrt(ln 1e16) / (2 pi (F/N - 1) L), the
+                              reading of Sec. 2.1 with the padding factor F/N of the box used) */
     double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
     phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
     uint32_t flags;        /* PHI_COMPONENT_Y or PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI
@@ -100,7 +104,7 @@ typedef struct {
 /* Derived quantities of a plan (filled by phi_describe / phi_plan_get_info). */
 typedef struct {
     int32_t n;             /* grid side N                                        */
-    int32_t n_fine;        /* FFT / fine-grid side 2N                            */
+    int32_t n_fine;        /* FFT / fine-grid side F: smallest power of two >= kappa N */
     int32_t n_nodes;       /* M = n_r * n_theta                                  */
     int32_t kernel_width;  /* exponential-of-semicircle kernel width w (cells)   */
     int32_t patch;         /* side Q of the fine-grid window the nodes touch     */
@@ -131,7 +135,7 @@ phi_status phi_plan(const phi_params* p, void* stream, phi_plan_t* out);
 
 /* Batch of independent solves (Sec. 2.1 applied to each member on its own box):
  * one plan for `count` members, each with its own parameters (grid side
- * 128..2048, spacing, node counts, tolerance); all members share one dtype.
+ * with a padded side F of 256..4096, spacing, node counts, tolerance); all members share one dtype.
  * Members with equal parameters (field by field) share their device tables; every
  * member has its own workspace.  phi_solve / phi_solve_adjoint on a batch plan
  * take packed buffers: member i's N_i x N_i array starts at element offset

@@ -145,8 +145,8 @@ phi_status phi_ds_create(const phi_params* solve, const phi_ds_options* opt, voi
         return err(PHI_ERR_INVALID_ARG, "unknown scheme");
     if (opt->potential != PHI_DS_SPLIT && opt->potential != PHI_DS_PERIODIC)
         return err(PHI_ERR_INVALID_ARG, "unknown potential solver");
-    if (solve->nx < 16 || solve->nx > 4096)
-        return err(PHI_ERR_UNSUPPORTED, "the stepper takes grid sides 16 .. 4096");
+    if (solve->nx < 16 || solve->nx > 4096 || (solve->nx & (solve->nx - 1)) != 0)
+        return err(PHI_ERR_UNSUPPORTED, "the stepper takes power-of-two grid sides 16 .. 4096");
     try {
         std::unique_ptr<phi_ds_s> ds(new phi_ds_s());
         ds->potential = opt->potential;

@@ -185,7 +185,7 @@ hipError_t periodic_log(const DevPlan& P, const void* in, void* out, hipStream_t
 
 template <typename R>
 hipError_t periodic_typed(const DevPlan& P, const void* in, void* out, hipStream_t s, KernelTimer* timer) {
-    switch (P.log_fine - 1) {
+    switch (P.log_n) {
         case 4: return periodic_log<R, 4>(P, in, out, s, timer);
         case 5: return periodic_log<R, 5>(P, in, out, s, timer);
         case 6: return periodic_log<R, 6>(P, in, out, s, timer);

@@ -106,7 +106,7 @@ TableParts layout_tables(const phi::HostPlan& hp, size_t es, Layout& L) {
     TableParts t;
     const size_t n = hp.n, f = hp.n_fine, m = hp.n_nodes;
     t.deconv = L.take(n * 8);
-    t.gx = L.take(2 * (n + 1) * 8);
+    t.gx = L.take(2 * (f / 2 + 1) * 8);
     t.gy = L.take(2 * f * 8);
     t.gyr = L.take(2 * f * es);
     t.q = L.take(m * 8);
@@ -127,8 +127,8 @@ size_t column_stride(const phi::HostPlan& hp) { return static_cast<size_t>(hp.n)
 
 WorkParts layout_work(const phi::HostPlan& hp, size_t es, Layout& L) {
     WorkParts w;
-    const size_t n = hp.n, q = hp.patch, m = hp.n_nodes, cs = column_stride(hp);
-    w.xt = L.take((n + 1) * cs * 2 * es);
+    const size_t n = hp.n, f = hp.n_fine, q = hp.patch, m = hp.n_nodes, cs = column_stride(hp);
+    w.xt = L.take((f / 2 + 1) * cs * 2 * es);
     w.tt = L.take(q * cs * 2 * es);
     w.win = L.take(q * q * 2 * es);
     w.pts = L.take(m * 2 * es);
@@ -197,6 +197,7 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->n = hp.n;
     d->n_fine = hp.n_fine;
     d->log_fine = hp.log_fine;
+    d->log_n = hp.log_n;
     d->patch = hp.patch;
     d->patch_lo = hp.patch_lo;
     d->width = hp.width;
@@ -207,7 +208,7 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     // unless the high-frequency columns carry more than 1.5 times the work they
     // have in a 2048^2 FP32 solve (N F log2 F times the element size), where
     // they are the longer branch (FP64 at 2048^2, both precisions at 4096^2).
-    const double col_work = hp.n * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
+    const double col_work = (f / 2) * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
     d->highfreq_first = col_work > 1.5 * (2048.0 * 4096.0 * 12.0 * 4.0) ? 1 : 0;
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));
@@ -541,7 +542,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
                 if (hp.log_fine < phi::kBatchMinLogFine || hp.log_fine > phi::kBatchMaxLogFine) {
                     delete plan;
                     return fail(nullptr, PHI_ERR_UNSUPPORTED,
-                                "member " + std::to_string(i) + ": batched grid sides are 128 .. 2048");
+                                "member " + std::to_string(i) + ": batched members need a padded side of 256 .. 4096");
                 }
                 set_params.push_back(p);
                 plan->sets.push_back(std::move(hp));
@@ -574,7 +575,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
             const phi::HostPlan& hp = plan->sets[plan->member_set[i]];
             const int g = phi::batch_lines(hp.log_fine);
             push_items(&rows, i, 0, hp.n, g);
-            push_items(hp.component == 2 ? &cols_mixed : &cols, i, 0, hp.n + 1, g);
+            push_items(hp.component == 2 ? &cols_mixed : &cols, i, 0, hp.n_fine / 2 + 1, g);
             push_items(&cols, i, 1, hp.patch, g);
             push_items(&nodes, i, 0, hp.n_sub, 1);
             push_items(&cols1, i, 0, hp.patch, g);
@@ -785,8 +786,8 @@ phi_status phi_nodes_type1(phi_plan_t plan, const void* coef, void* field, void*
 phi_status phi_solve_periodic(phi_plan_t plan, const void* rho, void* phi_out, void* stream) {
     phi_status st = check_plan(plan);
     if (st != PHI_OK) return st;
-    if (plan->n_members == 0 && plan->host.n < 16)
-        return fail(plan, PHI_ERR_UNSUPPORTED, "the periodic solver takes grid sides 16 .. 4096");
+    if (plan->n_members == 0 && (plan->host.log_n < 4 || plan->host.log_n > 12))
+        return fail(plan, PHI_ERR_UNSUPPORTED, "the periodic solver takes power-of-two grid sides 16 .. 4096");
     return run(plan, phi::Stage::Periodic, rho, phi_out, 0, stream);
 }
 

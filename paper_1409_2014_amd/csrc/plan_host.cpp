@@ -246,17 +246,22 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     if (p->hx != p->hy) { *err = "hx != hy: only equal spacings are implemented"; return PHI_ERR_UNSUPPORTED; }
     const int n = p->nx;
     if (n < 2 || n % 2 != 0) { *err = fmt("grid side must be even and >= 2 (got %g)", n); return PHI_ERR_INVALID_ARG; }
-    if (!is_pow2(n) || n < (1 << (kMinLogFine - 1)) || n > (1 << (kMaxLogFine - 1))) {
-        *err = fmt("grid side %g: only powers of two from 8 to 4096 are implemented", n);
-        return PHI_ERR_UNSUPPORTED;
-    }
+    if (n < kMinGrid) { *err = fmt("grid side %g: grids from 8 points per side are implemented", n); return PHI_ERR_UNSUPPORTED; }
     if (p->n_r < 1 || p->n_r > 1024) { *err = "n_r must be in [1, 1024]"; return PHI_ERR_INVALID_ARG; }
     if (p->n_theta < 2 || p->n_theta > 4096 || p->n_theta % 2 != 0) {
         *err = "n_theta must be even and in [2, 4096]"; return PHI_ERR_INVALID_ARG;
     }
-    if (p->pad != 2 && p->pad != 0) {
-        if (p->pad < 2) { *err = "padding factor kappa must be >= 2"; return PHI_ERR_INVALID_ARG; }
-        *err = "only the padding factor kappa = 2 is implemented"; return PHI_ERR_UNSUPPORTED;
+    const int kappa = (p->pad == 0) ? 2 : p->pad;
+    if (kappa < 2) { *err = "padding factor kappa must be >= 2"; return PHI_ERR_INVALID_ARG; }
+    if (kappa > kMaxPad) { *err = fmt("padding factor kappa %g: at most %g is implemented", kappa, kMaxPad); return PHI_ERR_UNSUPPORTED; }
+    // the padded box (Sec. 2.1) is the smallest power-of-two side >= kappa N:
+    // a box of factor F / N >= kappa, on which both FFT directions are radix-16 /
+    // radix-2^r register transforms
+    long long fine = 1LL << kMinLogFine;
+    while (fine < static_cast<long long>(kappa) * n) fine *= 2;
+    if (fine > (1LL << kMaxLogFine)) {
+        *err = fmt("grid side %g with kappa %g needs a padded side above 8192", n, kappa);
+        return PHI_ERR_UNSUPPORTED;
     }
     if (p->dtype != PHI_F64 && p->dtype != PHI_F32) { *err = "unknown dtype"; return PHI_ERR_INVALID_ARG; }
     if (!(p->tol > 0.0) || !std::isfinite(p->tol)) { *err = "tol must be positive"; return PHI_ERR_INVALID_ARG; }
@@ -280,8 +285,10 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     }
 
     hp->n = n;
-    hp->n_fine = 2 * n;
-    hp->log_fine = ilog2(2 * n);
+    hp->n_fine = static_cast<int>(fine);
+    hp->log_fine = ilog2(hp->n_fine);
+    hp->log_n = is_pow2(n) ? ilog2(n) : -1;
+    hp->kappa = kappa;
     hp->n_r = p->n_r;
     hp->n_theta = p->n_theta;
     hp->n_nodes = p->n_r * p->n_theta;
@@ -291,9 +298,11 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->dtype = p->dtype;
     hp->h = p->hx;
     hp->half_width = 0.5 * n * p->hx;
-    const int kappa = 2;
+    // the padding factor of the box actually used, F / N, sets the default sigma:
+    // (kappa - 1) L = (F - N) h / 2
+    const double kappa_eff = static_cast<double>(hp->n_fine) / n;
     hp->sigma = (p->sigma > 0.0) ? p->sigma
-                                 : std::sqrt(kLogInvEpsSplit) / (2.0 * kPi * (kappa - 1) * hp->half_width);
+                                 : std::sqrt(kLogInvEpsSplit) / (2.0 * kPi * (kappa_eff - 1.0) * hp->half_width);
     hp->cutoff = (p->cutoff > 0.0) ? p->cutoff : std::sqrt(kLogInvEpsSplit) * hp->sigma;
     if (!std::isfinite(hp->sigma) || !std::isfinite(hp->cutoff)) { *err = "sigma / cutoff not finite"; return PHI_ERR_INVALID_ARG; }
 
@@ -507,8 +516,8 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
 
     // ---- I1 multiplier tables --------------------------------------------------
     const double s2 = hp->sigma * hp->sigma;
-    hp->gx.resize(2 * (n + 1));
-    for (int m1 = 0; m1 <= n; ++m1) {
+    hp->gx.resize(2 * (nf / 2 + 1));
+    for (int m1 = 0; m1 <= nf / 2; ++m1) {
         const double k = m1 / (nf * hp->h);
         const double a = k * k / s2;
         hp->gx[2 * m1] = a;
@@ -527,7 +536,7 @@ phi_status build_host_plan(const phi_params* p, HostPlan* hp, std::string* err) 
     const int lg = hp->log_fine;
     fft_stage_twiddles(lg, &hp->twr);
     hp->twn.clear();
-    if (lg - 1 >= kMinLogFine) fft_stage_twiddles(lg - 1, &hp->twn);
+    if (hp->log_n >= kMinLogFine) fft_stage_twiddles(hp->log_n, &hp->twn);
     return PHI_OK;
 }
 

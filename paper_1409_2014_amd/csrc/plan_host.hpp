@@ -13,8 +13,10 @@
 
 namespace phi {
 
-constexpr int kMaxLogFine = 13;        // fine grid up to 8192 (N up to 4096)
-constexpr int kMinLogFine = 4;         // fine grid from 16 (N from 8)
+constexpr int kMaxLogFine = 13;        // padded / fine grid up to 8192 (N up to 4096 at kappa = 2)
+constexpr int kMinLogFine = 4;         // padded / fine grid from 16
+constexpr int kMinGrid = 8;            // smallest grid side
+constexpr int kMaxPad = 8;             // largest padding factor kappa
 constexpr int kMaxKernelWidth = 28;   // widest kernel: ES up to 16, the Gaussian up to 28
 constexpr int kMaxEsWidth = 16;       // widest ES kernel (node blocks for it need less LDS)
 constexpr int kMaxTile = 31;          // largest spread tile side bin + w - 1
@@ -24,9 +26,12 @@ constexpr int kMaxNodesPerSub = 64;    // most nodes per interp / spread subprob
 
 struct HostPlan {
     // problem
-    int n = 0;            // grid side N
-    int n_fine = 0;       // FFT side 2N (kappa = 2, NUFFT oversampling 2)
+    int n = 0;            // grid side N (even)
+    int n_fine = 0;       // FFT side F: the smallest power of two >= kappa N (padded I1 box
+                          // and NUFFT fine grid, oversampling F / N >= 2)
     int log_fine = 0;
+    int log_n = -1;       // log2 N when N is a power of two (the periodic solver), else -1
+    int kappa = 2;        // requested padding factor
     int n_r = 0, n_theta = 0, n_nodes = 0;
     int component = 0;          // multiplier -k_a k_b/|k|^2: 0 (a,b) = (x,x), 1 (y,y), 2 (x,y)
     int radial_jacobi = 0;      // Gauss-Jacobi(0, 1) radial rule instead of Gauss-Legendre
@@ -56,10 +61,10 @@ struct HostPlan {
     int max_gather = 0;                 // most tile entries summed into one window cell
     // tables
     std::vector<double> deconv;         // [N] 2 pi / (n_fine psi_hat(n')), n' = i - N/2
-    std::vector<double> gx;             // [2 (N+1)] (a, 1 - e^{-a}),  a = kx^2 / sigma^2, kx = m/(n_fine h)
+    std::vector<double> gx;             // [2 (F/2+1)] (a, 1 - e^{-a}),  a = kx^2 / sigma^2, kx = m/(n_fine h)
     std::vector<double> gy;             // [2 n_fine] (b, 1 - e^{-b}), signed frequency
     std::vector<double> twr;            // (re, im) per-stage twiddles of the register FFT of length n_fine
-    std::vector<double> twn;            // the same for length n (the periodic solver, n >= 16)
+    std::vector<double> twn;            // the same for length N (the periodic solver; N a power of two >= 16)
 };
 
 phi_status fill_defaults(phi_params* p, int32_t n, double h, phi_dtype dtype);

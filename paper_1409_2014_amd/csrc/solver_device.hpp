@@ -39,49 +39,61 @@ constexpr int rows_per_block() {
     constexpr int n = (1 << LOG) / 2;
     int lim = by_threads < by_lds ? by_threads : by_lds;
     lim = lim < n ? lim : n;
-    int g = 1;                      // largest power of two <= lim: divides N
-    while (2 * g <= lim) g *= 2;
+    int g = 1;                      // largest power of two <= lim (the last block of a
+    while (2 * g <= lim) g *= 2;    // grid whose side it does not divide is partly idle)
     return g;
 }
 
-// Grid column of register slot i of thread tid (centred positions: slots 0..3
-// hold n' >= 0, slots 12..15 hold n' < 0, the other slots are zero padding).
-template <int LOG>
-__device__ __forceinline__ int slot_col(int tid, int i) {
-    constexpr int NT = FftShape<LOG>::NT;
-    constexpr int N = (1 << LOG) / 2;
-    return (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
-}
+// A grid line of n points (n even, F >= 2n) sits at the centred positions
+// n' mod F of an F-point transform, n' = index - n/2: n' >= 0 at positions
+// [0, n/2), n' < 0 at [F - n/2, F).  In the register layout (position
+// p = tid + NT i) those are slots 0..3 and 12..15 (n/2 <= F/4), so slots 4..11
+// are zero padding at compile time; the grid index of position p is
+// p + n/2 (slots 0..3, p < n/2) or p - F + n/2 (slots 12..15, p >= F - n/2).
+// The kernels address a line through one base pointer at index n/2 with the
+// offsets p or p - F, so every load and store of a thread shares one address
+// register.
 
 // Rows of the grid, G per block, at centred positions n' mod F:
 // z = rho + i rho d(n1) d(n2) (the type-2 deconvolution rides in the imaginary
-// part), one F-point FFT; the transform of the real part on m = 0..N is the I1
-// half spectrum, that of the imaginary part on the Q window frequencies is the
-// type-2 row window.
+// part), one F-point FFT; the transform of the real part on m = 0..F/2 (I1
+// half spectrum) goes to the column-major XT, that of the imaginary part on
+// the Q window frequencies (the type-2 row window) to TT.  Rows at or beyond
+// N (the last block of a grid whose side G does not divide) transform zeros
+// and store nothing.
 template <typename R, int LOG, int DIR, int G>
 __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __restrict__ rho, int row0,
                                                   cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
-    constexpr int N = F / 2;
+    constexpr int HALF = F / 2;
     constexpr int NT = Sh::NT;
-    static_assert(N % G == 0, "the rows of a block must tile the grid");
     constexpr int LP = lds_group_stride(F);
+    const int n = P.n;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const double dy = P.deconv[row0 + g];
-    const R* src = rho + static_cast<size_t>(row0 + g) * N;
+    const bool row_ok = row0 + g < n;
+    const int row = row_ok ? row0 + g : n - 1;
+    const double dy = P.deconv[row];
+    // grid column n1 = position + N/2 (n' >= 0) or position - F + N/2 (n' < 0):
+    // one base address per array serves every slot
+    const int half = n >> 1;
+    const R* src = rho + static_cast<size_t>(row) * n + half;
+    const double* dx = P.deconv + half;
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
+        const int p = tid + NT * i;
+        v[i] = {R(0), R(0)};
         if (i < 4 || i >= 12) {
-            const int n1 = slot_col<LOG>(tid, i);
-            const R r = src[n1];
-            v[i] = {r, static_cast<R>(static_cast<double>(r) * P.deconv[n1] * dy)};
-        } else {
-            v[i] = {R(0), R(0)};
+            const int o = (i < 4) ? p : p - F;
+            const bool inside = (i < 4) ? (p < half) : (p >= F - half);
+            if (row_ok && inside) {
+                const R r = src[o];
+                v[i] = {r, static_cast<R>(static_cast<double>(r) * dx[o] * dy)};
+            }
         }
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
@@ -92,7 +104,7 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
     // outputs of the G rows, row index fastest: G-element runs of each column;
     // a compile-time number of passes with clamped indices
     cpx<R>* xt = static_cast<cpx<R>*>(P.xt);
-    constexpr int ITEMS = (N + 1) * G;
+    constexpr int ITEMS = (HALF + 1) * G;
     constexpr int PASSES = (ITEMS + NT * G - 1) / (NT * G);
 #pragma unroll
     for (int k = 0; k < PASSES; ++k) {
@@ -104,7 +116,8 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
         const cpx<R> a = l[lds_pad(m)];
         const cpx<R> b = l[lds_pad((F - m) & (F - 1))];
         // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2
-        if (idx < ITEMS) xt[static_cast<size_t>(m) * P.col_stride + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
+        if (idx < ITEMS && row0 + gg < n)
+            xt[static_cast<size_t>(m) * P.col_stride + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
     }
     cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
     for (int idx = threadIdx.x; idx < P.patch * G; idx += NT * G) {
@@ -115,7 +128,8 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
         const cpx<R> a = l[lds_pad(lf & (F - 1))];
         const cpx<R> b = l[lds_pad((-lf) & (F - 1))];
         // transform of the imaginary part: (Z[l] - conj Z[-l]) / (2i)
-        tt[static_cast<size_t>(i) * P.col_stride + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
+        if (row0 + gg < n)
+            tt[static_cast<size_t>(i) * P.col_stride + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
     }
 }
 
@@ -155,30 +169,40 @@ __device__ __forceinline__ constexpr R tiny_normal() {
 
 // Column m1 of the half spectrum (contiguous in XT, N values at centred y
 // positions) is transformed along y with the zero padding implicit: in the
-// register layout position tid + NT i holds a grid row only for i < 4
-// (p < N/2) and i >= 12 (p >= F - N/2), so the other inputs are compile-time
-// zeros and the inverse transform's outputs there are never formed.
+// register layout only slots 0..3 and 12..15 can hold grid rows (see above),
+// so the other inputs are compile-time zeros and the inverse transform's
+// outputs there are never formed.
 // MIXED: the multiplier -kx ky/|k|^2 (a separate instantiation, so that the DS
 // multiplier's code is unchanged by it).
 template <typename R, int LOG, int DIR, int G, bool MIXED>
 __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
-    constexpr int N = F / 2;
+    constexpr int HALF = F / 2;
     constexpr int NT = Sh::NT;
+    const int n = P.n;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * lds_group_stride(F);
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const int m1 = m1_base + g;   // 0..N (+ idle lanes of the last block)
-    const bool active = m1 <= N;
-    // idle lanes load column N and never store: no branch around the loads
-    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : N) * P.col_stride;
+    const int m1 = m1_base + g;   // 0..F/2 (+ idle lanes of the last block)
+    const bool active = m1 <= HALF;
+    // idle lanes load column F/2 and never store: no branch around the loads
+    cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : HALF) * P.col_stride;
+    // rows n' >= 0 at positions [0, N/2), n' < 0 at [F - N/2, F): one base
+    // address (row N/2 - position 0) serves every slot
+    const int half = n >> 1;
+    const cpx<R>* base = col + half;
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        if (i < 4 || i >= 12) v[i] = col[slot_col<LOG>(tid, i)];
-        else v[i] = {R(0), R(0)};
+        const int p = tid + NT * i;
+        v[i] = {R(0), R(0)};
+        if (i < 4) {
+            if (p < half) v[i] = base[p];
+        } else if (i >= 12) {
+            if (p >= F - half) v[i] = base[p - F];
+        }
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     // (b, 1 - e^{-b}) of the 16 rows this thread multiplies, fetched only now:
@@ -196,22 +220,22 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
     // The mixed numerator is odd in each frequency, and a bin on a Nyquist line
     // (|index| = F/2) stands for +k and -k: it takes the mean of the multiplier
     // over them, 0 (also at the corner).
-    const int mc = active ? m1 : N;
+    const int mc = active ? m1 : HALF;
     const R a = static_cast<R>(P.gx[2 * mc]);
     const R A = static_cast<R>(P.gx[2 * mc + 1]);
     const R scale = static_cast<R>(P.inv_f2);
     const bool ycomp = P.component == 1;
     const R fs = static_cast<R>(P.freq_scale);
-    const R fx = (mc == N) ? R(0) : static_cast<R>(mc) * fs;
+    const R fx = (mc == HALF) ? R(0) : static_cast<R>(mc) * fs;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const R b = gb[i].x;
         const R B = gb[i].y;
         R num;
         if constexpr (MIXED) {
-            const int p = tid + NT * i;           // frequency index along y, FFT order
-            const int ms = (p < N) ? p : p - F;   // p = N (Nyquist) -> -N
-            num = (p == N) ? R(0) : fx * (static_cast<R>(ms) * fs);
+            const int p = tid + NT * i;                 // frequency index along y, FFT order
+            const int ms = (p < HALF) ? p : p - F;      // p = F/2 (Nyquist) -> -F/2
+            num = (p == HALF) ? R(0) : fx * (static_cast<R>(ms) * fs);
         } else {
             num = ycomp ? b : a;
         }
@@ -222,9 +246,16 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
     }
     fft_reg<R, LOG, -DIR>(v, lds, tw, tid);
     if (active) {
+        cpx<R>* out = col + half;
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < 4 || i >= 12) col[slot_col<LOG>(tid, i)] = v[i];
+        for (int i = 0; i < 16; ++i) {
+            const int p = tid + NT * i;
+            if (i < 4) {
+                if (p < half) out[p] = v[i];
+            } else if (i >= 12) {
+                if (p >= F - half) out[p - F] = v[i];
+            }
+        }
     }
 }
 
@@ -235,7 +266,6 @@ template <typename R, int LOG, int DIR, int G>
 __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
-    constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
@@ -246,15 +276,17 @@ __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, c
     const bool active = i1 < q;
     const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(active ? i1 : 0) * P.col_stride;
     const cpx<R> zero = {R(0), R(0)};
+    const int half = P.n >> 1;
+    const cpx<R>* base = col + half;
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
+        const int p = tid + NT * i;
+        v[i] = zero;
         if (i < 4) {
-            v[i] = active ? col[tid + NT * i + N / 2] : zero;
+            if (active && p < half) v[i] = base[p];
         } else if (i >= 12) {
-            v[i] = active ? col[tid + NT * (i - 12)] : zero;
-        } else {
-            v[i] = zero;
+            if (active && p >= F - half) v[i] = base[p - F];
         }
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
@@ -500,7 +532,6 @@ template <typename R, int LOG, int DIR, int G, int COLS>
 __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
-    constexpr int N = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int BT = NT * G;
     constexpr int L = 4;
@@ -561,13 +592,19 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     if (active && g < COLS) {
-        cpx<R>* u = static_cast<cpx<R>*>(P.u);
+        const int half = P.n >> 1;
+        cpx<R>* u = static_cast<cpx<R>*>(P.u) + static_cast<size_t>(half) * q + i1;
+        const double* dy = P.deconv + half;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
+            const int p = tid + NT * i;
             if (i < 4 || i >= 12) {
-                const int n2 = (i < 4) ? tid + NT * i + N / 2 : tid + NT * (i - 12);
-                const double d = P.deconv[n2];
-                u[static_cast<size_t>(n2) * q + i1] = {static_cast<R>(v[i].x * d), static_cast<R>(v[i].y * d)};
+                const int o = (i < 4) ? p : p - F;     // grid row n2 = o + N/2
+                const bool inside = (i < 4) ? (p < half) : (p >= F - half);
+                if (inside) {
+                    const double d = dy[o];
+                    u[static_cast<ptrdiff_t>(o) * q] = {static_cast<R>(v[i].x * d), static_cast<R>(v[i].y * d)};
+                }
             }
         }
     }
@@ -581,16 +618,18 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
 // LDS: the Hermitian extension of the I1 half spectrum (column m of XT, conj at
 // F - m) plus i times the Hermitian part H[l] = (U[l] + conj U[-l]) / 2 of the
 // type-1 row on the window frequencies.  One inverse FFT then gives I1 in the
-// real part and Re(type-1 field) / d(n1) in the imaginary part.
+// real part and Re(type-1 field) / d(n1) in the imaginary part.  Rows at or
+// beyond N (the last block of a grid whose side G does not divide) transform
+// zeros and store nothing.
 template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2, int G>
 __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restrict__ out, int row0,
                                                   cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
-    constexpr int N = F / 2;
+    constexpr int HALF = F / 2;
     constexpr int NT = Sh::NT;
-    static_assert(N % G == 0, "the rows of a block must tile the grid");
     constexpr int LP = lds_group_stride(F);
+    const int n = P.n;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * LP;
@@ -598,9 +637,10 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
     const cpx<R>* xt = static_cast<const cpx<R>*>(P.xt);
     const cpx<R>* u = static_cast<const cpx<R>*>(P.u);
     const int q = P.patch, lo = P.patch_lo;
-    // (N+1) G entries (column m, row gg), row index fastest; every load is issued
-    // unconditionally (clamped index) so that all of them are in flight at once
-    constexpr int ITEMS = (N + 1) * G;
+    // (F/2+1) G entries (column m, row gg), row index fastest; every load is
+    // issued unconditionally (clamped index) so that all of them are in flight
+    // at once
+    constexpr int ITEMS = (HALF + 1) * G;
     constexpr int PASSES = (ITEMS + NT * G - 1) / (NT * G);
 #pragma unroll
     for (int k = 0; k < PASSES; ++k) {
@@ -608,7 +648,7 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
         const int idc = idx < ITEMS ? idx : ITEMS - 1;
         const int gg = idc % G;
         const int m = idc / G;
-        const int r = row0 + gg;
+        const int r = row0 + gg < n ? row0 + gg : n - 1;   // rows past N read row N - 1, never stored
         cpx<R> x = {R(0), R(0)};
         if constexpr (USE_I1) x = xt[static_cast<size_t>(m) * P.col_stride + r];
         cpx<R> hh = {R(0), R(0)};
@@ -629,19 +669,25 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
         // duplicate of the last entry rewrites the same values)
         cpx<R>* l = lds_all + gg * LP;
         l[lds_pad(m)] = {x.x - hh.y, x.y + hh.x};
-        if (m > 0 && m < N) l[lds_pad(F - m)] = {x.x + hh.y, -x.y + hh.x};
+        if (m > 0 && m < HALF) l[lds_pad(F - m)] = {x.x + hh.y, -x.y + hh.x};
     }
     __syncthreads();
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    R* dst = out + static_cast<size_t>(row0 + g) * N;
+    if (row0 + g < n) {
+        const int half = n >> 1;
+        R* dst = out + static_cast<size_t>(row0 + g) * n + half;
+        const double* dx = P.deconv + half;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (i < 4 || i >= 12) {
-            const int n1 = slot_col<LOG>(tid, i);
-            dst[n1] = static_cast<R>(static_cast<double>(v[i].x) + static_cast<double>(v[i].y) * P.deconv[n1]);
+        for (int i = 0; i < 16; ++i) {
+            const int p = tid + NT * i;
+            if (i < 4 || i >= 12) {
+                const int o = (i < 4) ? p : p - F;
+                const bool inside = (i < 4) ? (p < half) : (p >= F - half);
+                if (inside) dst[o] = static_cast<R>(static_cast<double>(v[i].x) + static_cast<double>(v[i].y) * dx[o]);
+            }
         }
     }
 }

@@ -1,14 +1,15 @@
 // HIP kernels of the split potential solve for gfx950 (see phi_solve.h).
 //
-// N = grid side, F = 2N the side of both the zero-padded I1 box and the NUFFT
-// fine grid, Q = side of the fine-grid window around frequency 0 that the
-// polar nodes' kernel taps touch, M = number of polar nodes, w = kernel width.
+// N = grid side (even), F = the side of both the zero-padded I1 box and the
+// NUFFT fine grid (the smallest power of two >= kappa N, so F >= 2N), Q = side
+// of the fine-grid window around frequency 0 that the polar nodes' kernel taps
+// touch, M = number of polar nodes, w = kernel width.
 // A solve runs six kernels; the node-side chain runs on a second stream
 // concurrently with the I1 column pass:
 //
 //   rows_forward   per grid row: z = rho + i rho d(n1) d(n2) at centred
 //                  positions, one F-point FFT; the transform of the real part
-//                  on m = 0..N (I1 half spectrum) goes to the column-major XT,
+//                  on m = 0..F/2 (I1 half spectrum) goes to the column-major XT,
 //                  that of the imaginary part on the Q window frequencies (the
 //                  type-2 row window) to TT.   [Sec. 2.1 eq. (9); Sec. 2.2 eq. (16)]
 //   cols_highfreq  per spectrum column: F-point FFT, times g1(k)/F^2, inverse
@@ -92,7 +93,7 @@ template <typename R, int LOG, int DIR>
 hipError_t launch_rows_forward_dir(const DevPlan& P, const R* src, hipStream_t s) {
     constexpr int G = rows_per_block<R, LOG>();
     constexpr int block = FftShape<LOG>::NT * G;
-    const int items = P.n / G;
+    const int items = (P.n + G - 1) / G;
     const int grid = items;   // one work item per block
     hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR>), dim3(grid), dim3(block), 0, s, P, src);
     return hipGetLastError();
@@ -108,7 +109,7 @@ template <typename R, int LOG, int DIR>
 hipError_t launch_cols_highfreq_dir(const DevPlan& P, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
     constexpr int block = FftShape<LOG>::NT * G;
-    const int items = (P.n + 1 + G - 1) / G;
+    const int items = (P.n_fine / 2 + 1 + G - 1) / G;
     const int grid = items;   // one work item per block
     if (P.component == 2) hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P);
     else hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P);
@@ -141,7 +142,7 @@ template <typename R, int LOG, int DIR, bool I1, bool I2>
 hipError_t launch_rows_inverse_parts(const DevPlan& P, R* dst, hipStream_t s) {
     constexpr int G = rows_per_block<R, LOG>();
     constexpr int block = FftShape<LOG>::NT * G;
-    const int items = P.n / G;
+    const int items = (P.n + G - 1) / G;
     const int grid = items;   // one work item per block
     hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2>), dim3(grid), dim3(block), 0, s, P, dst);
     return hipGetLastError();

@@ -13,6 +13,7 @@ namespace phi {
 struct DevPlan {
     phi_dtype dtype;
     int n, n_fine, log_fine;
+    int log_n;              // log2 N when N is a power of two (the periodic solver), else -1
     int patch, patch_lo, width, n_nodes;
     int component;          // 0: -kx^2/|k|^2, 1: -ky^2/|k|^2, 2: -kx ky/|k|^2
     int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
@@ -21,7 +22,7 @@ struct DevPlan {
     double h2, inv_f2;
     // FP64 tables
     const double* deconv;   // [N] 2 pi / (n_fine psi_hat(n'))
-    const double* gx;       // [2 (N+1)] I1 multiplier factors along x
+    const double* gx;       // [2 (F/2+1)] I1 multiplier factors along x
     const double* gy;       // [2 F] I1 multiplier factors along y
     const void* gyr;        // [F] (b, 1 - e^{-b}) pairs of gy in the data precision
     const double* q;        // [M] I2 weights q_j (without h^2)
@@ -37,7 +38,7 @@ struct DevPlan {
     const void* twn;        // the same for length N (periodic solver), twn_count complex
     int twn_count;
     // workspace, element type = data precision
-    void* xt;       // (N+1) columns of N complex: I1 half spectrum, column-major, col_stride apart
+    void* xt;       // (F/2+1) columns of N complex: I1 half spectrum, column-major, col_stride apart
     void* tt;       // Q columns of N complex: type-2 row window, column-major, col_stride apart
     void* win;      // Q x Q complex: type-2 fine-grid window, [y][x]
     void* pts;      // M complex: a_j = q_j rho_hat_j

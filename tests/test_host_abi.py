@@ -134,11 +134,14 @@ def test_describe_small_grid_uses_whole_fine_grid(lib):
 @pytest.mark.parametrize("kwargs,status", [
     (dict(n=64, h=0.25, n_theta=63), 1),            # odd azimuthal count
     (dict(n=64, h=-1.0), 1),                        # negative spacing
-    (dict(n=60, h=0.25), 2),                        # not a power of two
-    (dict(n=8192, h=0.25), 2),                      # too large
+    (dict(n=61, h=0.25), 1),                        # odd grid side
+    (dict(n=6, h=0.25), 2),                         # below 8 points per side
+    (dict(n=8192, h=0.25), 2),                      # padded side above 8192
+    (dict(n=4098, h=0.25), 2),
+    (dict(n=2800, h=0.25, pad=3), 2),
     (dict(n=64, h=0.25, tol=1e-9, dtype="float32"), 3),
     (dict(n=64, h=0.25, tol=1e-16), 3),
-    (dict(n=64, h=0.25, pad=3), 2),
+    (dict(n=64, h=0.25, pad=9), 2),                 # kappa above 8
     (dict(n=64, h=0.25, pad=1), 1),
     (dict(n=64, h=0.25, bin=5), 1),                 # bin side not in {4, 8, 16}
     (dict(n=64, h=0.25, sub_nodes=65), 1),          # more nodes per block than the LDS holds
@@ -282,3 +285,20 @@ def test_plan_nodes_with_the_jacobi_rule_equal_the_oracle(lib):
     a = a[np.lexsort((np.round(a[:, 1], 10), np.round(a[:, 0], 10)))]
     b = b[np.lexsort((np.round(b[:, 1], 10), np.round(b[:, 0], 10)))]
     assert np.max(np.abs(a - b)) < 1e-15
+
+
+@pytest.mark.parametrize("n,pad,fine", [(96, 2, 256), (384, 2, 1024), (1536, 2, 4096), (3072, 2, 8192),
+                                        (10, 2, 32), (100, 3, 512), (2048, 3, 8192), (1024, 4, 4096),
+                                        (64, 2, 128), (2730, 3, 8192)])
+def test_padded_side_is_the_smallest_power_of_two_at_least_kappa_n(lib, n, pad, fine):
+    """Any even grid side: the padded box of I1 (and the NUFFT fine grid) is the
+    smallest power of two >= kappa N, and the default sigma follows the padding
+    factor F / N of that box (Sec. 2.1 with kappa = F / N), as in the oracle."""
+    import oracle as O
+    import paper_1409_2014_amd.solver as S
+    h = 1 / 32
+    d = S.describe(n=n, h=h, pad=pad)
+    assert d["n_fine"] == fine
+    sigma, c = O.split_constants(O.SplitParams(n=n, h=h, n_r=8, n_theta=8, pad_side=fine))
+    assert abs(d["sigma"] - sigma) <= 1e-14 * sigma
+    assert abs(d["cutoff"] - c) <= 1e-14 * c

@@ -24,8 +24,8 @@ def test_solve_bytes_match_the_stated_totals():
 
 
 def test_kernel_bytes_sum_to_the_fft_passes():
-    info = {"n": 2048, "patch": 64, "n_nodes": 8192, "kernel_width": 8, "n_sub": 182, "tile": 11,
-            "n_contrib": 19507}
+    info = {"n": 2048, "n_fine": 4096, "patch": 64, "n_nodes": 8192, "kernel_width": 8, "n_sub": 182,
+            "tile": 11, "n_contrib": 19507}
     kb = bench.kernel_bytes(info, 4)
     spec = 2049 * 2048 * 8
     assert kb["cols_highfreq"] == 2 * spec
