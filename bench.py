@@ -76,7 +76,7 @@ def kernel_bytes(info: dict, real_bytes: int) -> dict:
     sr, sc = real_bytes, 2 * real_bytes
     spec = (info["n_fine"] // 2 + 1) * n * sc   # I1 half spectrum, F/2+1 columns of N values
     tiles = info["n_sub"] * info["tile"] ** 2 * sc
-    return {
+    out = {
         "rows_forward": n * n * sr + spec + q * n * sc,
         "cols_highfreq": 2 * spec,
         "cols_type2": q * n * sc + q * q * sc,
@@ -86,6 +86,9 @@ def kernel_bytes(info: dict, real_bytes: int) -> dict:
         "cols_type1": tiles + info["n_contrib"] * 4 + (q * q + 1) * 4 + n * q * sc,
         "rows_inverse": spec + n * q * sc + n * n * sr,
     }
+    # the fused launch holds the I1 columns and the node-side chain
+    out["middle"] = out["cols_highfreq"] + out["cols_type2"] + out["nodes"] + out["cols_type1"]
+    return out
 
 
 def kernel_flops(info: dict) -> dict:
@@ -94,8 +97,10 @@ def kernel_flops(info: dict) -> dict:
     transform, not of the pruned code, which does less)."""
     n, q, f = info["n"], info["patch"], info["n_fine"]
     fft = 5 * f * math.log2(f)
-    return {"rows_forward": n * fft, "cols_highfreq": 2 * (f // 2 + 1) * fft, "rows_inverse": n * fft,
-            "cols_type2": q * fft, "cols_type1": q * fft}
+    out = {"rows_forward": n * fft, "cols_highfreq": 2 * (f // 2 + 1) * fft, "rows_inverse": n * fft,
+           "cols_type2": q * fft, "cols_type1": q * fft}
+    out["middle"] = out["cols_highfreq"] + out["cols_type2"] + out["cols_type1"]
+    return out
 
 
 def solve_alg_bytes(n: int, real_bytes: int) -> int:
@@ -497,6 +502,9 @@ def main() -> int:
 
     plan32 = ps.Plan(N, h, dtype=torch.float32, n_r=N_R, n_theta=N_THETA, tol=TOL32)
     plan64 = ps.Plan(N, h, dtype=torch.float64, n_r=N_R, n_theta=N_THETA, tol=TOL64)
+    # the same solve with the node-side chain as separate launches on a second
+    # stream (bit-identical results): its per-kernel times split the work by stage
+    plan32s = ps.Plan(N, h, dtype=torch.float32, n_r=N_R, n_theta=N_THETA, tol=TOL32, two_streams=True)
     out32 = torch.empty_like(rho32_dev)
     out64 = torch.empty_like(rho64_dev)
     back32 = torch.empty_like(rho32_dev)
@@ -516,6 +524,9 @@ def main() -> int:
         plan64.solve(rho64_dev, out64)
         plan64.solve_adjoint(out64, back64)
 
+    def fwd32s():
+        plan32s.solve(rho32_dev, out32)
+
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -524,14 +535,15 @@ def main() -> int:
         del src, dst
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    for fn in (fwd32, fwd64, pair32, pair64):
+    for fn in (fwd32, fwd64, pair32, pair64, fwd32s):
         for _ in range(args.warmup):
             fn()
     torch.cuda.synchronize()
 
     if args.launch == "graph":
-        fwd32, fwd64, pair32, pair64 = (capture_graph(f, torch) for f in (fwd32, fwd64, pair32, pair64))
-        for fn in (fwd32, fwd64, pair32, pair64):
+        fwd32, fwd64, pair32, pair64, fwd32s = (capture_graph(f, torch)
+                                                for f in (fwd32, fwd64, pair32, pair64, fwd32s))
+        for fn in (fwd32, fwd64, pair32, pair64, fwd32s):
             for _ in range(args.warmup):
                 fn()
         torch.cuda.synchronize()
@@ -542,6 +554,7 @@ def main() -> int:
     t64 = timed_rate(fwd64, k, torch)
     tp32 = timed_rate(pair32, k, torch)
     tp64 = timed_rate(pair64, k, torch)
+    t32s = timed_rate(fwd32s, k, torch)
     phi32 = out32.double().cpu().numpy()
     phi64 = out64.double().cpu().numpy()
 
@@ -549,6 +562,7 @@ def main() -> int:
     print("[bench] per-kernel event timing", file=sys.stderr, flush=True)
     nbytes = kernel_bytes(plan32.info, 4)
     kernels = event_kernels(lambda: plan32.solve_timed(rho32_dev, out32), k, nbytes)
+    kernels_split = event_kernels(lambda: plan32s.solve_timed(rho32_dev, out32), k, nbytes)
     dominant = max(kernels, key=lambda name: kernels[name]["avg_us"])
     achieved = kernels[dominant]["gbs"]
     flops32 = kernel_flops(plan32.info)
@@ -583,9 +597,12 @@ def main() -> int:
         "solve_roofline_frac": {"f32": round(alg32 * k / t32 / 1e9 / HBM_PEAK_GBS, 4),
                                 "f64": round(alg64 * k / t64 / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_f32": kernels,
+        # the two-stream layout: the node-side chain as its own launches beside the I1
+        # columns (same results), graph-replayed rate and per-kernel event times
+        "two_streams_f32": {"solves_per_s": k / t32s, "kernels": kernels_split},
         # the paper's split of solve time (Sec. 3): FFT-side kernels (I1, with the type-2
         # row transform and the recombination fused in) against the node-side kernels
-        "time_split_f32": time_split(kernels),
+        "time_split_f32": time_split(kernels_split),
         "node_sort": {"bin": plan32.info["bin"], "sub_nodes": plan32.info["sub_nodes"],
                       "n_sub": plan32.info["n_sub"]},
         # the FFT kernels are bound by their vector ALU work (the counters show
@@ -604,6 +621,7 @@ def main() -> int:
     }
     plan32.close()
     plan64.close()
+    plan32s.close()
     legs = set() if args.no_extra_legs else {x.strip() for x in args.legs.split(",") if x.strip()}
     unknown = legs - {"batch", "adjoint", "stepper", "periodic", "dynamics"}
     if unknown:

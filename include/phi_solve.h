@@ -70,6 +70,14 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
                                 Gaussian's Fourier transform as deconvolution, instead of the
                                 exponential of semicircle.  Needs bin + w - 1 <= 31 (tol >= 5e-13
                                 at bin 4); other cases return PHI_ERR_UNSUPPORTED. */
+#define PHI_TWO_STREAMS 32u /* run the node-side chain as its own three launches on a second stream,
+                                concurrently with the I1 column pass, also where a plan would run
+                                it fused: on padded sides up to 512 the I1 columns and the whole
+                                chain are by default one launch whose dependent blocks wait on
+                                device counters (three launches per solve instead of five on the
+                                critical path); results are bit-identical.  Larger sides, the
+                                mixed multiplier and the Gaussian kernel above 16 cells always
+                                use the two-stream layout. */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
                                 subproblem sizes {32, 64} on the device and keep the fastest; the
                                 choice is visible in phi_plan_info.bin / .sub_nodes.  Results of
@@ -221,6 +229,14 @@ phi_status phi_solve_lowfreq(phi_plan_t plan, const void* rho, void* i2, void* s
  * calling thread. */
 phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t adjoint, void* stream,
                            float* kernel_ms, const char** names, int32_t capacity, int32_t* count);
+
+/* Synchronises the device and reports whether any wait inside the plan's fused
+ * solve launch (the I1 columns and the node-side chain, whose blocks wait on
+ * device counters) ran
+ * past its spin limit since the plan was created: PHI_OK if none did (and for
+ * batch plans), PHI_ERR_DEVICE with a message otherwise.  Such a launch still
+ * ends, but its result is not valid. */
+phi_status phi_plan_device_status(phi_plan_t plan);
 
 /* Host-only helpers used by the plan (exported for CPU tests). */
 phi_status phi_host_gauss_legendre(int32_t n, double* x, double* w);

@@ -15,6 +15,7 @@ PHI_COMPONENT_XY = 8
 PHI_AUTOTUNE = 2
 PHI_RADIAL_JACOBI = 4
 PHI_KERNEL_GAUSSIAN = 16
+PHI_TWO_STREAMS = 32
 
 STATUS_NAMES = {
     0: "PHI_OK", 1: "PHI_ERR_INVALID_ARG", 2: "PHI_ERR_UNSUPPORTED", 3: "PHI_ERR_TOL_UNREACHABLE",
@@ -97,6 +98,7 @@ def _declare(lib):
                                  ctypes.POINTER(ctypes.c_char_p), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]),
         "phi_plan_get_info": (st, [_P, ctypes.POINTER(PhiPlanInfo)]),
+        "phi_plan_device_status": (st, [_P]),
         "phi_plan_nodes": (st, [_P, _DP, _DP, _DP]),
         "phi_host_gauss_legendre": (st, [ctypes.c_int32, _DP, _DP]),
         "phi_host_gauss_jacobi01": (st, [ctypes.c_int32, _DP, _DP]),
@@ -146,7 +148,7 @@ def exported_symbols():
         "phi_batch_member_info",
         "phi_solve", "phi_solve_noalloc", "phi_solve_adjoint",
         "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1", "phi_solve_periodic",
-        "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre", "phi_host_gauss_jacobi01",
+        "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_device_status", "phi_plan_nodes", "phi_host_gauss_legendre", "phi_host_gauss_jacobi01",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",
         "phi_status_string", "phi_last_error",
         "phi_ds_create", "phi_ds_substeps", "phi_ds_destroy", "phi_ds_plan", "phi_ds_forward", "phi_ds_backward",

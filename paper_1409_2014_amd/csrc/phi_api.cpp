@@ -68,6 +68,9 @@ phi_status device_fail(phi_plan_t plan, hipError_t e, const char* where) {
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
+// largest padded side (log2) whose solves use the fused middle launch by default
+constexpr int kFusedMaxLogFine = 9;
+
 phi_status check_plan(phi_plan_t plan) {
     if (!is_live(plan)) return fail(nullptr, PHI_ERR_INVALID_ARG, "plan is NULL or was destroyed");
     return PHI_OK;
@@ -96,6 +99,10 @@ struct Layout {
 // everything a plan reads and never writes
 struct TableParts {
     Part deconv, gx, gy, gyr, q, cell, sub, cst, con, taps, twr, twn;
+};
+// counters of the fused middle launch: written by every solve, zero between solves
+struct SyncPart {
+    Part sync;
 };
 // everything a solve writes
 struct WorkParts {
@@ -190,8 +197,14 @@ void point_work(char* base, const WorkParts& w, phi::DevPlan* d) {
     d->u = base + w.u.off;
 }
 
+SyncPart layout_sync(Layout& L) {
+    SyncPart s;
+    s.sync = L.take(phi::kSyncWords * sizeof(unsigned));
+    return s;
+}
+
 void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableParts& t,
-              const WorkParts& w, phi::DevPlan* d) {
+              const WorkParts& w, const SyncPart& sp, phi::DevPlan* d) {
     const double f = hp.n_fine;
     d->dtype = dtype;
     d->n = hp.n;
@@ -210,6 +223,15 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     // they are the longer branch (FP64 at 2048^2, both precisions at 4096^2).
     const double col_work = (f / 2) * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
     d->highfreq_first = col_work > 1.5 * (2048.0 * 4096.0 * 12.0 * 4.0) ? 1 : 0;
+    // The I1 columns and the node-side chain as one launch where that measured
+    // faster: padded sides up to 512 (graph replay on MI355X, 64^2 FP32 46 ->
+    // 41.5 us, 256^2 54 -> 47.5 us); from 1024^2 on the chain's critical path
+    // inside the shared launch is longer than beside it on a second stream
+    // (1024^2 FP32 52 -> 63 us, 2048^2 104 -> 117 us).  Not for the kernel
+    // variants the fused launch leaves out, or when asked for two streams.
+    d->fused = (!hp.two_streams && hp.component != 2 && hp.width <= phi::kMaxEsWidth &&
+                hp.log_fine <= kFusedMaxLogFine) ? 1 : 0;
+    d->sync = reinterpret_cast<unsigned*>(base + sp.sync.off);
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));
     d->h2 = hp.h * hp.h;
@@ -277,6 +299,7 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
     const size_t es = f32 ? 4 : 8;
     Layout L;
     const TableParts tp = layout_tables(hp, es, L);
+    const SyncPart sp = layout_sync(L);
     const WorkParts wp = layout_work(hp, es, L);
     plan->block_bytes = L.cursor;
     e = hipMalloc(&plan->block, L.cursor);
@@ -288,6 +311,7 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
     char* base = static_cast<char*>(plan->block);
     std::vector<std::vector<float>> keep;
     e = upload_tables(hp, tp, base, f32, s, keep);
+    if (e == hipSuccess) e = hipMemsetAsync(base + sp.sync.off, 0, sp.sync.bytes, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release(plan.get());
@@ -298,7 +322,18 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
         release(plan.get());
         return st;
     }
-    fill_dev(hp, p->dtype, base, tp, wp, &plan->dev);
+    fill_dev(hp, p->dtype, base, tp, wp, sp, &plan->dev);
+    if (plan->dev.fused) {
+        // the fused launch needs its waiting blocks to be fewer than the blocks
+        // the device holds at once; keep at least half the slots for the rest
+        int capacity = 0;
+        e = phi::middle_capacity(plan->dev, &capacity);
+        if (e != hipSuccess) {
+            release(plan.get());
+            return device_fail(nullptr, e, "occupancy query");
+        }
+        if (2 * phi::middle_waiting_blocks(plan->dev) > capacity) plan->dev.fused = 0;
+    }
     *out = plan.release();
     return PHI_OK;
 }
@@ -586,6 +621,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         for (const phi::HostPlan& hp : plan->sets) tparts.push_back(layout_tables(hp, es, L));
         std::vector<WorkParts> wparts;
         for (int i = 0; i < count; ++i) wparts.push_back(layout_work(plan->sets[plan->member_set[i]], es, L));
+        const SyncPart bsync = layout_sync(L);   // batch kernels do not use the fused launch
         const Part p_dev = L.take(sizeof(phi::DevPlan) * count);
         const Part p_off = L.take(sizeof(int64_t) * (count + 1));
         const Part p_rows = L.take(sizeof(phi::WorkItem) * rows.size());
@@ -609,7 +645,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         std::vector<phi::DevPlan> devs(count);
         for (int i = 0; i < count; ++i)
             fill_dev(plan->sets[plan->member_set[i]], dtype, base, tparts[plan->member_set[i]], wparts[i],
-                     &devs[i]);
+                     bsync, &devs[i]);
         auto up = [&](const Part& pt, const void* src) -> hipError_t {
             if (pt.bytes == 0) return hipSuccess;
             return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
@@ -818,6 +854,8 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
     if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(plan, e, "hipStreamSynchronize");
+    st = phi_plan_device_status(plan);
+    if (st != PHI_OK) return st;
     *count = t.count;
     for (int i = 0; i < t.count && i < capacity; ++i) {
         float ms = 0.f;
@@ -826,6 +864,23 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
         kernel_ms[i] = ms;
         names[i] = t.names[i];
     }
+    return PHI_OK;
+}
+
+phi_status phi_plan_device_status(phi_plan_t plan) {
+    phi_status st = check_plan(plan);
+    if (st != PHI_OK) return st;
+    if (plan->n_members > 0) return PHI_OK;   // batches do not use the fused launch
+    st = check_device(plan);
+    if (st != PHI_OK) return st;
+    unsigned flag = 0;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(&flag, plan->dev.sync + phi::kSyncError * phi::kSyncStride, sizeof(flag),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(plan, e, "phi_plan_device_status");
+    if (flag != 0)
+        return fail(plan, PHI_ERR_DEVICE, "a wait inside the fused solve launch exceeded its spin limit");
     return PHI_OK;
 }
 

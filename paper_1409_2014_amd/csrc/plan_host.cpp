@@ -271,7 +271,7 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
         return PHI_ERR_TOL_UNREACHABLE;
     }
     if ((p->flags & ~(PHI_COMPONENT_Y | PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI |
-                      PHI_KERNEL_GAUSSIAN)) != 0) {
+                      PHI_KERNEL_GAUSSIAN | PHI_TWO_STREAMS)) != 0) {
         *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG;
     }
     if ((p->flags & PHI_COMPONENT_Y) && (p->flags & PHI_COMPONENT_XY)) {
@@ -295,6 +295,7 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->component = (p->flags & PHI_COMPONENT_XY) ? 2 : (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
     hp->radial_jacobi = (p->flags & PHI_RADIAL_JACOBI) ? 1 : 0;
     hp->gaussian_kernel = (p->flags & PHI_KERNEL_GAUSSIAN) ? 1 : 0;
+    hp->two_streams = (p->flags & PHI_TWO_STREAMS) ? 1 : 0;
     hp->dtype = p->dtype;
     hp->h = p->hx;
     hp->half_width = 0.5 * n * p->hx;

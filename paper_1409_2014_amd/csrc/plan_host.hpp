@@ -35,6 +35,7 @@ struct HostPlan {
     int n_r = 0, n_theta = 0, n_nodes = 0;
     int component = 0;          // multiplier -k_a k_b/|k|^2: 0 (a,b) = (x,x), 1 (y,y), 2 (x,y)
     int radial_jacobi = 0;      // Gauss-Jacobi(0, 1) radial rule instead of Gauss-Legendre
+    int two_streams = 0;        // node-side chain as separate launches on a second stream
     int gaussian_kernel = 0;    // Greengard-Lee Gaussian gridding instead of the ES kernel
     phi_dtype dtype = PHI_F64;
     double h = 0, half_width = 0, sigma = 0, cutoff = 0;

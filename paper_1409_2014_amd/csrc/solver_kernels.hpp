@@ -8,6 +8,18 @@
 
 namespace phi {
 
+// Slots of a plan's counter block for the fused middle launch (see
+// block_sync.hpp): slot k is the unsigned at index k * kSyncStride, one
+// 128-byte line each.
+enum SyncSlot : int {
+    kSyncT2Done = 0,      // type-2 window blocks finished
+    kSyncNodesDone = 1,   // node blocks finished
+    kSyncError = 2,       // sticky: a wait exceeded its spin limit
+    kSyncSlots = 3,
+};
+constexpr int kSyncStride = 32;
+constexpr int kSyncWords = kSyncSlots * kSyncStride;
+
 // Everything a kernel needs, passed by value.  All pointers are device
 // pointers into the plan's single allocation.
 struct DevPlan {
@@ -17,6 +29,7 @@ struct DevPlan {
     int patch, patch_lo, width, n_nodes;
     int component;          // 0: -kx^2/|k|^2, 1: -ky^2/|k|^2, 2: -kx ky/|k|^2
     int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
+    int fused;              // a solve runs the I1 columns and the node-side chain as one launch
     double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index
     int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
     double h2, inv_f2;
@@ -44,6 +57,7 @@ struct DevPlan {
     void* pts;      // M complex: a_j = q_j rho_hat_j
     void* tiles;    // n_sub x E x E complex: each subproblem's spread tile
     void* u;        // N x Q complex: type-1 column transforms, [n2][x]
+    unsigned* sync; // kSyncSlots counters of the fused launch (plan-owned, zero between launches)
 };
 
 // Streams and events a plan uses to run the node-side chain concurrently with
@@ -71,6 +85,14 @@ hipError_t enqueue_periodic(const DevPlan& P, const void* in, void* out, hipStre
 // Records the start (end = false) or the end (end = true) of kernel `name` on
 // stream s; no-op without a timer.
 hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s);
+
+// Blocks of the fused middle launch of plan P that can be resident on the
+// current device at once (the launch is deadlock-free while the blocks that
+// wait are fewer than this).
+hipError_t middle_capacity(const DevPlan& P, int* blocks);
+
+// Blocks of the fused middle launch that wait for other blocks of it.
+inline int middle_waiting_blocks(const DevPlan& P) { return P.n_sub + P.patch; }
 
 // Enqueue a stage chain on stream s (no host synchronisation).  adjoint = 1
 // reverses every transform direction (the transposed operator).

@@ -31,7 +31,8 @@ def _dtype_code(dtype) -> int:
 def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta: int = 128,
                 tol: float | None = None, sigma: float | None = None, cutoff: float | None = None,
                 component: str = "x", pad: int = 2, bin: int = 0, sub_nodes: int = 0,
-                autotune: bool = False, radial: str = "legendre", kernel: str = "es") -> B.PhiParams:
+                autotune: bool = False, radial: str = "legendre", kernel: str = "es",
+                two_streams: bool = False) -> B.PhiParams:
     code = _dtype_code(dtype)
     p = B.PhiParams()
     B.check(B.lib().phi_params_default(ctypes.byref(p), int(n), float(h), code))
@@ -51,7 +52,8 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
         raise ValueError(f"kernel must be 'es' or 'gaussian', got {kernel!r}")
     p.flags = (comp_flags[component] | (B.PHI_AUTOTUNE if autotune else 0)
                | (B.PHI_RADIAL_JACOBI if radial == "jacobi" else 0)
-               | (B.PHI_KERNEL_GAUSSIAN if kernel == "gaussian" else 0))
+               | (B.PHI_KERNEL_GAUSSIAN if kernel == "gaussian" else 0)
+               | (B.PHI_TWO_STREAMS if two_streams else 0))
     p.bin = int(bin)
     p.sub_nodes = int(sub_nodes)
     return p
@@ -240,6 +242,12 @@ class Plan:
                                             _stream_handle(self.device), ms, names, cap,
                                             ctypes.byref(count)), self._handle)
         return [(names[i].decode(), float(ms[i])) for i in range(min(count.value, cap))]
+
+    def device_status(self) -> None:
+        """Synchronise and raise if a wait inside the fused solve launch ran past
+        its spin limit since the plan was created."""
+        with torch.cuda.device(self.device):
+            B.check(B.lib().phi_plan_device_status(self._handle), self._handle)
 
     def nodes(self):
         """(kx, ky, q) of the plan's polar nodes as float64 numpy arrays, plan order."""

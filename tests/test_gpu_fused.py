@@ -1,0 +1,108 @@
+"""The fused middle launch (the I1 columns and the whole node-side chain in one
+launch whose dependent blocks wait on device counters; the default on padded
+sides up to 512) against the two-stream layout of separate launches:
+bit-identical results, forward and transposed, on every padded side from 16
+to 512, repeated calls (the counters are zeroed by each solve's first
+kernel), graph replays, and the device-side spin-limit flag never set.  Both
+layouts also stay within the solve's bars of the FP64 oracle (checked by the
+parity tests; here one small case closes the loop)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOLS = {torch.float64: 1e-12, torch.float32: 1e-7}
+
+
+@pytest.fixture(scope="module")
+def ps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1409_2014_amd as ps
+    return ps
+
+
+def density(n, half, seed):
+    spec = W.draw_mixture(seed, 8, 0.375 * half, (0.5, 2.0))
+    if half > 16:
+        spec = W.MixtureSpec(spec.cx, spec.cy, spec.wx * half / 16, spec.wy * half / 16, spec.phase)
+    return W.mixture_density(n, half, spec)
+
+
+CASES = [(8, 4.0), (16, 4.0), (64, 8.0), (96, 4.0), (200, 8.0), (256, 8.0)]
+
+
+@pytest.mark.parametrize("n,half", CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_launch_equals_two_streams(ps, n, half, dtype):
+    print(f"case: fused vs two streams N={n} {dtype}", flush=True)
+    h = 2 * half / n
+    rho = torch.as_tensor(density(n, half, 500 + n), dtype=dtype, device="cuda")
+    fused = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
+    split = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype], two_streams=True)
+    a1 = fused.solve(rho)
+    b1 = split.solve(rho)
+    assert torch.equal(a1, b1)
+    # repeated calls: the counters are back at zero after every launch
+    for _ in range(3):
+        assert torch.equal(fused.solve(rho), a1)
+    a2 = fused.solve_adjoint(a1)
+    b2 = split.solve_adjoint(b1)
+    assert torch.equal(a2, b2)
+    fused.device_status()
+    fused.close()
+    split.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_launch_under_graph_replay(ps, dtype):
+    """Ten replays of a captured forward + transposed pair, with eager solves
+    between them: every replay equals the eager result."""
+    n, half = 256, 8.0
+    h = 2 * half / n
+    print(f"case: fused graph replay N={n} {dtype}", flush=True)
+    plan = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
+    rho = torch.as_tensor(density(n, half, 77), dtype=dtype, device="cuda")
+    ref_f = plan.solve(rho)
+    ref_b = plan.solve_adjoint(ref_f)
+    out_f = torch.empty_like(rho)
+    out_b = torch.empty_like(rho)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.solve(rho, out_f)
+        plan.solve_adjoint(out_f, out_b)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.solve(rho, out_f)
+        plan.solve_adjoint(out_f, out_b)
+    for i in range(10):
+        out_f.zero_()
+        out_b.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_f, ref_f), f"replay {i}"
+        assert torch.equal(out_b, ref_b), f"replay {i}"
+        assert torch.equal(plan.solve(rho), ref_f)
+    plan.device_status()
+    plan.close()
+
+
+def test_fused_launch_matches_oracle(ps):
+    n, half = 96, 4.0
+    h = 2 * half / n
+    print("case: fused vs oracle N=96 FP64", flush=True)
+    rho = density(n, half, 9)
+    plan = ps.Plan(n, h, dtype=torch.float64, tol=1e-12)
+    got = plan.solve(torch.as_tensor(rho, device="cuda")).cpu().numpy()
+    fine = plan.info["n_fine"]
+    plan.close()
+    ref = O.phi(rho, O.SplitParams(n=n, h=h, n_r=64, n_theta=128, pad_side=fine))
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
