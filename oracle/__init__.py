@@ -11,7 +11,8 @@ Modules
   split_solver  the split quadrature by direct sums: I1 (padded DFT), polar rule,
                 type-2 / type-1 direct sums, Phi, literal transpose
   closed_forms  exact potentials that pin the oracle (Examples 1 and 2,
-                anisotropic Gaussians, the I2 of a point source)
+                anisotropic Gaussians, the I2 of a point source, the 2-D
+                Coulomb potential of Gaussians)
   ds_stepper    split-step (Strang) time integration of the DS system with
                 Phi from split_solver, the L4 loss and its reverse-mode gradient
   periodic      the standard periodic FFT potential solver the paper compares

@@ -8,7 +8,10 @@ density with a known answer, independent of any discretisation:
   * an axis-aligned anisotropic Gaussian through a one-dimensional integral
     (derived below), which by superposition gives the potential of |u|^2 for
     any Gaussian-mixture wave function,
-  * the low-frequency part I2 of a point source (a Hankel-transform identity).
+  * the low-frequency part I2 of a point source (a Hankel-transform identity),
+  * the 2-D Coulomb potential (multiplier 1/|k|, the Remark of Sec. 2.1) of an
+    isotropic Gaussian (a Bessel-function closed form) and of an axis-aligned
+    Gaussian (a one-dimensional integral), hence of any Gaussian mixture.
 """
 from __future__ import annotations
 
@@ -24,6 +27,9 @@ __all__ = [
     "phi_mixture",
     "rho_mixture_from_terms",
     "i2_point_source",
+    "coulomb_isotropic_gaussian",
+    "coulomb_axis_gaussian",
+    "coulomb_mixture",
 ]
 
 
@@ -190,3 +196,58 @@ def i2_point_source(x: np.ndarray, y: np.ndarray, sigma: float) -> np.ndarray:
                          0.5 * sigma ** 2)
     aniso = math.pi * cos2 * (first - 0.5 * sigma ** 2 * np.exp(-e_arg))
     return iso + aniso
+
+
+def coulomb_isotropic_gaussian(x: np.ndarray, y: np.ndarray, amplitude: float = 1.0,
+                               a: float = 1.0) -> np.ndarray:
+    """2-D Coulomb potential Phi = int rho(y) / |x - y| dy (Fourier multiplier
+    1/|k| in the 2 pi convention of eq. 5) of rho = amplitude e^{-a r^2}:
+
+        Phi = amplitude pi^{3/2} / sqrt(a) e^{-a r^2/2} I_0(a r^2/2).
+
+    In polar coordinates the angular integral of 1/|x - y| against the radial
+    density gives a Bessel function: with s = |y|, int_0^{2 pi} e^{2 r s cos t} dt
+    = 2 pi I_0(2 r s) after completing |x - y|^2 through the Gaussian's
+    Laplace representation 1/|z| = pi^{-1/2} int_0^inf t^{-1/2} e^{-t z^2} dt;
+    the value at r = 0 is amplitude pi^{3/2}/sqrt(a).  scipy's exponentially
+    scaled i0e(z) = e^{-z} I_0(z) serves as the Bessel function."""
+    from scipy.special import i0e
+    r2 = x * x + y * y
+    return amplitude * math.pi ** 1.5 / math.sqrt(a) * i0e(0.5 * a * r2)
+
+
+def coulomb_axis_gaussian(xr: np.ndarray, yr: np.ndarray, a: float, b: float,
+                          step: float = 0.125, umin: float = -40.0, umax: float = 40.0) -> np.ndarray:
+    """2-D Coulomb potential of G = exp(-X^2/a^2 - Y^2/b^2) (X, Y relative to its
+    centre).  From 1/|z| = pi^{-1/2} int_0^inf t^{-1/2} e^{-t |z|^2} dt, the
+    Gaussian convolution per axis int e^{-y^2/a^2} e^{-t (X-y)^2} dy =
+    a sqrt(pi/(1 + a^2 t)) e^{-t X^2/(1 + a^2 t)}, and t = s^2:
+
+        Phi = 2 sqrt(pi) a b int_0^inf e^{-s^2 X^2/(1+a^2 s^2) - s^2 Y^2/(1+b^2 s^2)}
+              / sqrt((1 + a^2 s^2)(1 + b^2 s^2)) ds.
+
+    The integral is taken with s = e^u and the trapezoidal rule on u (the
+    integrand times s decays exponentially in both directions of u, so the rule
+    converges geometrically; exact power-of-two step and integer ends)."""
+    xr = np.asarray(xr, dtype=np.float64)
+    yr = np.asarray(yr, dtype=np.float64)
+    u = umin + step * np.arange(int(round((umax - umin) / step)) + 1)
+    s = np.exp(u)
+    s2 = (s * s)[None, :]
+    shape = xr.shape
+    xf = xr.reshape(-1, 1)
+    yf = yr.reshape(-1, 1)
+    da = 1.0 + a * a * s2
+    db = 1.0 + b * b * s2
+    integrand = np.exp(-s2 * xf * xf / da - s2 * yf * yf / db) / np.sqrt(da * db) * s[None, :]   # ds = s du
+    total = step * integrand.sum(axis=1)
+    return (2.0 * math.sqrt(math.pi) * a * b * total).reshape(shape)
+
+
+def coulomb_mixture(terms, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """2-D Coulomb potential of a Gaussian-mixture density (mixture_terms) by
+    superposition."""
+    out = np.zeros(np.broadcast(x, y).shape)
+    for weight, mx, my, sx, sy in terms:
+        out += weight * coulomb_axis_gaussian(x - mx, y - my, sx, sy)
+    return out

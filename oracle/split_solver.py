@@ -38,6 +38,12 @@ Readings of points the paper leaves open (each is listed in the design notes):
     smooth radial integrand); azimuthal rule: trapezoid theta_j = 2 pi j/N_theta.
   * I2 is complex in eq. 12; its real part is taken (the imaginary part is
     zero by the k -> -k symmetry of the node set when N_theta is even).
+  * the 2-D Coulomb multiplier 1/|k| (the Remark of Sec. 2.1): the paper's
+    Gaussian partition leaves a cone in the I1 integrand at k = 0 (its error is
+    pinned as a measured reading); the partition erfc(|k|/sigma) keeps the I1
+    integrand erf(|k|/sigma)/|k| smooth and the polar one erfc(r/sigma) smooth in
+    r, as Sec. 2.1 asks of the two parts.  The radial rule is Gauss-Legendre:
+    1/|k| cancels the Jacobian r.
 """
 from __future__ import annotations
 
@@ -81,7 +87,18 @@ class SplitParams:
                 "xy": -kx ky/|k|^2 (the mixed one; with the other two the whole
                 tensor -k_i k_j/|k|^2, another potential the Remark of Sec. 2.1
                 covers: bounded, even and of degree 0, so the split carries over
-                with only the multiplier's values changed)
+                with only the multiplier's values changed);
+                "coulomb": 1/|k|, the 2-D Coulomb potential int rho(y)/|x-y| dy
+                (the Remark of Sec. 2.1: any multiplier with a known transform)
+    partition   the partition function p(k) of Sec. 2.1 (eq. 8): "gauss" is the
+                paper's e^{-|k|^2/sigma^2}; "erfc" is erfc(|k|/sigma), for
+                "coulomb" only.  Sec. 2.1 asks that the I1 integrand be smooth
+                in Cartesian and the I2 integrand in polar coordinates.  With
+                1/|k| the Gaussian p leaves (1 - p)/|k| ~ |k|/sigma^2 at k = 0, a
+                cone the padded trapezoidal rule resolves only to an error that
+                falls like 1/((kappa-1) L); erf(|k|/sigma)/|k| is an even entire
+                function of |k| (smooth at 0), and p(r) r / r = erfc(r/sigma) is
+                smooth in r, so both parts keep spectral accuracy.  None: "gauss"
     """
     n: int
     h: float
@@ -94,6 +111,16 @@ class SplitParams:
     component: str = "xx"
     radial: str = "legendre"    # or "jacobi": Gauss-Jacobi(0, 1), the weight r built in
     pad_side: int | None = None
+    partition: str | None = None
+
+    @property
+    def partition_kind(self) -> str:
+        kind = "gauss" if self.partition is None else self.partition
+        if kind not in ("gauss", "erfc"):
+            raise ValueError(f"unknown partition {kind!r}")
+        if kind == "erfc" and self.component != "coulomb":
+            raise ValueError("the erfc partition is for the Coulomb multiplier 1/|k| only")
+        return kind
 
     @property
     def half_width(self) -> float:
@@ -131,12 +158,25 @@ def grid_points(p: SplitParams) -> np.ndarray:
 
 
 def highfreq_multiplier(kx: np.ndarray, ky: np.ndarray, sigma: float,
-                        component: str = "xx") -> np.ndarray:
+                        component: str = "xx", partition: str = "gauss") -> np.ndarray:
     """g1(k) = -(k_a^2/|k|^2) (1 - exp(-|k|^2/sigma^2)), g1(0) = 0.
 
     The integrand of I1 (Sec. 2.1, eq. 9) divided by rho_hat.  1 - e^{-s} is
-    formed as -expm1(-s) so that it keeps full relative accuracy near k = 0."""
+    formed as -expm1(-s) so that it keeps full relative accuracy near k = 0.
+    "coulomb": (1 - p(k))/|k|, i.e. (1 - e^{-|k|^2/sigma^2})/|k| (0 at k = 0) or,
+    with the erfc partition, erf(|k|/sigma)/|k| (2/(sigma sqrt(pi)) at k = 0)."""
     k2 = kx * kx + ky * ky
+    if component == "coulomb":
+        from scipy.special import erf
+        kk = np.sqrt(k2)
+        out = np.zeros_like(k2)
+        nz = k2 > 0.0
+        if partition == "erfc":
+            out[nz] = erf(kk[nz] / sigma) / kk[nz]
+            out[~nz] = 2.0 / (sigma * math.sqrt(math.pi))
+        else:
+            out[nz] = (-np.expm1(-k2[nz] / sigma ** 2)) / kk[nz]
+        return out
     num = {"xx": kx * kx, "yy": ky * ky, "xy": kx * ky}[component]
     out = np.zeros_like(k2)
     nz = k2 > 0.0
@@ -159,7 +199,7 @@ def padded_multiplier(p: SplitParams) -> np.ndarray:
     -1/2)."""
     sigma, _ = split_constants(p)
     kx, ky = _padded_frequencies(p)
-    g1 = highfreq_multiplier(kx, ky, sigma, p.component)
+    g1 = highfreq_multiplier(kx, ky, sigma, p.component, p.partition_kind)
     if p.component == "xy":
         nyq = p.padded_side // 2
         g1[nyq, :] = 0.0
@@ -228,13 +268,29 @@ def polar_rule(p: SplitParams):
     (c/2) w_i r_i (the Jacobian r of eq. 11 folded in); azimuthal trapezoid
     theta_j = 2 pi j / N_theta with weight 2 pi / N_theta.  The I2 weight is
         q_ij = -omega_i omega_j cos^2(theta_j) p(k_ij)      ("xx")
-    (sin^2 for "yy", cos sin for "xy": the multiplier on the unit circle).  Returns flattened arrays kx, ky, q of length N_r N_theta
-    in (radial-major, angle-minor) order."""
+    (sin^2 for "yy", cos sin for "xy": the multiplier on the unit circle).
+    "coulomb": the multiplier 1/r cancels the Jacobian r, so
+        q_ij = (omega_i / r_i) omega_j p(r_i)
+    with p the Gaussian or erfc(r/sigma) (see SplitParams).  Returns flattened
+    arrays kx, ky, q of length N_r N_theta in (radial-major, angle-minor) order."""
+    partition = p.partition_kind           # validates the partition for the component
     sigma, _ = split_constants(p)
     r, w_r, theta, w_t = polar_nodes_weights(p)
     rr, tt = np.meshgrid(r, theta, indexing="ij")
     kx = rr * np.cos(tt)
     ky = rr * np.sin(tt)
+    if p.component == "coulomb":
+        if p.radial == "jacobi":
+            # the rule's weight is the Jacobian, which 1/r cancels: the integrand
+            # p(r) is smooth, and p(r)/r against the weight (1 + x) is not
+            raise ValueError("the Coulomb multiplier cancels the Jacobian: use the Gauss-Legendre radial rule")
+        if partition == "erfc":
+            from scipy.special import erfc
+            part = erfc(rr / sigma)
+        else:
+            part = np.exp(-(rr ** 2) / sigma ** 2)
+        q = (w_r[:, None] / rr * w_t) * part
+        return kx.ravel(), ky.ravel(), q.ravel()
     ang = {"xx": np.cos(tt) ** 2, "yy": np.sin(tt) ** 2, "xy": np.cos(tt) * np.sin(tt)}[p.component]
     q = -(w_r[:, None] * w_t) * ang * np.exp(-(rr ** 2) / sigma ** 2)
     return kx.ravel(), ky.ravel(), q.ravel()

@@ -168,15 +168,17 @@ def _pins_hold():
 def _sign_of_i1(monkeypatch):
     orig = O.highfreq_multiplier
     monkeypatch.setattr(O, "highfreq_multiplier",
-                        lambda kx, ky, s, component="xx": -orig(kx, ky, s, component) if component == "xy"
-                        else orig(kx, ky, s, component))
+                        lambda kx, ky, s, component="xx", partition="gauss":
+                        -orig(kx, ky, s, component, partition) if component == "xy"
+                        else orig(kx, ky, s, component, partition))
 
 
 def _abs_of_i1(monkeypatch):
     orig = O.highfreq_multiplier
     monkeypatch.setattr(O, "highfreq_multiplier",
-                        lambda kx, ky, s, component="xx": -np.abs(orig(kx, ky, s, component)) if component == "xy"
-                        else orig(kx, ky, s, component))
+                        lambda kx, ky, s, component="xx", partition="gauss":
+                        -np.abs(orig(kx, ky, s, component, partition)) if component == "xy"
+                        else orig(kx, ky, s, component, partition))
 
 
 def _squared_angle_in_i2(monkeypatch):

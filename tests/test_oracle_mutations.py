@@ -78,7 +78,7 @@ def _sin_for_cos(monkeypatch):
 
 
 def _partition_not_complement(monkeypatch):
-    def bad(kx, ky, sigma, component="xx"):
+    def bad(kx, ky, sigma, component="xx", partition="gauss"):
         k2 = kx * kx + ky * ky
         num = kx * kx if component == "xx" else ky * ky
         out = np.zeros_like(k2)
