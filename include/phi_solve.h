@@ -62,6 +62,21 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
                                 -k_i k_j/|k|^2 (Sec. 2.1, Remark: the split needs only the
                                 multiplier's values; this one is also bounded, even, and degree-0
                                 homogeneous, so I1 stays smooth at k = 0).  Not with PHI_COMPONENT_Y. */
+#define PHI_COMPONENT_COULOMB 64u /* multiplier 1/|k|: the 2-D Coulomb potential int rho(y)/|x - y| dy
+                                (Sec. 2.1, Remark: the split applies to any multiplier whose
+                                transform is known).  1/|k| cancels the polar Jacobian r, so
+                                q_j = (c/2) w_i (2 pi/N_theta) p(r_i) with Gauss-Legendre radial
+                                nodes (PHI_RADIAL_JACOBI is refused), and the I1 multiplier is
+                                (1 - p(k))/|k|.  The partition is p = erfc(|k|/sigma) unless
+                                PHI_PARTITION_GAUSS is set: both integrands are then smooth
+                                (erf(r)/r is even and entire), and the solve reaches the NUFFT
+                                tolerance.  Not with PHI_COMPONENT_Y / _XY; not in batches, the
+                                periodic solver or the stepper (PHI_ERR_UNSUPPORTED). */
+#define PHI_PARTITION_GAUSS 128u /* with PHI_COMPONENT_COULOMB: the paper's partition
+                                p = e^{-|k|^2/sigma^2}, which leaves a cone |k|/sigma^2 in the I1
+                                integrand at k = 0; the padded trapezoidal rule then resolves I1
+                                only to about 3e-4 relative at L = 8 (falling like 1/L at the
+                                default sigma).  Kept to reproduce that limit. */
 #define PHI_RADIAL_JACOBI 4u /* radial rule Gauss-Jacobi(0, 1) on [0, c] (weight r built in; the rule
                                 Sec. 2.1 names) instead of Gauss-Legendre with r in the weight */
 #define PHI_KERNEL_GAUSSIAN 16u /* NUFFT spreading kernel: the truncated Gaussian of Greengard-Lee
@@ -103,8 +118,9 @@ typedef struct {
                               reading of Sec. 2.1 with the padding factor F/N of the box used) */
     double cutoff;         /* disk radius c   (<= 0: sqrt(ln 1e16) * sigma)                     */
     phi_dtype dtype;       /* data precision of rho / Phi; node and deconvolution tables are FP64 */
-    uint32_t flags;        /* PHI_COMPONENT_Y or PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI
-                              | PHI_KERNEL_GAUSSIAN                                                */
+    uint32_t flags;        /* PHI_COMPONENT_Y, PHI_COMPONENT_XY or PHI_COMPONENT_COULOMB
+                              (| PHI_PARTITION_GAUSS) | PHI_AUTOTUNE | PHI_RADIAL_JACOBI
+                              | PHI_KERNEL_GAUSSIAN | PHI_TWO_STREAMS                              */
     int32_t bin;           /* bin side of the node sort in fine-grid cells: 4, 8 or 16 (0: 4)    */
     int32_t sub_nodes;     /* most nodes per spreading / interpolation block, 8..64 (0: 64)      */
 } phi_params;

@@ -16,6 +16,8 @@ PHI_AUTOTUNE = 2
 PHI_RADIAL_JACOBI = 4
 PHI_KERNEL_GAUSSIAN = 16
 PHI_TWO_STREAMS = 32
+PHI_COMPONENT_COULOMB = 64
+PHI_PARTITION_GAUSS = 128
 
 STATUS_NAMES = {
     0: "PHI_OK", 1: "PHI_ERR_INVALID_ARG", 2: "PHI_ERR_UNSUPPORTED", 3: "PHI_ERR_TOL_UNREACHABLE",

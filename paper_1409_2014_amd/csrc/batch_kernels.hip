@@ -68,7 +68,8 @@ __global__ __launch_bounds__(kBatchThreads) void kb_cols(BatchDev B) {
     const WorkItem w = (MIXED ? B.cols_mixed : B.cols)[xcd_logical_block(blockIdx.x, gridDim.x)];
     const DevPlan P = B.members[w.member];
     if (w.kind == 0) {
-        PHI_BATCH_LOG(P.log_fine, (cols_highfreq_body<R, LOG_, DIR, batch_lines(LOG_), MIXED>(P, w.item, lds_all)));
+        PHI_BATCH_LOG(P.log_fine, (cols_highfreq_body<R, LOG_, DIR, batch_lines(LOG_),
+                                                    MIXED ? kKindMixed : kKindQuadratic>(P, w.item, lds_all)));
     } else {
         PHI_BATCH_LOG(P.log_fine, (cols_type2_body<R, LOG_, DIR, batch_lines(LOG_)>(P, w.item, lds_all)));
     }

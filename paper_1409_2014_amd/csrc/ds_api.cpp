@@ -145,6 +145,8 @@ phi_status phi_ds_create(const phi_params* solve, const phi_ds_options* opt, voi
         return err(PHI_ERR_INVALID_ARG, "unknown scheme");
     if (opt->potential != PHI_DS_SPLIT && opt->potential != PHI_DS_PERIODIC)
         return err(PHI_ERR_INVALID_ARG, "unknown potential solver");
+    if (solve->flags & (PHI_COMPONENT_COULOMB | PHI_PARTITION_GAUSS))
+        return err(PHI_ERR_UNSUPPORTED, "the DS stepper takes the DS multiplier, not the Coulomb one");
     if (solve->nx < 16 || solve->nx > 4096 || (solve->nx & (solve->nx - 1)) != 0)
         return err(PHI_ERR_UNSUPPORTED, "the stepper takes power-of-two grid sides 16 .. 4096");
     try {

@@ -216,6 +216,8 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->width = hp.width;
     d->n_nodes = hp.n_nodes;
     d->component = hp.component;
+    d->partition_erfc = hp.partition_erfc;
+    d->inv_sigma = 1.0 / hp.sigma;
     // The two branches of a solve share the GPU, and the one enqueued first is
     // served first: the node-side chain (the same few small kernels at every N)
     // unless the high-frequency columns carry more than 1.5 times the work they
@@ -229,7 +231,7 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     // inside the shared launch is longer than beside it on a second stream
     // (1024^2 FP32 52 -> 63 us, 2048^2 104 -> 117 us).  Not for the kernel
     // variants the fused launch leaves out, or when asked for two streams.
-    d->fused = (!hp.two_streams && hp.component != 2 && hp.width <= phi::kMaxEsWidth &&
+    d->fused = (!hp.two_streams && hp.component <= 1 && hp.width <= phi::kMaxEsWidth &&
                 hp.log_fine <= kFusedMaxLogFine) ? 1 : 0;
     d->sync = reinterpret_cast<unsigned*>(base + sp.sync.off);
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
@@ -574,6 +576,11 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
                     delete plan;
                     return fail(nullptr, st, "member " + std::to_string(i) + ": " + err);
                 }
+                if (hp.component == 3) {
+                    delete plan;
+                    return fail(nullptr, PHI_ERR_UNSUPPORTED,
+                                "member " + std::to_string(i) + ": the Coulomb multiplier is not batched");
+                }
                 if (hp.log_fine < phi::kBatchMinLogFine || hp.log_fine > phi::kBatchMaxLogFine) {
                     delete plan;
                     return fail(nullptr, PHI_ERR_UNSUPPORTED,
@@ -822,6 +829,8 @@ phi_status phi_nodes_type1(phi_plan_t plan, const void* coef, void* field, void*
 phi_status phi_solve_periodic(phi_plan_t plan, const void* rho, void* phi_out, void* stream) {
     phi_status st = check_plan(plan);
     if (st != PHI_OK) return st;
+    if (plan->n_members == 0 && plan->host.component == 3)
+        return fail(plan, PHI_ERR_UNSUPPORTED, "the periodic solver takes the DS multipliers, not the Coulomb one");
     if (plan->n_members == 0 && (plan->host.log_n < 4 || plan->host.log_n > 12))
         return fail(plan, PHI_ERR_UNSUPPORTED, "the periodic solver takes power-of-two grid sides 16 .. 4096");
     return run(plan, phi::Stage::Periodic, rho, phi_out, 0, stream);

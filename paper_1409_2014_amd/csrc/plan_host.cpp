@@ -270,12 +270,26 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
         *err = fmt("tol %g outside [%g, 0.1] for this dtype", p->tol, tol_min);
         return PHI_ERR_TOL_UNREACHABLE;
     }
-    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_COMPONENT_XY | PHI_AUTOTUNE | PHI_RADIAL_JACOBI |
-                      PHI_KERNEL_GAUSSIAN | PHI_TWO_STREAMS)) != 0) {
+    if ((p->flags & ~(PHI_COMPONENT_Y | PHI_COMPONENT_XY | PHI_COMPONENT_COULOMB | PHI_PARTITION_GAUSS |
+                      PHI_AUTOTUNE | PHI_RADIAL_JACOBI | PHI_KERNEL_GAUSSIAN | PHI_TWO_STREAMS)) != 0) {
         *err = "unknown flag bits"; return PHI_ERR_INVALID_ARG;
     }
-    if ((p->flags & PHI_COMPONENT_Y) && (p->flags & PHI_COMPONENT_XY)) {
-        *err = "PHI_COMPONENT_Y and PHI_COMPONENT_XY exclude each other"; return PHI_ERR_INVALID_ARG;
+    {
+        const int comps = ((p->flags & PHI_COMPONENT_Y) ? 1 : 0) + ((p->flags & PHI_COMPONENT_XY) ? 1 : 0) +
+                          ((p->flags & PHI_COMPONENT_COULOMB) ? 1 : 0);
+        if (comps > 1) {
+            *err = "PHI_COMPONENT_Y, PHI_COMPONENT_XY and PHI_COMPONENT_COULOMB exclude each other";
+            return PHI_ERR_INVALID_ARG;
+        }
+    }
+    if ((p->flags & PHI_PARTITION_GAUSS) && !(p->flags & PHI_COMPONENT_COULOMB)) {
+        *err = "PHI_PARTITION_GAUSS applies to PHI_COMPONENT_COULOMB only (the Gaussian partition is the "
+               "default of the other multipliers)";
+        return PHI_ERR_INVALID_ARG;
+    }
+    if ((p->flags & PHI_COMPONENT_COULOMB) && (p->flags & PHI_RADIAL_JACOBI)) {
+        *err = "the Coulomb multiplier cancels the polar Jacobian: its radial rule is Gauss-Legendre";
+        return PHI_ERR_INVALID_ARG;
     }
     if (p->bin != 0 && p->bin != 4 && p->bin != 8 && p->bin != kMaxBinSize) {
         *err = "bin must be 0, 4, 8 or 16"; return PHI_ERR_INVALID_ARG;
@@ -292,7 +306,9 @@ phi_status derive(const phi_params* p, HostPlan* hp, std::string* err) {
     hp->n_r = p->n_r;
     hp->n_theta = p->n_theta;
     hp->n_nodes = p->n_r * p->n_theta;
-    hp->component = (p->flags & PHI_COMPONENT_XY) ? 2 : (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
+    hp->component = (p->flags & PHI_COMPONENT_COULOMB) ? 3 : (p->flags & PHI_COMPONENT_XY) ? 2
+                    : (p->flags & PHI_COMPONENT_Y) ? 1 : 0;
+    hp->partition_erfc = ((p->flags & PHI_COMPONENT_COULOMB) && !(p->flags & PHI_PARTITION_GAUSS)) ? 1 : 0;
     hp->radial_jacobi = (p->flags & PHI_RADIAL_JACOBI) ? 1 : 0;
     hp->gaussian_kernel = (p->flags & PHI_KERNEL_GAUSSIAN) ? 1 : 0;
     hp->two_streams = (p->flags & PHI_TWO_STREAMS) ? 1 : 0;
@@ -350,6 +366,8 @@ void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double
     // theta_j = 2 pi j / N_theta with weight 2 pi / N_theta;
     // q_ij = -w_r w_theta cos^2(theta_j) exp(-r_i^2 / sigma^2)   (sin^2 for the y component,
     // cos sin for the mixed one: the multiplier's value on the unit circle).
+    // Coulomb (1/|k|): the multiplier cancels the Jacobian, q_ij = (c/2) w_i w_theta p(r_i)
+    // with p = erfc(r/sigma) or the Gaussian (Gauss-Legendre only).
     std::vector<double> gx(hp.n_r), gw(hp.n_r);
     if (hp.radial_jacobi) gauss_jacobi01(hp.n_r, gx.data(), gw.data());
     else gauss_legendre(hp.n_r, gx.data(), gw.data());
@@ -364,6 +382,18 @@ void polar_nodes(const HostPlan& hp, std::vector<double>* kx, std::vector<double
         // Gauss-Legendre gets it folded into the weight
         const double wr = hp.radial_jacobi ? 0.25 * hp.cutoff * hp.cutoff * gw[i] : 0.5 * hp.cutoff * gw[i] * r;
         const double damp = std::exp(-(r * r) / (hp.sigma * hp.sigma));
+        if (hp.component == 3) {
+            const double part = hp.partition_erfc ? std::erfc(r / hp.sigma) : damp;
+            const double w0 = 0.5 * hp.cutoff * gw[i];
+            for (int j = 0; j < hp.n_theta; ++j) {
+                const double th = kPi * (2.0 * j / hp.n_theta);
+                const int idx = i * hp.n_theta + j;
+                (*kx)[idx] = r * std::cos(th);
+                (*ky)[idx] = r * std::sin(th);
+                (*q)[idx] = w0 * wt * part;
+            }
+            continue;
+        }
         for (int j = 0; j < hp.n_theta; ++j) {
             // angle 2 pi j / N_theta evaluated as pi * (2j / N_theta) in [0, 2 pi)
             const double th = kPi * (2.0 * j / hp.n_theta);

@@ -33,7 +33,8 @@ struct HostPlan {
     int log_n = -1;       // log2 N when N is a power of two (the periodic solver), else -1
     int kappa = 2;        // requested padding factor
     int n_r = 0, n_theta = 0, n_nodes = 0;
-    int component = 0;          // multiplier -k_a k_b/|k|^2: 0 (a,b) = (x,x), 1 (y,y), 2 (x,y)
+    int component = 0;          // multiplier -k_a k_b/|k|^2: 0 (a,b) = (x,x), 1 (y,y), 2 (x,y); 3: 1/|k|
+    int partition_erfc = 0;     // Coulomb with the partition erfc(|k|/sigma) (else the Gaussian)
     int radial_jacobi = 0;      // Gauss-Jacobi(0, 1) radial rule instead of Gauss-Legendre
     int two_streams = 0;        // node-side chain as separate launches on a second stream
     int gaussian_kernel = 0;    // Greengard-Lee Gaussian gridding instead of the ES kernel

@@ -172,9 +172,28 @@ __device__ __forceinline__ constexpr R tiny_normal() {
 // register layout only slots 0..3 and 12..15 can hold grid rows (see above),
 // so the other inputs are compile-time zeros and the inverse transform's
 // outputs there are never formed.
-// MIXED: the multiplier -kx ky/|k|^2 (a separate instantiation, so that the DS
-// multiplier's code is unchanged by it).
-template <typename R, int LOG, int DIR, int G, bool MIXED>
+// KIND selects the multiplier at compile time (separate instantiations, so that
+// the DS multiplier's code is unchanged by the others):
+//   0  -kx^2/|k|^2 or -ky^2/|k|^2 (P.component 0 / 1)
+//   1  -kx ky/|k|^2
+//   2  1/|k| with the Gaussian partition:  g1 = (1 - e^{-|k|^2/sigma^2}) / |k|
+//   3  1/|k| with the erfc partition:      g1 = erf(|k|/sigma) / |k|
+constexpr int kKindQuadratic = 0, kKindMixed = 1, kKindCoulombGauss = 2, kKindCoulombErfc = 3;
+
+// erf(x)/x for x >= 0, an even entire function: the series 2/sqrt(pi) (1 - x^2/3)
+// below a threshold where the next term (x^4/10) is below the precision's
+// rounding, the library erf above it.
+template <typename R>
+__device__ __forceinline__ R erf_over_x(R x, R x2) {
+    constexpr R two_over_sqrt_pi = R(1.1283791670955126);
+    if constexpr (sizeof(R) == 4) {
+        return x < 1e-2f ? two_over_sqrt_pi * (1.0f - x2 * (1.0f / 3.0f)) : erff(x) / x;
+    } else {
+        return x < 1e-5 ? two_over_sqrt_pi * (1.0 - x2 * (1.0 / 3.0)) : erf(x) / x;
+    }
+}
+
+template <typename R, int LOG, int DIR, int G, int KIND>
 __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
@@ -227,21 +246,32 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
     const bool ycomp = P.component == 1;
     const R fs = static_cast<R>(P.freq_scale);
     const R fx = (mc == HALF) ? R(0) : static_cast<R>(mc) * fs;
+    const R inv_sigma = static_cast<R>(P.inv_sigma);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const R b = gb[i].x;
         const R B = gb[i].y;
-        R num;
-        if constexpr (MIXED) {
-            const int p = tid + NT * i;                 // frequency index along y, FFT order
-            const int ms = (p < HALF) ? p : p - F;      // p = F/2 (Nyquist) -> -F/2
-            num = (p == HALF) ? R(0) : fx * (static_cast<R>(ms) * fs);
+        R gfac;
+        if constexpr (KIND == kKindCoulombGauss) {
+            // (1 - e^{-(a+b)}) / (sigma sqrt(a+b)): 0 * finite at k = 0
+            const R s2 = a + b + tiny_normal<R>();
+            gfac = (A + B - A * B) * (inv_sigma * scale) / sqrt(s2);
+        } else if constexpr (KIND == kKindCoulombErfc) {
+            const R s2 = a + b;
+            gfac = erf_over_x<R>(sqrt(s2), s2) * (inv_sigma * scale);
         } else {
-            num = ycomp ? b : a;
+            R num;
+            if constexpr (KIND == kKindMixed) {
+                const int p = tid + NT * i;                 // frequency index along y, FFT order
+                const int ms = (p < HALF) ? p : p - F;      // p = F/2 (Nyquist) -> -F/2
+                num = (p == HALF) ? R(0) : fx * (static_cast<R>(ms) * fs);
+            } else {
+                num = ycomp ? b : a;
+            }
+            // den = 0 only at k = 0, where num = 0: the quotient is 0 there
+            const R den = a + b + tiny_normal<R>();
+            gfac = -(num * recip(den)) * (A + B - A * B) * scale;
         }
-        // den = 0 only at k = 0, where num = 0: the quotient is 0 there
-        const R den = a + b + tiny_normal<R>();
-        const R gfac = -(num * recip(den)) * (A + B - A * B) * scale;
         v[i] = cscale(v[i], gfac);
     }
     fft_reg<R, LOG, -DIR>(v, lds, tw, tid);

@@ -59,11 +59,11 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
     rows_forward_body<R, LOG, DIR, G>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
-template <typename R, int LOG, int DIR, bool MIXED>
+template <typename R, int LOG, int DIR, int KIND>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P) {
     constexpr int G = lines_per_block<LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    cols_highfreq_body<R, LOG, DIR, G, MIXED>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
+    cols_highfreq_body<R, LOG, DIR, G, KIND>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
 // one window column per block: the Q columns are few, so at small N blocks of
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
     const unsigned b = blockIdx.x;
     if (b >= S.chain) {
         const int c = xcd_logical_block(static_cast<int>(b - S.chain), static_cast<int>(S.total - S.chain));
-        cols_highfreq_body<R, LOG, DIR, G, false>(P, c * G, lds);
+        cols_highfreq_body<R, LOG, DIR, G, kKindQuadratic>(P, c * G, lds);
         return;
     }
     // the chain is the critical path: its waves issue first on a shared SIMD
@@ -171,7 +171,7 @@ hipError_t launch_middle(const DevPlan& P, int dir, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
     constexpr int block = FftShape<LOG>::NT * G;
     const MiddleSplit m = middle_split(P, G);
-    if (!P.sync || P.component == 2 || P.width > kMaxEsWidth) return hipErrorInvalidValue;
+    if (!P.sync || P.component > 1 || P.width > kMaxEsWidth) return hipErrorInvalidValue;
     if (dir < 0) hipLaunchKernelGGL((k_middle<R, LOG, -1>), dim3(m.total), dim3(block), 0, s, P, m);
     else hipLaunchKernelGGL((k_middle<R, LOG, 1>), dim3(m.total), dim3(block), 0, s, P, m);
     return hipGetLastError();
@@ -199,8 +199,14 @@ hipError_t launch_cols_highfreq_dir(const DevPlan& P, hipStream_t s) {
     constexpr int block = FftShape<LOG>::NT * G;
     const int items = (P.n_fine / 2 + 1 + G - 1) / G;
     const int grid = items;   // one work item per block
-    if (P.component == 2) hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P);
-    else hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P);
+    if (P.component == 2)
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindMixed>), dim3(grid), dim3(block), 0, s, P);
+    else if (P.component == 3 && P.partition_erfc)
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombErfc>), dim3(grid), dim3(block), 0, s, P);
+    else if (P.component == 3)
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombGauss>), dim3(grid), dim3(block), 0, s, P);
+    else
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindQuadratic>), dim3(grid), dim3(block), 0, s, P);
     return hipGetLastError();
 }
 

@@ -27,7 +27,9 @@ struct DevPlan {
     int n, n_fine, log_fine;
     int log_n;              // log2 N when N is a power of two (the periodic solver), else -1
     int patch, patch_lo, width, n_nodes;
-    int component;          // 0: -kx^2/|k|^2, 1: -ky^2/|k|^2, 2: -kx ky/|k|^2
+    int component;          // 0: -kx^2/|k|^2, 1: -ky^2/|k|^2, 2: -kx ky/|k|^2, 3: 1/|k| (Coulomb)
+    int partition_erfc;     // Coulomb: partition erfc(|k|/sigma) (else e^{-|k|^2/sigma^2})
+    double inv_sigma;       // 1 / sigma
     int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
     int fused;              // a solve runs the I1 columns and the node-side chain as one launch
     double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index

@@ -32,7 +32,7 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
                 tol: float | None = None, sigma: float | None = None, cutoff: float | None = None,
                 component: str = "x", pad: int = 2, bin: int = 0, sub_nodes: int = 0,
                 autotune: bool = False, radial: str = "legendre", kernel: str = "es",
-                two_streams: bool = False) -> B.PhiParams:
+                two_streams: bool = False, partition: str | None = None) -> B.PhiParams:
     code = _dtype_code(dtype)
     p = B.PhiParams()
     B.check(B.lib().phi_params_default(ctypes.byref(p), int(n), float(h), code))
@@ -43,14 +43,20 @@ def make_params(n: int, h: float, *, dtype=torch.float64, n_r: int = 64, n_theta
     p.pad = int(pad)
     p.sigma = float(sigma) if sigma else 0.0
     p.cutoff = float(cutoff) if cutoff else 0.0
-    comp_flags = {"x": 0, "xx": 0, "y": B.PHI_COMPONENT_Y, "yy": B.PHI_COMPONENT_Y, "xy": B.PHI_COMPONENT_XY}
+    comp_flags = {"x": 0, "xx": 0, "y": B.PHI_COMPONENT_Y, "yy": B.PHI_COMPONENT_Y, "xy": B.PHI_COMPONENT_XY,
+                  "coulomb": B.PHI_COMPONENT_COULOMB}
     if component not in comp_flags:
         raise ValueError(f"component must be one of {sorted(comp_flags)}, got {component!r}")
     if radial not in ("legendre", "jacobi"):
         raise ValueError(f"radial must be 'legendre' or 'jacobi', got {radial!r}")
     if kernel not in ("es", "gaussian"):
         raise ValueError(f"kernel must be 'es' or 'gaussian', got {kernel!r}")
+    if partition not in (None, "erfc", "gauss"):
+        raise ValueError(f"partition must be 'erfc' or 'gauss', got {partition!r}")
+    if partition == "erfc" and component != "coulomb":
+        raise ValueError("the erfc partition is for the Coulomb multiplier only")
     p.flags = (comp_flags[component] | (B.PHI_AUTOTUNE if autotune else 0)
+               | (B.PHI_PARTITION_GAUSS if partition == "gauss" and component == "coulomb" else 0)
                | (B.PHI_RADIAL_JACOBI if radial == "jacobi" else 0)
                | (B.PHI_KERNEL_GAUSSIAN if kernel == "gaussian" else 0)
                | (B.PHI_TWO_STREAMS if two_streams else 0))
@@ -130,7 +136,9 @@ class Plan:
          sigma=None, cutoff=None, component="x", bin=0, sub_nodes=0, autotune=False)
 
     component selects the multiplier: "x" -kx^2/|k|^2 (the DS potential), "y"
-    -ky^2/|k|^2, "xy" -kx ky/|k|^2; radial "legendre" or "jacobi" the radial
+    -ky^2/|k|^2, "xy" -kx ky/|k|^2, "coulomb" 1/|k| (the 2-D Coulomb potential;
+    partition "erfc" (default) or "gauss", the paper's e^{-|k|^2/sigma^2},
+    which leaves a cone in the I1 integrand); radial "legendre" or "jacobi" the radial
     rule; kernel "es" or "gaussian" (Greengard-Lee gridding) the NUFFT kernel.  bin / sub_nodes set the node sort (0: 4
     cells, 64 nodes); autotune=True times the candidates on the device at plan
     time (as eager solves) and keeps the fastest; under graph replay the

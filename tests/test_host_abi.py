@@ -302,3 +302,34 @@ def test_padded_side_is_the_smallest_power_of_two_at_least_kappa_n(lib, n, pad, 
     sigma, c = O.split_constants(O.SplitParams(n=n, h=h, n_r=8, n_theta=8, pad_side=fine))
     assert abs(d["sigma"] - sigma) <= 1e-14 * sigma
     assert abs(d["cutoff"] - c) <= 1e-14 * c
+
+
+@pytest.mark.parametrize("partition", ["erfc", "gauss"])
+def test_plan_nodes_for_coulomb_equal_the_oracle(lib, partition):
+    """The Coulomb weights q_j = (c/2) w_i (2 pi/N_theta) p(r_i) as the plan builds
+    them, against the oracle's rule (Sec. 2.1, Remark)."""
+    import paper_1409_2014_amd.solver as S
+    kx, ky, q = S.host_polar_nodes(n=64, h=0.25, n_r=24, n_theta=48, component="coulomb", partition=partition)
+    okx, oky, oq = O.polar_rule(O.SplitParams(n=64, h=0.25, n_r=24, n_theta=48, component="coulomb",
+                                              partition=partition))
+    a = np.stack([kx, ky, q], axis=1)
+    b = np.stack([okx, oky, oq], axis=1)
+    a = a[np.lexsort((np.round(a[:, 1], 10), np.round(a[:, 0], 10)))]
+    b = b[np.lexsort((np.round(b[:, 1], 10), np.round(b[:, 0], 10)))]
+    assert np.max(np.abs(a - b)) <= 1e-15 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("flags", [
+    lambda B: B.PHI_COMPONENT_COULOMB | B.PHI_COMPONENT_Y,
+    lambda B: B.PHI_COMPONENT_COULOMB | B.PHI_COMPONENT_XY,
+    lambda B: B.PHI_COMPONENT_COULOMB | B.PHI_RADIAL_JACOBI,
+    lambda B: B.PHI_PARTITION_GAUSS,
+])
+def test_coulomb_flag_combinations_are_refused(lib, flags):
+    import ctypes
+    import paper_1409_2014_amd.solver as S
+    from paper_1409_2014_amd import _binding as B
+    p = S.make_params(n=64, h=0.25)
+    p.flags = flags(B)
+    info = B.PhiPlanInfo()
+    assert lib.phi_describe(ctypes.byref(p), ctypes.byref(info)) == 1
