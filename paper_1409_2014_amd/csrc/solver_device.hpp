@@ -337,8 +337,9 @@ __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, c
 // bin of bin x bin window cells, so all their taps fall in the E x E tile
 // (E = bin + w - 1) at the bin's corner.  The block stages that tile of the
 // type-2 window, the nodes' tap values and first-tap offsets in LDS, then
-//   interp:  c_j = sum_{t1,t2} tile[oy+t2][ox+t1] psi_x[t1] psi_y[t2]
-//            (16 lanes per node, fixed reduction tree)        [eq. (16), (12)]
+//   interp:  c_j = sum_{t2} psi_y[t2] sum_{t1} tile[oy+t2][ox+t1] psi_x[t1]
+//            (16 lanes per node, lane t2 sums its tap row, then a fixed
+//            rotate-and-add tree across the 16 lanes)          [eq. (16), (12)]
 //   a_j = q_j h^2 c_j                                          [eq. (12)]
 //   spread:  T[cb][ca] = sum_j a_j psi_x[ca-ox_j] psi_y[cb-oy_j] (one thread per
 //            tile cell, nodes in order, compensated in FP32)   [eq. (15)]
@@ -360,11 +361,35 @@ template <typename R, int WMAX>
 struct NodeLds {
     cpx<R> tile[kTileMax * kTileMax];
     R taps[kMaxNodesPerSub * 2 * WMAX];   // per node: w x-taps, then w y-taps
-    int ox[kMaxNodesPerSub];
-    int oy[kMaxNodesPerSub];
+    int2 off[kMaxNodesPerSub];            // first-tap offset (x, y) in the tile
     double qh[kMaxNodesPerSub];   // q_j h^2
     cpx<R> val[kMaxNodesPerSub];
 };
+
+// Sum over the 16 lanes of each row of the wave (lanes 16r .. 16r + 15), in a
+// fixed order: four rotate-and-add steps (rotations by 8, 4, 2, 1 lanes within
+// the row, DPP row_ror on the vector ALU, no LDS round trip).  Every lane ends
+// with the row's sum; lane 16r's association order is the same in every call.
+template <int CTRL>
+__device__ __forceinline__ float row_rotate(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double row_rotate(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+template <typename R>
+__device__ __forceinline__ R row16_sum(R v) {
+    constexpr int kRowRor = 0x120;   // DPP row_ror:n is kRowRor + n
+    v += row_rotate<kRowRor + 8>(v);
+    v += row_rotate<kRowRor + 4>(v);
+    v += row_rotate<kRowRor + 2>(v);
+    v += row_rotate<kRowRor + 1>(v);
+    return v;
+}
 
 template <typename R>
 __device__ __forceinline__ void kahan_add(R& s, R& c, R v) {
@@ -452,42 +477,61 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
         if (e < n_taps) s.taps[e] = tv[k];
     }
     if (has_node) {
-        s.ox[jn] = cx - x0;
-        s.oy[jn] = cy - y0;
+        s.off[jn] = make_int2(cx - x0, cy - y0);
         if constexpr (MODE == 0) s.qh[jn] = qv * P.h2;
         if constexpr (MODE == 2) s.val[jn] = cv;
     }
+    // the staged tile's rows are ES = E | 1 entries apart: an odd stride puts
+    // the 16 lanes of a node, one tap row each, in distinct LDS banks
+    const int ES = E | 1;
     if constexpr (MODE != 2) {
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int c = threadIdx.x + k * NTH;
-            if (c < E * E) s.tile[c] = tl[k];
+            const int cb = small_div(c, magic_e), ca = c - cb * E;
+            if (c < E * E) s.tile[cb * ES + ca] = tl[k];
         }
     }
     __syncthreads();
     if constexpr (MODE != 2) {
+        static_assert(kLanesPerNode == 16, "one DPP row per node");
         const int lane = threadIdx.x % kLanesPerNode;
-        const unsigned magic_w = small_div_magic(w);
         for (int jj0 = 0; jj0 < count; jj0 += NTH / kLanesPerNode) {
             const int jj = jj0 + threadIdx.x / kLanesPerNode;
             cpx<R> acc = {R(0), R(0)};
             if (jj < count) {
-                const int ox = s.ox[jj], oy = s.oy[jj];
+                const int2 o = s.off[jj];
                 const R* tj = s.taps + jj * w2;
-                for (int t = lane; t < w * w; t += kLanesPerNode) {
-                    const int t2 = small_div(t, magic_w);
-                    const int t1 = t - t2 * w;
-                    const R k = tj[t1] * tj[w + t2];
-                    const cpx<R> b = s.tile[(oy + t2) * E + ox + t1];
-                    acc.x += b.x * k;
-                    acc.y += b.y * k;
+                // lane t2 (and t2 + 16 for the widest Gaussian kernels) sums one
+                // tap row: psi_y[t2] sum_t1 tile[oy+t2][ox+t1] psi_x[t1], four
+                // taps at a time with clamped indices and zero weights past w,
+                // so the loads of a chunk issue together without branches
+                for (int t2 = lane; t2 < w; t2 += kLanesPerNode) {
+                    const cpx<R>* trow = s.tile + (o.y + t2) * ES + o.x;
+                    cpx<R> row = {R(0), R(0)};
+                    for (int t0 = 0; t0 < w; t0 += 4) {
+                        R k[4];
+                        cpx<R> b[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int t1 = min(t0 + u, w - 1);
+                            const R kv = tj[t1];
+                            k[u] = (t0 + u < w) ? kv : R(0);
+                            b[u] = trow[t1];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            row.x += b[u].x * k[u];
+                            row.y += b[u].y * k[u];
+                        }
+                    }
+                    const R ky = tj[w + t2];
+                    acc.x += row.x * ky;
+                    acc.y += row.y * ky;
                 }
             }
-#pragma unroll
-            for (int off = kLanesPerNode / 2; off > 0; off >>= 1) {
-                acc.x += __shfl_xor(acc.x, off, kLanesPerNode);
-                acc.y += __shfl_xor(acc.y, off, kLanesPerNode);
-            }
+            acc.x = row16_sum(acc.x);
+            acc.y = row16_sum(acc.y);
             if (jj < count && lane == 0) {
                 const int j = first + jj;
                 if constexpr (MODE == 1) {
@@ -521,8 +565,9 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
                 const int jj = j0 + u;
                 const bool valid = jj < j_hi;
                 const int jc = valid ? jj : j_lo;
-                const int t1 = ca - s.ox[jc];
-                const int t2 = cb - s.oy[jc];
+                const int2 o = s.off[jc];
+                const int t1 = ca - o.x;
+                const int t2 = cb - o.y;
                 const bool in = valid && static_cast<unsigned>(t1) < static_cast<unsigned>(w) &&
                                 static_cast<unsigned>(t2) < static_cast<unsigned>(w);
                 const R* tj = s.taps + jc * w2;
