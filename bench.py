@@ -247,7 +247,8 @@ def batch_leg(args, torch, ps, W) -> dict:
     h = 1/32 (seed 1), FP32, the default node sort (bin 4, 64 nodes per
     subproblem: under graph replay it beat the plan-time autotuner's picks,
     2.27 against 2.39 ms per batch), one launch per stage over all
-    members, replayed from a captured graph."""
+    members (the node-side launches on a second stream beside the I1
+    columns), replayed from a captured graph."""
     members = W.batch_members(seed=1, count=256)
     params = [dict(n=n, h=2 * half / n, n_r=N_R, n_theta=N_THETA, tol=TOL32)
               for n, half, _ in members]
@@ -269,14 +270,14 @@ def batch_leg(args, torch, ps, W) -> dict:
     step_s = t / k
     alg = sum(solve_alg_bytes(n, 4) for n, _, _ in members)
     # algorithmic bytes of each batched launch: the members' single-solve figures summed
-    nbytes = {"rows_forward": 0, "cols": 0, "nodes": 0, "cols_type1": 0, "rows_inverse": 0}
+    nbytes = {"rows_forward": 0, "cols_type2": 0, "cols": 0, "nodes": 0, "cols_type1": 0, "rows_inverse": 0}
     sizes = {}
     for i, (n, _, _) in enumerate(members):
         info = bp.member_info(i)
         kb = kernel_bytes(info, 4)
-        for name in ("rows_forward", "nodes", "cols_type1", "rows_inverse"):
+        for name in ("rows_forward", "cols_type2", "nodes", "cols_type1", "rows_inverse"):
             nbytes[name] += kb[name]
-        nbytes["cols"] += kb["cols_highfreq"] + kb["cols_type2"]
+        nbytes["cols"] += kb["cols_highfreq"]
         if n not in sizes:
             sizes[n] = {"members": 0, "bin": info["bin"], "sub_nodes": info["sub_nodes"]}
         sizes[n]["members"] += 1

@@ -416,7 +416,7 @@ phi_status autotune(const phi_params* p, hipStream_t s, phi_params* best) {
 
 hipError_t enqueue_any(phi_plan_t plan, phi::Stage stage, const void* in, void* out, int adjoint, hipStream_t s,
                        phi::KernelTimer* timer) {
-    if (plan->n_members > 0) return phi::enqueue_batch(plan->batch, in, out, adjoint, s, timer);
+    if (plan->n_members > 0) return phi::enqueue_batch(plan->batch, plan->streams, in, out, adjoint, s, timer);
     return phi::enqueue(plan->dev, plan->streams, stage, in, out, adjoint, s, timer);
 }
 
@@ -612,13 +612,13 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             return plan->sets[plan->member_set[a]].n > plan->sets[plan->member_set[b]].n;
         });
-        std::vector<phi::WorkItem> rows, cols, cols_mixed, nodes, cols1;
+        std::vector<phi::WorkItem> rows, cols, cols_t2, cols_mixed, nodes, cols1;
         for (int i : order) {
             const phi::HostPlan& hp = plan->sets[plan->member_set[i]];
             const int g = phi::batch_lines(hp.log_fine);
             push_items(&rows, i, 0, hp.n, g);
             push_items(hp.component == 2 ? &cols_mixed : &cols, i, 0, hp.n_fine / 2 + 1, g);
-            push_items(&cols, i, 1, hp.patch, g);
+            push_items(&cols_t2, i, 1, hp.patch, g);
             push_items(&nodes, i, 0, hp.n_sub, 1);
             push_items(&cols1, i, 0, hp.patch, g);
         }
@@ -633,6 +633,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         const Part p_off = L.take(sizeof(int64_t) * (count + 1));
         const Part p_rows = L.take(sizeof(phi::WorkItem) * rows.size());
         const Part p_cols = L.take(sizeof(phi::WorkItem) * cols.size());
+        const Part p_cols_t2 = L.take(sizeof(phi::WorkItem) * cols_t2.size());
         const Part p_cols_mixed = L.take(sizeof(phi::WorkItem) * cols_mixed.size());
         const Part p_nodes = L.take(sizeof(phi::WorkItem) * nodes.size());
         const Part p_cols1 = L.take(sizeof(phi::WorkItem) * cols1.size());
@@ -661,6 +662,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         if (e == hipSuccess) e = up(p_off, plan->offsets.data());
         if (e == hipSuccess) e = up(p_rows, rows.data());
         if (e == hipSuccess) e = up(p_cols, cols.data());
+        if (e == hipSuccess) e = up(p_cols_t2, cols_t2.data());
         if (e == hipSuccess) e = up(p_cols_mixed, cols_mixed.data());
         if (e == hipSuccess) e = up(p_nodes, nodes.data());
         if (e == hipSuccess) e = up(p_cols1, cols1.data());
@@ -676,16 +678,24 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         b.offsets = reinterpret_cast<const int64_t*>(base + p_off.off);
         b.rows = reinterpret_cast<const phi::WorkItem*>(base + p_rows.off);
         b.cols = reinterpret_cast<const phi::WorkItem*>(base + p_cols.off);
+        b.cols_t2 = reinterpret_cast<const phi::WorkItem*>(base + p_cols_t2.off);
         b.cols_mixed = reinterpret_cast<const phi::WorkItem*>(base + p_cols_mixed.off);
         b.nodes = reinterpret_cast<const phi::WorkItem*>(base + p_nodes.off);
         b.cols1 = reinterpret_cast<const phi::WorkItem*>(base + p_cols1.off);
         b.n_rows = static_cast<int>(rows.size());
         b.n_cols = static_cast<int>(cols.size());
+        b.n_cols_t2 = static_cast<int>(cols_t2.size());
         b.n_cols_mixed = static_cast<int>(cols_mixed.size());
         for (const phi::HostPlan& hp : plan->sets) b.wide_kernel |= (hp.width > phi::kMaxEsWidth) ? 1 : 0;
         b.n_nodes = static_cast<int>(nodes.size());
         b.n_cols1 = static_cast<int>(cols1.size());
         plan->host = plan->sets[plan->member_set[0]];
+        phi_status sst = create_streams(plan);
+        if (sst != PHI_OK) {
+            release(plan);
+            delete plan;
+            return sst;
+        }
         return register_plan(plan, out);
     } catch (const std::bad_alloc&) {
         if (plan) {

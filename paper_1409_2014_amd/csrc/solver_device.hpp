@@ -61,7 +61,9 @@ constexpr int rows_per_block() {
 // the Q window frequencies (the type-2 row window) to TT.  Rows at or beyond
 // N (the last block of a grid whose side G does not divide) transform zeros
 // and store nothing.
-template <typename R, int LOG, int DIR, int G>
+// EXACT: the grid side is F/2 (a power of two at kappa = 2), so every bound
+// below is a compile-time constant (the general form tests each slot and row).
+template <typename R, int LOG, int DIR, int G, bool EXACT>
 __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __restrict__ rho, int row0,
                                                   cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
@@ -69,17 +71,17 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
     constexpr int HALF = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int LP = lds_group_stride(F);
-    const int n = P.n;
+    const int n = EXACT ? F / 2 : P.n;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * LP;
     const cpx<R>* tw = static_cast<const cpx<R>*>(P.twr);
-    const bool row_ok = row0 + g < n;
+    const bool row_ok = EXACT || row0 + g < n;
     const int row = row_ok ? row0 + g : n - 1;
     const double dy = P.deconv[row];
     // grid column n1 = position + N/2 (n' >= 0) or position - F + N/2 (n' < 0):
     // one base address per array serves every slot
-    const int half = n >> 1;
+    const int half = EXACT ? F / 4 : (n >> 1);
     const R* src = rho + static_cast<size_t>(row) * n + half;
     const double* dx = P.deconv + half;
     cpx<R> v[16];
@@ -116,7 +118,7 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
         const cpx<R> a = l[lds_pad(m)];
         const cpx<R> b = l[lds_pad((F - m) & (F - 1))];
         // transform of the real part: X[m] = (Z[m] + conj Z[-m]) / 2
-        if (idx < ITEMS && row0 + gg < n)
+        if (idx < ITEMS && (EXACT || row0 + gg < n))
             xt[static_cast<size_t>(m) * P.col_stride + row0 + gg] = {R(0.5) * (a.x + b.x), R(0.5) * (a.y - b.y)};
     }
     cpx<R>* tt = static_cast<cpx<R>*>(P.tt);
@@ -128,7 +130,7 @@ __device__ __forceinline__ void rows_forward_body(const DevPlan& P, const R* __r
         const cpx<R> a = l[lds_pad(lf & (F - 1))];
         const cpx<R> b = l[lds_pad((-lf) & (F - 1))];
         // transform of the imaginary part: (Z[l] - conj Z[-l]) / (2i)
-        if (row0 + gg < n)
+        if (EXACT || row0 + gg < n)
             tt[static_cast<size_t>(i) * P.col_stride + row0 + gg] = {R(0.5) * (a.y + b.y), R(-0.5) * (a.x - b.x)};
     }
 }
@@ -193,13 +195,13 @@ __device__ __forceinline__ R erf_over_x(R x, R x2) {
     }
 }
 
-template <typename R, int LOG, int DIR, int G, int KIND>
+template <typename R, int LOG, int DIR, int G, int KIND, bool EXACT>
 __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
     constexpr int HALF = F / 2;
     constexpr int NT = Sh::NT;
-    const int n = P.n;
+    const int n = EXACT ? F / 2 : P.n;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * lds_group_stride(F);
@@ -210,7 +212,7 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
     cpx<R>* col = static_cast<cpx<R>*>(P.xt) + static_cast<size_t>(active ? m1 : HALF) * P.col_stride;
     // rows n' >= 0 at positions [0, N/2), n' < 0 at [F - N/2, F): one base
     // address (row N/2 - position 0) serves every slot
-    const int half = n >> 1;
+    const int half = EXACT ? F / 4 : (n >> 1);
     const cpx<R>* base = col + half;
     cpx<R> v[16];
 #pragma unroll
@@ -292,7 +294,7 @@ __device__ __forceinline__ void cols_highfreq_body(const DevPlan& P, int m1_base
 // ---------------------------------------------------------------------------
 // cols_type2: FFT along y of the type-2 row window, keep the Q window rows
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int DIR, int G>
+template <typename R, int LOG, int DIR, int G, bool EXACT>
 __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
@@ -306,7 +308,7 @@ __device__ __forceinline__ void cols_type2_body(const DevPlan& P, int i1_base, c
     const bool active = i1 < q;
     const cpx<R>* col = static_cast<const cpx<R>*>(P.tt) + static_cast<size_t>(active ? i1 : 0) * P.col_stride;
     const cpx<R> zero = {R(0), R(0)};
-    const int half = P.n >> 1;
+    const int half = EXACT ? F / 4 : (P.n >> 1);
     const cpx<R>* base = col + half;
     cpx<R> v[16];
 #pragma unroll
@@ -603,7 +605,7 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
 // grid size.  Column c is staged in group c's buffer; group g transforms
 // column g % COLS (with COLS = 1 every group runs the same transform, which the
 // block's barriers need anyway) and groups g < COLS store.
-template <typename R, int LOG, int DIR, int G, int COLS>
+template <typename R, int LOG, int DIR, int G, int COLS, bool EXACT>
 __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
     constexpr int F = Sh::F;
@@ -667,7 +669,7 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     if (active && g < COLS) {
-        const int half = P.n >> 1;
+        const int half = EXACT ? F / 4 : (P.n >> 1);
         cpx<R>* u = static_cast<cpx<R>*>(P.u) + static_cast<size_t>(half) * q + i1;
         const double* dy = P.deconv + half;
 #pragma unroll
@@ -696,7 +698,7 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
 // real part and Re(type-1 field) / d(n1) in the imaginary part.  Rows at or
 // beyond N (the last block of a grid whose side G does not divide) transform
 // zeros and store nothing.
-template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2, int G>
+template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2, int G, bool EXACT>
 __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restrict__ out, int row0,
                                                   cpx<R>* lds_all) {
     using Sh = FftShape<LOG>;
@@ -704,7 +706,7 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
     constexpr int HALF = F / 2;
     constexpr int NT = Sh::NT;
     constexpr int LP = lds_group_stride(F);
-    const int n = P.n;
+    const int n = EXACT ? F / 2 : P.n;
     const int g = threadIdx.x / NT;
     const int tid = threadIdx.x - g * NT;
     cpx<R>* lds = lds_all + g * LP;
@@ -723,7 +725,7 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
         const int idc = idx < ITEMS ? idx : ITEMS - 1;
         const int gg = idc % G;
         const int m = idc / G;
-        const int r = row0 + gg < n ? row0 + gg : n - 1;   // rows past N read row N - 1, never stored
+        const int r = (EXACT || row0 + gg < n) ? row0 + gg : n - 1;   // rows past N read row N - 1, never stored
         cpx<R> x = {R(0), R(0)};
         if constexpr (USE_I1) x = xt[static_cast<size_t>(m) * P.col_stride + r];
         cpx<R> hh = {R(0), R(0)};
@@ -751,8 +753,8 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
-    if (row0 + g < n) {
-        const int half = n >> 1;
+    if (EXACT || row0 + g < n) {
+        const int half = EXACT ? F / 4 : (n >> 1);
         R* dst = out + static_cast<size_t>(row0 + g) * n + half;
         const double* dx = P.deconv + half;
 #pragma unroll

@@ -49,21 +49,21 @@ namespace phi {
 // ---------------------------------------------------------------------------
 // Single-solve kernels: one work item per block
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int DIR>
+template <typename R, int LOG, int DIR, bool EXACT>
 __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_forward(
     DevPlan P, const R* __restrict__ rho) {
     constexpr int G = rows_per_block<R, LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
     // the counters of the solve's middle launch start from zero
     if (blockIdx.x == 0 && threadIdx.x == 0 && P.sync) reset_counters(P.sync);
-    rows_forward_body<R, LOG, DIR, G>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
+    rows_forward_body<R, LOG, DIR, G, EXACT>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
-template <typename R, int LOG, int DIR, int KIND>
+template <typename R, int LOG, int DIR, int KIND, bool EXACT>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_highfreq(DevPlan P) {
     constexpr int G = lines_per_block<LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    cols_highfreq_body<R, LOG, DIR, G, KIND>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
+    cols_highfreq_body<R, LOG, DIR, G, KIND, EXACT>(P, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
 // one window column per block: the Q columns are few, so at small N blocks of
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
 template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__(FftShape<LOG>::NT) void k_cols_type2(DevPlan P) {
     __shared__ cpx<R> lds_all[lds_group_stride(1 << LOG)];
-    cols_type2_body<R, LOG, DIR, 1>(P, blockIdx.x, lds_all);
+    cols_type2_body<R, LOG, DIR, 1, false>(P, blockIdx.x, lds_all);
 }
 
 template <typename R, int MODE, int WMAX>
@@ -85,16 +85,16 @@ template <typename R, int LOG, int DIR>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_cols_type1(DevPlan P) {
     constexpr int G = lines_per_block<LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    cols_type1_body<R, LOG, DIR, G, 1>(P, blockIdx.x, lds_all);
+    cols_type1_body<R, LOG, DIR, G, 1, false>(P, blockIdx.x, lds_all);
 }
 
-template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2>
+template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2, bool EXACT>
 __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_inverse(
     DevPlan P, R* __restrict__ out) {
     constexpr int G = rows_per_block<R, LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    rows_inverse_body<R, LOG, DIR, USE_I1, USE_I2, G>(P, out, xcd_logical_block(blockIdx.x, gridDim.x) * G,
-                                                      lds_all);
+    rows_inverse_body<R, LOG, DIR, USE_I1, USE_I2, G, EXACT>(P, out, xcd_logical_block(blockIdx.x, gridDim.x) * G,
+                                                             lds_all);
 }
 
 // Blocks of the middle launch by index: [0, t2_end) type-2 window columns,
@@ -112,7 +112,7 @@ constexpr size_t middle_lds_bytes() {
     return fft > node ? fft : node;
 }
 
-template <typename R, int LOG, int DIR>
+template <typename R, int LOG, int DIR, bool EXACT>
 __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_middle(DevPlan P, MiddleSplit S) {
     constexpr int G = lines_per_block<LOG>();
     constexpr int NTH = FftShape<LOG>::NT * G;
@@ -121,13 +121,13 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
     const unsigned b = blockIdx.x;
     if (b >= S.chain) {
         const int c = xcd_logical_block(static_cast<int>(b - S.chain), static_cast<int>(S.total - S.chain));
-        cols_highfreq_body<R, LOG, DIR, G, kKindQuadratic>(P, c * G, lds);
+        cols_highfreq_body<R, LOG, DIR, G, kKindQuadratic, EXACT>(P, c * G, lds);
         return;
     }
     // the chain is the critical path: its waves issue first on a shared SIMD
     __builtin_amdgcn_s_setprio(3);
     if (b < S.t2_end) {
-        cols_type2_body<R, LOG, DIR, G>(P, static_cast<int>(b) * G, lds);
+        cols_type2_body<R, LOG, DIR, G, false>(P, static_cast<int>(b) * G, lds);
         signal_done(P.sync, kSyncT2Done);
     } else if (b < S.nodes_end) {
         wait_count(P.sync, kSyncT2Done, S.t2_end);
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
         signal_done(P.sync, kSyncNodesDone);
     } else {
         wait_count(P.sync, kSyncNodesDone, S.nodes_end - S.t2_end);
-        cols_type1_body<R, LOG, -DIR, G, 1>(P, static_cast<int>(b - S.nodes_end), lds);
+        cols_type1_body<R, LOG, -DIR, G, 1, false>(P, static_cast<int>(b - S.nodes_end), lds);
     }
 }
 
@@ -158,7 +158,7 @@ template <typename R, int LOG>
 hipError_t capacity_middle(const DevPlan& P, int* blocks) {
     constexpr int block = FftShape<LOG>::NT * lines_per_block<LOG>();
     int per_cu = 0, cus = 0, dev = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_middle<R, LOG, -1>, block, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_middle<R, LOG, -1, false>, block, 0);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     *blocks = per_cu * cus;
@@ -172,8 +172,11 @@ hipError_t launch_middle(const DevPlan& P, int dir, hipStream_t s) {
     constexpr int block = FftShape<LOG>::NT * G;
     const MiddleSplit m = middle_split(P, G);
     if (!P.sync || P.component > 1 || P.width > kMaxEsWidth) return hipErrorInvalidValue;
-    if (dir < 0) hipLaunchKernelGGL((k_middle<R, LOG, -1>), dim3(m.total), dim3(block), 0, s, P, m);
-    else hipLaunchKernelGGL((k_middle<R, LOG, 1>), dim3(m.total), dim3(block), 0, s, P, m);
+    const bool exact = 2 * P.n == P.n_fine;
+    if (dir < 0 && exact) hipLaunchKernelGGL((k_middle<R, LOG, -1, true>), dim3(m.total), dim3(block), 0, s, P, m);
+    else if (dir < 0) hipLaunchKernelGGL((k_middle<R, LOG, -1, false>), dim3(m.total), dim3(block), 0, s, P, m);
+    else if (exact) hipLaunchKernelGGL((k_middle<R, LOG, 1, true>), dim3(m.total), dim3(block), 0, s, P, m);
+    else hipLaunchKernelGGL((k_middle<R, LOG, 1, false>), dim3(m.total), dim3(block), 0, s, P, m);
     return hipGetLastError();
 }
 
@@ -183,7 +186,8 @@ hipError_t launch_rows_forward_dir(const DevPlan& P, const R* src, hipStream_t s
     constexpr int block = FftShape<LOG>::NT * G;
     const int items = (P.n + G - 1) / G;
     const int grid = items;   // one work item per block
-    hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR>), dim3(grid), dim3(block), 0, s, P, src);
+    if (2 * P.n == P.n_fine) hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P, src);
+    else hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P, src);
     return hipGetLastError();
 }
 
@@ -199,14 +203,22 @@ hipError_t launch_cols_highfreq_dir(const DevPlan& P, hipStream_t s) {
     constexpr int block = FftShape<LOG>::NT * G;
     const int items = (P.n_fine / 2 + 1 + G - 1) / G;
     const int grid = items;   // one work item per block
-    if (P.component == 2)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindMixed>), dim3(grid), dim3(block), 0, s, P);
+    // the exact-bounds variants are taken wherever the batched kernels take them
+    // (the DS, y and mixed multipliers), so a batch member and its single plan
+    // run the same code; the Coulomb multipliers use the general bounds only
+    const bool exact = 2 * P.n == P.n_fine;
+    if (P.component == 2 && exact)
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindMixed, true>), dim3(grid), dim3(block), 0, s, P);
+    else if (P.component == 2)
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindMixed, false>), dim3(grid), dim3(block), 0, s, P);
     else if (P.component == 3 && P.partition_erfc)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombErfc>), dim3(grid), dim3(block), 0, s, P);
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombErfc, false>), dim3(grid), dim3(block), 0, s, P);
     else if (P.component == 3)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombGauss>), dim3(grid), dim3(block), 0, s, P);
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombGauss, false>), dim3(grid), dim3(block), 0, s, P);
+    else if (exact)
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindQuadratic, true>), dim3(grid), dim3(block), 0, s, P);
     else
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindQuadratic>), dim3(grid), dim3(block), 0, s, P);
+        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindQuadratic, false>), dim3(grid), dim3(block), 0, s, P);
     return hipGetLastError();
 }
 
@@ -238,7 +250,11 @@ hipError_t launch_rows_inverse_parts(const DevPlan& P, R* dst, hipStream_t s) {
     constexpr int block = FftShape<LOG>::NT * G;
     const int items = (P.n + G - 1) / G;
     const int grid = items;   // one work item per block
-    hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2>), dim3(grid), dim3(block), 0, s, P, dst);
+    // the full solve (I1 and I2) has an exact-bounds variant; the stage variants use the general one
+    if (I1 && I2 && 2 * P.n == P.n_fine)
+        hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2, I1 && I2>), dim3(grid), dim3(block), 0, s, P, dst);
+    else
+        hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2, false>), dim3(grid), dim3(block), 0, s, P, dst);
     return hipGetLastError();
 }
 

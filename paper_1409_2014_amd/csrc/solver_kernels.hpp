@@ -130,11 +130,12 @@ struct BatchDev {
     const DevPlan* members = nullptr;
     const int64_t* offsets = nullptr;
     const WorkItem* rows = nullptr;    // rows_forward and rows_inverse
-    const WorkItem* cols = nullptr;    // I1 columns and type-2 window columns
+    const WorkItem* cols = nullptr;    // I1 spectrum columns
+    const WorkItem* cols_t2 = nullptr; // type-2 window columns
     const WorkItem* cols_mixed = nullptr;  // I1 columns of the members with the mixed multiplier
     const WorkItem* nodes = nullptr;   // subproblems
     const WorkItem* cols1 = nullptr;   // type-1 window columns
-    int n_rows = 0, n_cols = 0, n_cols_mixed = 0, n_nodes = 0, n_cols1 = 0;
+    int n_rows = 0, n_cols = 0, n_cols_t2 = 0, n_cols_mixed = 0, n_nodes = 0, n_cols1 = 0;
     int wide_kernel = 0;               // some member's kernel is wider than kMaxEsWidth
 };
 
@@ -145,8 +146,9 @@ size_t scratch_capacity();
 hipError_t scratch_region(int device, void** ptr);
 
 // Enqueue one solve (adjoint = 0) or transposed solve (adjoint = 1) of every
-// member on stream s: five launches in stream order.
-hipError_t enqueue_batch(const BatchDev& B, const void* in, void* out, int adjoint, hipStream_t s,
-                         KernelTimer* timer = nullptr);
+// member on stream s (the node-side launches on ss.side, joined before the
+// last launch; on s alone when ss.side is null).
+hipError_t enqueue_batch(const BatchDev& B, const StreamSet& ss, const void* in, void* out, int adjoint,
+                         hipStream_t s, KernelTimer* timer = nullptr);
 
 }  // namespace phi
