@@ -55,11 +55,11 @@ VALU_PEAK_PUBLISHED_F32 = 157.3
 # until the counters are taken again.
 TRAFFIC_RECORD = {
     "kernel": "cols_highfreq",
-    "fetch_kib": 16750.1, "write_kib": 32784.0,
-    "copy_fetch_kib": 131088.8, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
-    "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
+    "fetch_kib": 16750.6, "write_kib": 32784.0,
+    "copy_fetch_kib": 131088.75, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "sources": ("block_sync.hpp", "device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "840e21fffd7d67c7fd61d14fce3913d97903fc1d07c4d3fd49d365ef01668752",
+    "sha256": "a1518494a89dd717d5ebc29d576bfd8ff168789e4ba2bc0757c8735de1e95f75",
 }
 
 N = 2048
@@ -564,9 +564,12 @@ def main() -> int:
     nbytes = kernel_bytes(plan32.info, 4)
     kernels = event_kernels(lambda: plan32.solve_timed(rho32_dev, out32), k, nbytes)
     kernels_split = event_kernels(lambda: plan32s.solve_timed(rho32_dev, out32), k, nbytes)
-    dominant = max(kernels, key=lambda name: kernels[name]["avg_us"])
-    achieved = kernels[dominant]["gbs"]
+    # the roofline object covers the longest of the transform kernels (the ones with a
+    # flop count); under a profiler's counter passes a node-side kernel can be the
+    # longest launch, and it has no flop roof
     flops32 = kernel_flops(plan32.info)
+    dominant = max((name for name in kernels if name in flops32), key=lambda name: kernels[name]["avg_us"])
+    achieved = kernels[dominant]["gbs"]
     for name, kv in kernels.items():
         if name in flops32:
             kv["tflops"] = round(flops32[name] / (kv["avg_us"] * 1e-6) / 1e12, 2)

@@ -17,6 +17,7 @@
 //   cols           I1 spectrum columns (g1 multiplier and inverse), then those
 //                  of the members with the mixed multiplier
 //   after both:    rows_inverse, every member's rows         (-DIR)
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "solver_device.hpp"
@@ -140,10 +141,10 @@ hipError_t enqueue_batch_dir(const BatchDev& B, const StreamSet& ss, const void*
                              KernelTimer* timer) {
     const dim3 blk(kBatchThreads);
     PHI_LAUNCH_B("rows_forward", B.n_rows, s,
-                 hipLaunchKernelGGL((kb_rows_forward<R, DIR>), dim3(B.n_rows), blk, 0, s, B,
+                 PHI_LAUNCH((kb_rows_forward<R, DIR>), dim3(B.n_rows), blk, 0, s, B,
                                     static_cast<const R*>(in)));
     PHI_LAUNCH_B("cols_type2", B.n_cols_t2, s,
-                 hipLaunchKernelGGL((kb_cols<R, DIR, false>), dim3(B.n_cols_t2), blk, 0, s, B, B.cols_t2));
+                 PHI_LAUNCH((kb_cols<R, DIR, false>), dim3(B.n_cols_t2), blk, 0, s, B, B.cols_t2));
     hipStream_t side = ss.side ? ss.side : s;
     if (ss.side) {
         PHI_TRY_B(hipEventRecord(ss.fork, s));
@@ -151,20 +152,20 @@ hipError_t enqueue_batch_dir(const BatchDev& B, const StreamSet& ss, const void*
     }
     if (B.wide_kernel)
         PHI_LAUNCH_B("nodes", B.n_nodes, side,
-                     hipLaunchKernelGGL((kb_nodes<R, kMaxKernelWidth>), dim3(B.n_nodes), blk, 0, side, B));
+                     PHI_LAUNCH((kb_nodes<R, kMaxKernelWidth>), dim3(B.n_nodes), blk, 0, side, B));
     else
         PHI_LAUNCH_B("nodes", B.n_nodes, side,
-                     hipLaunchKernelGGL((kb_nodes<R, kMaxEsWidth>), dim3(B.n_nodes), blk, 0, side, B));
+                     PHI_LAUNCH((kb_nodes<R, kMaxEsWidth>), dim3(B.n_nodes), blk, 0, side, B));
     PHI_LAUNCH_B("cols_type1", B.n_cols1, side,
-                 hipLaunchKernelGGL((kb_cols_type1<R, -DIR>), dim3(B.n_cols1), blk, 0, side, B));
+                 PHI_LAUNCH((kb_cols_type1<R, -DIR>), dim3(B.n_cols1), blk, 0, side, B));
     if (ss.side) PHI_TRY_B(hipEventRecord(ss.join, side));
     PHI_LAUNCH_B("cols", B.n_cols, s,
-                 hipLaunchKernelGGL((kb_cols<R, DIR, false>), dim3(B.n_cols), blk, 0, s, B, B.cols));
+                 PHI_LAUNCH((kb_cols<R, DIR, false>), dim3(B.n_cols), blk, 0, s, B, B.cols));
     PHI_LAUNCH_B("cols_mixed", B.n_cols_mixed, s,
-                 hipLaunchKernelGGL((kb_cols<R, DIR, true>), dim3(B.n_cols_mixed), blk, 0, s, B, B.cols_mixed));
+                 PHI_LAUNCH((kb_cols<R, DIR, true>), dim3(B.n_cols_mixed), blk, 0, s, B, B.cols_mixed));
     if (ss.side) PHI_TRY_B(hipStreamWaitEvent(s, ss.join, 0));
     PHI_LAUNCH_B("rows_inverse", B.n_rows, s,
-                 hipLaunchKernelGGL((kb_rows_inverse<R, -DIR>), dim3(B.n_rows), blk, 0, s, B, static_cast<R*>(out)));
+                 PHI_LAUNCH((kb_rows_inverse<R, -DIR>), dim3(B.n_rows), blk, 0, s, B, static_cast<R*>(out)));
     return hipSuccess;
 }
 

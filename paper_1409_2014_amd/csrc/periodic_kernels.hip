@@ -17,6 +17,7 @@
 //   per_rows_inverse   per pair of rows: the Hermitian extensions of both half
 //                      spectra combined as X_a + i X_b, one inverse FFT:
 //                      Phi_a = Re, Phi_b = Im.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "solver_device.hpp"
@@ -163,22 +164,22 @@ hipError_t periodic_log(const DevPlan& P, const void* in, void* out, hipStream_t
     constexpr int NT = FftShape<LOG>::NT;
     hipError_t e = mark_kernel(timer, "per_rows_forward", false, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_per_rows_forward<R, LOG>), dim3(N / 2 / GR), dim3(NT * GR), 0, s, P,
+    PHI_LAUNCH((k_per_rows_forward<R, LOG>), dim3(N / 2 / GR), dim3(NT * GR), 0, s, P,
                        static_cast<const R*>(in));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_rows_forward", true, s)) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_cols", false, s)) != hipSuccess) return e;
     const int col_blocks = (N / 2 + 1 + GC - 1) / GC;
     if (P.component == 2)
-        hipLaunchKernelGGL((k_per_cols<R, LOG, 2>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
+        PHI_LAUNCH((k_per_cols<R, LOG, 2>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
     else if (P.component == 1)
-        hipLaunchKernelGGL((k_per_cols<R, LOG, 1>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
+        PHI_LAUNCH((k_per_cols<R, LOG, 1>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
     else
-        hipLaunchKernelGGL((k_per_cols<R, LOG, 0>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
+        PHI_LAUNCH((k_per_cols<R, LOG, 0>), dim3(col_blocks), dim3(NT * GC), 0, s, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_cols", true, s)) != hipSuccess) return e;
     if ((e = mark_kernel(timer, "per_rows_inverse", false, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_per_rows_inverse<R, LOG>), dim3(N / 2 / GR), dim3(NT * GR), 0, s, P, static_cast<R*>(out));
+    PHI_LAUNCH((k_per_rows_inverse<R, LOG>), dim3(N / 2 / GR), dim3(NT * GR), 0, s, P, static_cast<R*>(out));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return mark_kernel(timer, "per_rows_inverse", true, s);
 }

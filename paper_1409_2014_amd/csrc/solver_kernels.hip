@@ -39,6 +39,7 @@
 // (block_sync.hpp states why every wait ends).  A solve is then three launches
 // on one stream: rows_forward (which also zeroes the chain's counters), middle,
 // rows_inverse.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "solver_device.hpp"
@@ -173,10 +174,10 @@ hipError_t launch_middle(const DevPlan& P, int dir, hipStream_t s) {
     const MiddleSplit m = middle_split(P, G);
     if (!P.sync || P.component > 1 || P.width > kMaxEsWidth) return hipErrorInvalidValue;
     const bool exact = 2 * P.n == P.n_fine;
-    if (dir < 0 && exact) hipLaunchKernelGGL((k_middle<R, LOG, -1, true>), dim3(m.total), dim3(block), 0, s, P, m);
-    else if (dir < 0) hipLaunchKernelGGL((k_middle<R, LOG, -1, false>), dim3(m.total), dim3(block), 0, s, P, m);
-    else if (exact) hipLaunchKernelGGL((k_middle<R, LOG, 1, true>), dim3(m.total), dim3(block), 0, s, P, m);
-    else hipLaunchKernelGGL((k_middle<R, LOG, 1, false>), dim3(m.total), dim3(block), 0, s, P, m);
+    if (dir < 0 && exact) PHI_LAUNCH((k_middle<R, LOG, -1, true>), dim3(m.total), dim3(block), 0, s, P, m);
+    else if (dir < 0) PHI_LAUNCH((k_middle<R, LOG, -1, false>), dim3(m.total), dim3(block), 0, s, P, m);
+    else if (exact) PHI_LAUNCH((k_middle<R, LOG, 1, true>), dim3(m.total), dim3(block), 0, s, P, m);
+    else PHI_LAUNCH((k_middle<R, LOG, 1, false>), dim3(m.total), dim3(block), 0, s, P, m);
     return hipGetLastError();
 }
 
@@ -186,8 +187,8 @@ hipError_t launch_rows_forward_dir(const DevPlan& P, const R* src, hipStream_t s
     constexpr int block = FftShape<LOG>::NT * G;
     const int items = (P.n + G - 1) / G;
     const int grid = items;   // one work item per block
-    if (2 * P.n == P.n_fine) hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P, src);
-    else hipLaunchKernelGGL((k_rows_forward<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P, src);
+    if (2 * P.n == P.n_fine) PHI_LAUNCH((k_rows_forward<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P, src);
+    else PHI_LAUNCH((k_rows_forward<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P, src);
     return hipGetLastError();
 }
 
@@ -208,17 +209,17 @@ hipError_t launch_cols_highfreq_dir(const DevPlan& P, hipStream_t s) {
     // run the same code; the Coulomb multipliers use the general bounds only
     const bool exact = 2 * P.n == P.n_fine;
     if (P.component == 2 && exact)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindMixed, true>), dim3(grid), dim3(block), 0, s, P);
+        PHI_LAUNCH((k_cols_highfreq<R, LOG, DIR, kKindMixed, true>), dim3(grid), dim3(block), 0, s, P);
     else if (P.component == 2)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindMixed, false>), dim3(grid), dim3(block), 0, s, P);
+        PHI_LAUNCH((k_cols_highfreq<R, LOG, DIR, kKindMixed, false>), dim3(grid), dim3(block), 0, s, P);
     else if (P.component == 3 && P.partition_erfc)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombErfc, false>), dim3(grid), dim3(block), 0, s, P);
+        PHI_LAUNCH((k_cols_highfreq<R, LOG, DIR, kKindCoulombErfc, false>), dim3(grid), dim3(block), 0, s, P);
     else if (P.component == 3)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindCoulombGauss, false>), dim3(grid), dim3(block), 0, s, P);
+        PHI_LAUNCH((k_cols_highfreq<R, LOG, DIR, kKindCoulombGauss, false>), dim3(grid), dim3(block), 0, s, P);
     else if (exact)
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindQuadratic, true>), dim3(grid), dim3(block), 0, s, P);
+        PHI_LAUNCH((k_cols_highfreq<R, LOG, DIR, kKindQuadratic, true>), dim3(grid), dim3(block), 0, s, P);
     else
-        hipLaunchKernelGGL((k_cols_highfreq<R, LOG, DIR, kKindQuadratic, false>), dim3(grid), dim3(block), 0, s, P);
+        PHI_LAUNCH((k_cols_highfreq<R, LOG, DIR, kKindQuadratic, false>), dim3(grid), dim3(block), 0, s, P);
     return hipGetLastError();
 }
 
@@ -230,8 +231,8 @@ hipError_t launch_cols_highfreq(const DevPlan& P, int dir, hipStream_t s) {
 template <typename R, int LOG>
 hipError_t launch_cols_type2(const DevPlan& P, int dir, hipStream_t s) {
     const int blocks = P.patch;
-    if (dir < 0) hipLaunchKernelGGL((k_cols_type2<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT), 0, s, P);
-    else hipLaunchKernelGGL((k_cols_type2<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT), 0, s, P);
+    if (dir < 0) PHI_LAUNCH((k_cols_type2<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT), 0, s, P);
+    else PHI_LAUNCH((k_cols_type2<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT), 0, s, P);
     return hipGetLastError();
 }
 
@@ -239,8 +240,8 @@ template <typename R, int LOG>
 hipError_t launch_cols_type1(const DevPlan& P, int dir, hipStream_t s) {
     constexpr int G = lines_per_block<LOG>();
     const int blocks = P.patch;   // one window column per block
-    if (dir < 0) hipLaunchKernelGGL((k_cols_type1<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
-    else hipLaunchKernelGGL((k_cols_type1<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
+    if (dir < 0) PHI_LAUNCH((k_cols_type1<R, LOG, -1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
+    else PHI_LAUNCH((k_cols_type1<R, LOG, 1>), dim3(blocks), dim3(FftShape<LOG>::NT * G), 0, s, P);
     return hipGetLastError();
 }
 
@@ -252,9 +253,9 @@ hipError_t launch_rows_inverse_parts(const DevPlan& P, R* dst, hipStream_t s) {
     const int grid = items;   // one work item per block
     // the full solve (I1 and I2) has an exact-bounds variant; the stage variants use the general one
     if (I1 && I2 && 2 * P.n == P.n_fine)
-        hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2, I1 && I2>), dim3(grid), dim3(block), 0, s, P, dst);
+        PHI_LAUNCH((k_rows_inverse<R, LOG, DIR, I1, I2, I1 && I2>), dim3(grid), dim3(block), 0, s, P, dst);
     else
-        hipLaunchKernelGGL((k_rows_inverse<R, LOG, DIR, I1, I2, false>), dim3(grid), dim3(block), 0, s, P, dst);
+        PHI_LAUNCH((k_rows_inverse<R, LOG, DIR, I1, I2, false>), dim3(grid), dim3(block), 0, s, P, dst);
     return hipGetLastError();
 }
 
@@ -328,10 +329,10 @@ hipError_t run_capacity(const DevPlan& P, int* blocks) {
 template <typename R, int MODE>
 hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t s) {
     if (P.width > kMaxEsWidth)
-        hipLaunchKernelGGL((k_nodes<R, MODE, kMaxKernelWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
+        PHI_LAUNCH((k_nodes<R, MODE, kMaxKernelWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
                            static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
     else
-        hipLaunchKernelGGL((k_nodes<R, MODE, kMaxEsWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
+        PHI_LAUNCH((k_nodes<R, MODE, kMaxEsWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
                            static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
     return hipGetLastError();
 }
@@ -409,14 +410,30 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
 
 }  // namespace
 
+LaunchEvents& launch_events() {
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
 hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s) {
     if (!t) return hipSuccess;
     if (t->count >= KernelTimer::kMax) return hipErrorInvalidValue;
+    LaunchEvents& le = launch_events();
     if (!end) {
         t->names[t->count] = name;
-        return hipEventRecord(t->ev[2 * t->count], s);
+        le.start = t->ev[2 * t->count];
+        le.stop = t->ev[2 * t->count + 1];
+        le.used = false;
+        return hipSuccess;
     }
-    return hipEventRecord(t->ev[2 * t->count++ + 1], s);
+    hipError_t e = hipSuccess;
+    if (!le.used) {   // nothing was launched in between: an empty interval
+        e = hipEventRecord(t->ev[2 * t->count], s);
+        if (e == hipSuccess) e = hipEventRecord(t->ev[2 * t->count + 1], s);
+    }
+    le = LaunchEvents();
+    ++t->count;
+    return e;
 }
 
 hipError_t middle_capacity(const DevPlan& P, int* blocks) {

@@ -84,9 +84,33 @@ struct KernelTimer {
 // FFTs over the I1 half-spectrum workspace); N >= 16.
 hipError_t enqueue_periodic(const DevPlan& P, const void* in, void* out, hipStream_t s, KernelTimer* timer);
 
-// Records the start (end = false) or the end (end = true) of kernel `name` on
-// stream s; no-op without a timer.
+// Starts (end = false) or closes (end = true) the timing of kernel `name` on
+// stream s; no-op without a timer.  The kernel launched in between receives the
+// timer's two events through launch_events(), and the runtime records in them
+// the kernel's own start and end (as the profiler sees it, not the enqueue
+// around it).
 hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s);
+
+// Events for the next kernel launch of this host thread (null when nothing is timed).
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+LaunchEvents& launch_events();
+
+// Every solver kernel is launched through this macro: a plain launch, or, while
+// a kernel is being timed, the runtime's launch with start and stop events
+// (hipExtLaunchKernelGGL; kernel sources include <hip/hip_ext.h>).
+#define PHI_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                             \
+    do {                                                                                               \
+        ::phi::LaunchEvents& ev_ = ::phi::launch_events();                                             \
+        if (ev_.start && !ev_.used) {                                                                  \
+            ev_.used = true;                                                                           \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+        } else {                                                                                       \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                        \
+        }                                                                                              \
+    } while (0)
 
 // Blocks of the fused middle launch of plan P that can be resident on the
 // current device at once (the launch is deadlock-free while the blocks that
