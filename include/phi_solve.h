@@ -86,13 +86,16 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
                                 exponential of semicircle.  Needs bin + w - 1 <= 31 (tol >= 5e-13
                                 at bin 4); other cases return PHI_ERR_UNSUPPORTED. */
 #define PHI_TWO_STREAMS 32u /* run the node-side chain as its own three launches on a second stream,
-                                concurrently with the I1 column pass, also where a plan would run
-                                it fused: on padded sides up to 512 the I1 columns and the whole
-                                chain are by default one launch whose dependent blocks wait on
-                                device counters (three launches per solve instead of five on the
-                                critical path); results are bit-identical.  Larger sides, the
-                                mixed multiplier and the Gaussian kernel above 16 cells always
-                                use the two-stream layout. */
+                                concurrently with the I1 column pass, also where a plan would
+                                otherwise keep the solve on one stream: on padded sides up to 512
+                                the I1 columns and the whole chain are by default one launch whose
+                                dependent blocks wait on device counters (the DS and y multipliers;
+                                three launches per solve instead of five on the critical path); FP32
+                                solves on padded sides 1024 and 2048 by default run the chain's
+                                three launches on the solve's stream, each with a slice of the I1
+                                columns beside the chain's blocks.  Results are bit-identical in
+                                every layout.  Other cases and the Gaussian kernel above 16 cells
+                                always use the two-stream layout. */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
                                 subproblem sizes {32, 64} on the device and keep the fastest; the
                                 choice is visible in phi_plan_info.bin / .sub_nodes.  Results of

@@ -47,7 +47,7 @@ def build(verbose: bool = False) -> str:
     incs = [f"-I{INCLUDE}", f"-I{CSRC}", f"-I{ROCM}/include"]
     jobs = []
     for src, compiler in (("plan_host.cpp", "gxx"), ("phi_api.cpp", "gxx"), ("ds_api.cpp", "gxx"),
-                          ("solver_kernels.hip", "hipcc"), ("batch_kernels.hip", "hipcc"),
+                          ("solver_kernels.hip", "hipcc"), ("shared_kernels.hip", "hipcc"), ("batch_kernels.hip", "hipcc"),
                           ("ds_kernels.hip", "hipcc"), ("periodic_kernels.hip", "hipcc"),
                           ("scratch.hip", "hipcc")):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")

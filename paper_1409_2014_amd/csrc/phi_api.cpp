@@ -70,6 +70,9 @@ size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 // largest padded side (log2) whose solves use the fused middle launch by default
 constexpr int kFusedMaxLogFine = 9;
+// relative lengths of the type-2, node and type-1 stages of the node-side
+// chain, by which the shared layout splits the I1 columns over its launches
+constexpr double kSharedWeights[3] = {1.0, 1.6, 2.0};
 
 phi_status check_plan(phi_plan_t plan) {
     if (!is_live(plan)) return fail(nullptr, PHI_ERR_INVALID_ARG, "plan is NULL or was destroyed");
@@ -233,6 +236,24 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     // variants the fused launch leaves out, or when asked for two streams.
     d->fused = (!hp.two_streams && hp.component <= 1 && hp.width <= phi::kMaxEsWidth &&
                 hp.log_fine <= kFusedMaxLogFine) ? 1 : 0;
+    // FP32 solves on padded sides 1024 and 2048 run the shared layout: the
+    // chain's three launches on the solve's stream, each with a slice of the I1
+    // columns sized to the stage's expected length (relative weights
+    // kSharedWeights).  Graph replay on MI355X: 512^2 FP32 63.7 -> 41.9 us,
+    // 1024^2 FP32 49..58 -> 50 us (the two-stream layout's time varies from run
+    // to run); where the I1 columns are the longer branch (FP64, and FP32 from
+    // 2048^2 on) the two-stream layout measured faster (2048^2 FP64 143 against
+    // 153 us, FP32 99 against 101 us).
+    d->shared = (!d->fused && !hp.two_streams && hp.width <= phi::kMaxEsWidth && dtype == PHI_F32 &&
+                 hp.log_fine >= phi::kSharedMinLogFine && hp.log_fine <= phi::kSharedMaxLogFine) ? 1 : 0;
+    {
+        const int g = hp.log_fine >= 12 ? 1 : (256 >> (hp.log_fine - 4));   // I1 columns per block
+        const int col_blocks = (hp.n_fine / 2 + 1 + g - 1) / g;
+        const double wsum = kSharedWeights[0] + kSharedWeights[1] + kSharedWeights[2];
+        d->shared_cols[0] = static_cast<int>(col_blocks * kSharedWeights[0] / wsum);
+        d->shared_cols[1] = static_cast<int>(col_blocks * kSharedWeights[1] / wsum);
+        d->shared_cols[2] = col_blocks - d->shared_cols[0] - d->shared_cols[1];
+    }
     d->sync = reinterpret_cast<unsigned*>(base + sp.sync.off);
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));

@@ -113,18 +113,13 @@ constexpr size_t middle_lds_bytes() {
     return fft > node ? fft : node;
 }
 
-template <typename R, int LOG, int DIR, bool EXACT>
-__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_middle(DevPlan P, MiddleSplit S) {
+// One block of the node-side chain (b < S.chain), by its role.
+template <typename R, int LOG, int DIR>
+__device__ __forceinline__ void chain_block(const DevPlan& P, const MiddleSplit& S, unsigned b,
+                                            unsigned char* lds_raw) {
     constexpr int G = lines_per_block<LOG>();
     constexpr int NTH = FftShape<LOG>::NT * G;
-    __shared__ __align__(16) unsigned char lds_raw[middle_lds_bytes<R, LOG>()];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(lds_raw);
-    const unsigned b = blockIdx.x;
-    if (b >= S.chain) {
-        const int c = xcd_logical_block(static_cast<int>(b - S.chain), static_cast<int>(S.total - S.chain));
-        cols_highfreq_body<R, LOG, DIR, G, kKindQuadratic, EXACT>(P, c * G, lds);
-        return;
-    }
     // the chain is the critical path: its waves issue first on a shared SIMD
     __builtin_amdgcn_s_setprio(3);
     if (b < S.t2_end) {
@@ -139,6 +134,19 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
         wait_count(P.sync, kSyncNodesDone, S.nodes_end - S.t2_end);
         cols_type1_body<R, LOG, -DIR, G, 1, false>(P, static_cast<int>(b - S.nodes_end), lds);
     }
+}
+
+template <typename R, int LOG, int DIR, bool EXACT>
+__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_middle(DevPlan P, MiddleSplit S) {
+    constexpr int G = lines_per_block<LOG>();
+    __shared__ __align__(16) unsigned char lds_raw[middle_lds_bytes<R, LOG>()];
+    const unsigned b = blockIdx.x;
+    if (b >= S.chain) {
+        const int c = xcd_logical_block(static_cast<int>(b - S.chain), static_cast<int>(S.total - S.chain));
+        cols_highfreq_body<R, LOG, DIR, G, kKindQuadratic, EXACT>(P, c * G, reinterpret_cast<cpx<R>*>(lds_raw));
+        return;
+    }
+    chain_block<R, LOG, DIR>(P, S, b, lds_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,6 +370,13 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
             PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
             if (P.fused) {
                 PHI_STEP("middle", s, (run_middle<R>(P, dir, s)));
+                PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
+                return hipSuccess;
+            }
+            if (P.shared) {
+                PHI_STEP("shared_type2", s, (launch_shared_stage(P, 0, dir, s)));
+                PHI_STEP("shared_nodes", s, (launch_shared_stage(P, 1, dir, s)));
+                PHI_STEP("shared_type1", s, (launch_shared_stage(P, 2, dir, s)));
                 PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
                 return hipSuccess;
             }

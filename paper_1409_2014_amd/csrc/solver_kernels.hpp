@@ -32,6 +32,8 @@ struct DevPlan {
     double inv_sigma;       // 1 / sigma
     int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
     int fused;              // a solve runs the I1 columns and the node-side chain as one launch
+    int shared;             // (not fused) each node-side launch also runs a slice of the I1 columns
+    int shared_cols[3];     // I1 column blocks in the type-2, node and type-1 launches of that layout
     double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index
     int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
     double h2, inv_f2;
@@ -111,6 +113,16 @@ LaunchEvents& launch_events();
             hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                        \
         }                                                                                              \
     } while (0)
+
+// Padded sides (log2) for which the shared layout's kernels are built.
+constexpr int kSharedMinLogFine = 10;
+constexpr int kSharedMaxLogFine = 11;
+
+// One launch of the shared layout on stream s: stage 0 (type-2 window
+// columns), 1 (node subproblems) or 2 (type-1 window columns) of the node-side
+// chain in its first blocks, and P.shared_cols[stage] blocks of I1 spectrum
+// columns after them.  dir is the solve's transform direction.
+hipError_t launch_shared_stage(const DevPlan& P, int stage, int dir, hipStream_t s);
 
 // Blocks of the fused middle launch of plan P that can be resident on the
 // current device at once (the launch is deadlock-free while the blocks that

@@ -1,11 +1,17 @@
-"""The fused middle launch (the I1 columns and the whole node-side chain in one
-launch whose dependent blocks wait on device counters; the default on padded
-sides up to 512) against the two-stream layout of separate launches:
-bit-identical results, forward and transposed, on every padded side from 16
-to 512, repeated calls (the counters are zeroed by each solve's first
-kernel), graph replays, and the device-side spin-limit flag never set.  Both
-layouts also stay within the solve's bars of the FP64 oracle (checked by the
-parity tests; here one small case closes the loop)."""
+"""The one-stream layouts of a solve's middle part against the two-stream
+layout of separate launches (PHI_TWO_STREAMS):
+  * the fused middle launch (the I1 columns and the whole node-side chain in
+    one launch whose dependent blocks wait on device counters; the default on
+    padded sides up to 512): bit-identical results, forward and transposed, on
+    every padded side from 16 to 512, repeated calls (the counters are zeroed
+    by each solve's first kernel), graph replays, and the device-side
+    spin-limit flag never set;
+  * the shared layout (each of the chain's three launches also runs a slice of
+    the I1 columns; the default for FP32 on padded sides 1024 and 2048):
+    bit-identical results, forward and transposed, for every multiplier, at
+    exact and general grid bounds, and under graph replay.
+Every layout also stays within the solve's bars of the FP64 oracle (checked by
+the parity tests; here one small case per layout closes the loop)."""
 import numpy as np
 import pytest
 
@@ -34,7 +40,8 @@ def density(n, half, seed):
     return W.mixture_density(n, half, spec)
 
 
-CASES = [(8, 4.0), (16, 4.0), (64, 8.0), (96, 4.0), (200, 8.0), (256, 8.0)]
+CASES = [(8, 4.0), (16, 4.0), (64, 8.0), (96, 4.0), (200, 8.0), (256, 8.0), (300, 8.0), (512, 8.0),
+         (600, 12.0), (1024, 16.0), (2048, 16.0)]
 
 
 @pytest.mark.parametrize("n,half", CASES)
@@ -59,11 +66,28 @@ def test_fused_launch_equals_two_streams(ps, n, half, dtype):
     split.close()
 
 
+@pytest.mark.parametrize("component", ["y", "xy", "coulomb"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_fused_launch_under_graph_replay(ps, dtype):
+def test_shared_layout_other_multipliers(ps, component, dtype):
+    n, half = 512, 8.0
+    print(f"case: shared layout vs two streams N={n} {component} {dtype}", flush=True)
+    h = 2 * half / n
+    rho = torch.as_tensor(density(n, half, 41), dtype=dtype, device="cuda")
+    a = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype], component=component)
+    b = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype], component=component, two_streams=True)
+    fa = a.solve(rho)
+    assert torch.equal(fa, b.solve(rho))
+    assert torch.equal(a.solve_adjoint(fa), b.solve_adjoint(fa))
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("n,half", [(256, 8.0), (1024, 16.0)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_launch_under_graph_replay(ps, n, half, dtype):
     """Ten replays of a captured forward + transposed pair, with eager solves
-    between them: every replay equals the eager result."""
-    n, half = 256, 8.0
+    between them: every replay equals the eager result (the fused middle launch
+    at 256^2, the shared layout at 1024^2 in FP32)."""
     h = 2 * half / n
     print(f"case: fused graph replay N={n} {dtype}", flush=True)
     plan = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
@@ -95,10 +119,10 @@ def test_fused_launch_under_graph_replay(ps, dtype):
     plan.close()
 
 
-def test_fused_launch_matches_oracle(ps):
-    n, half = 96, 4.0
+@pytest.mark.parametrize("n,half", [(96, 4.0), (300, 8.0)])
+def test_fused_launch_matches_oracle(ps, n, half):
     h = 2 * half / n
-    print("case: fused vs oracle N=96 FP64", flush=True)
+    print(f"case: default layout vs oracle N={n} FP64", flush=True)
     rho = density(n, half, 9)
     plan = ps.Plan(n, h, dtype=torch.float64, tol=1e-12)
     got = plan.solve(torch.as_tensor(rho, device="cuda")).cpu().numpy()
