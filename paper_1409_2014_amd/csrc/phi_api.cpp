@@ -223,11 +223,12 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     d->inv_sigma = 1.0 / hp.sigma;
     // The two branches of a solve share the GPU, and the one enqueued first is
     // served first: the node-side chain (the same few small kernels at every N)
-    // unless the high-frequency columns carry more than 1.5 times the work they
-    // have in a 2048^2 FP32 solve (N F log2 F times the element size), where
-    // they are the longer branch (FP64 at 2048^2, both precisions at 4096^2).
+    // unless the high-frequency columns carry at least the work they have in a
+    // 2048^2 FP32 solve (N F log2 F times the element size), where they are the
+    // longer branch.  Graph replay on MI355X: 2048^2 FP32 98.2 -> 95.8..97.2 us
+    // with the columns first, 1024^2 FP64 60.5 -> 70.5 us (so chain first there).
     const double col_work = (f / 2) * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
-    d->highfreq_first = col_work > 1.5 * (2048.0 * 4096.0 * 12.0 * 4.0) ? 1 : 0;
+    d->highfreq_first = col_work >= 2048.0 * 4096.0 * 12.0 * 4.0 ? 1 : 0;
     // The I1 columns and the node-side chain as one launch where that measured
     // faster: padded sides up to 512 (graph replay on MI355X, 64^2 FP32 46 ->
     // 41.5 us, 256^2 54 -> 47.5 us); from 1024^2 on the chain's critical path
