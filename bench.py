@@ -56,10 +56,10 @@ VALU_PEAK_PUBLISHED_F32 = 157.3
 TRAFFIC_RECORD = {
     "kernel": "cols_highfreq",
     "fetch_kib": 16751.1, "write_kib": 32784.0,
-    "copy_fetch_kib": 131093.81, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
-    "sources": ("block_sync.hpp", "device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
+    "copy_fetch_kib": 131088.88, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "018604a0bf4eacc7563e254a48e4827b8d7dcd5f974f9493719c7c38597cd671",
+    "sha256": "3b3c4c59eeb53b94a2c57da5d5e1f87f827a65e74e06f8cfa8c72beba9404cf7",
 }
 
 N = 2048
@@ -86,8 +86,6 @@ def kernel_bytes(info: dict, real_bytes: int) -> dict:
         "cols_type1": tiles + info["n_contrib"] * 4 + (q * q + 1) * 4 + n * q * sc,
         "rows_inverse": spec + n * q * sc + n * n * sr,
     }
-    # the fused launch holds the I1 columns and the node-side chain
-    out["middle"] = out["cols_highfreq"] + out["cols_type2"] + out["nodes"] + out["cols_type1"]
     return out
 
 
@@ -99,7 +97,6 @@ def kernel_flops(info: dict) -> dict:
     fft = 5 * f * math.log2(f)
     out = {"rows_forward": n * fft, "cols_highfreq": 2 * (f // 2 + 1) * fft, "rows_inverse": n * fft,
            "cols_type2": q * fft, "cols_type1": q * fft}
-    out["middle"] = out["cols_highfreq"] + out["cols_type2"] + out["cols_type1"]
     return out
 
 

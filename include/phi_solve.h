@@ -87,15 +87,12 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
                                 at bin 4); other cases return PHI_ERR_UNSUPPORTED. */
 #define PHI_TWO_STREAMS 32u /* run the node-side chain as its own three launches on a second stream,
                                 concurrently with the I1 column pass, also where a plan would
-                                otherwise keep the solve on one stream: on padded sides up to 512
-                                the I1 columns and the whole chain are by default one launch whose
-                                dependent blocks wait on device counters (the DS and y multipliers;
-                                three launches per solve instead of five on the critical path); FP32
-                                solves on padded sides 1024 and 2048 by default run the chain's
-                                three launches on the solve's stream, each with a slice of the I1
-                                columns beside the chain's blocks.  Results are bit-identical in
-                                every layout.  Other cases and the Gaussian kernel above 16 cells
-                                always use the two-stream layout. */
+                                otherwise keep the solve on one stream: on padded sides up to 1024
+                                (and 2048 in FP32) the chain's three launches run by default
+                                on the solve's stream, each with a slice of the I1 columns beside
+                                the chain's blocks.  Results are bit-identical in both layouts.
+                                Larger sides and the Gaussian kernel above 16 cells always use
+                                the two-stream layout. */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and
                                 subproblem sizes {32, 64} on the device and keep the fastest; the
                                 choice is visible in phi_plan_info.bin / .sub_nodes.  Results of
@@ -248,14 +245,6 @@ phi_status phi_solve_lowfreq(phi_plan_t plan, const void* rho, void* i2, void* s
  * calling thread. */
 phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t adjoint, void* stream,
                            float* kernel_ms, const char** names, int32_t capacity, int32_t* count);
-
-/* Synchronises the device and reports whether any wait inside the plan's fused
- * solve launch (the I1 columns and the node-side chain, whose blocks wait on
- * device counters) ran
- * past its spin limit since the plan was created: PHI_OK if none did (and for
- * batch plans), PHI_ERR_DEVICE with a message otherwise.  Such a launch still
- * ends, but its result is not valid. */
-phi_status phi_plan_device_status(phi_plan_t plan);
 
 /* Host-only helpers used by the plan (exported for CPU tests). */
 phi_status phi_host_gauss_legendre(int32_t n, double* x, double* w);

@@ -100,7 +100,6 @@ def _declare(lib):
                                  ctypes.POINTER(ctypes.c_char_p), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]),
         "phi_plan_get_info": (st, [_P, ctypes.POINTER(PhiPlanInfo)]),
-        "phi_plan_device_status": (st, [_P]),
         "phi_plan_nodes": (st, [_P, _DP, _DP, _DP]),
         "phi_host_gauss_legendre": (st, [ctypes.c_int32, _DP, _DP]),
         "phi_host_gauss_jacobi01": (st, [ctypes.c_int32, _DP, _DP]),
@@ -150,7 +149,7 @@ def exported_symbols():
         "phi_batch_member_info",
         "phi_solve", "phi_solve_noalloc", "phi_solve_adjoint",
         "phi_solve_highfreq", "phi_solve_lowfreq", "phi_nodes_type2", "phi_nodes_type1", "phi_solve_periodic",
-        "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_device_status", "phi_plan_nodes", "phi_host_gauss_legendre", "phi_host_gauss_jacobi01",
+        "phi_destroy", "phi_solve_timed", "phi_plan_get_info", "phi_plan_nodes", "phi_host_gauss_legendre", "phi_host_gauss_jacobi01",
         "phi_host_es_kernel", "phi_host_es_transform", "phi_host_polar_nodes",
         "phi_status_string", "phi_last_error",
         "phi_ds_create", "phi_ds_substeps", "phi_ds_destroy", "phi_ds_plan", "phi_ds_forward", "phi_ds_backward",

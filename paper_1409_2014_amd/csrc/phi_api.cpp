@@ -68,8 +68,6 @@ phi_status device_fail(phi_plan_t plan, hipError_t e, const char* where) {
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-// largest padded side (log2) whose solves use the fused middle launch by default
-constexpr int kFusedMaxLogFine = 9;
 // relative lengths of the type-2, node and type-1 stages of the node-side
 // chain, by which the shared layout splits the I1 columns over its launches
 constexpr double kSharedWeights[3] = {1.0, 1.6, 2.0};
@@ -102,10 +100,6 @@ struct Layout {
 // everything a plan reads and never writes
 struct TableParts {
     Part deconv, gx, gy, gyr, q, cell, sub, cst, con, taps, twr, twn;
-};
-// counters of the fused middle launch: written by every solve, zero between solves
-struct SyncPart {
-    Part sync;
 };
 // everything a solve writes
 struct WorkParts {
@@ -200,14 +194,8 @@ void point_work(char* base, const WorkParts& w, phi::DevPlan* d) {
     d->u = base + w.u.off;
 }
 
-SyncPart layout_sync(Layout& L) {
-    SyncPart s;
-    s.sync = L.take(phi::kSyncWords * sizeof(unsigned));
-    return s;
-}
-
 void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableParts& t,
-              const WorkParts& w, const SyncPart& sp, phi::DevPlan* d) {
+              const WorkParts& w, phi::DevPlan* d) {
     const double f = hp.n_fine;
     d->dtype = dtype;
     d->n = hp.n;
@@ -229,24 +217,22 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     // with the columns first, 1024^2 FP64 60.5 -> 70.5 us (so chain first there).
     const double col_work = (f / 2) * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
     d->highfreq_first = col_work >= 2048.0 * 4096.0 * 12.0 * 4.0 ? 1 : 0;
-    // The I1 columns and the node-side chain as one launch where that measured
-    // faster: padded sides up to 512 (graph replay on MI355X, 64^2 FP32 46 ->
-    // 41.5 us, 256^2 54 -> 47.5 us); from 1024^2 on the chain's critical path
-    // inside the shared launch is longer than beside it on a second stream
-    // (1024^2 FP32 52 -> 63 us, 2048^2 104 -> 117 us).  Not for the kernel
-    // variants the fused launch leaves out, or when asked for two streams.
-    d->fused = (!hp.two_streams && hp.component <= 1 && hp.width <= phi::kMaxEsWidth &&
-                hp.log_fine <= kFusedMaxLogFine) ? 1 : 0;
-    // FP32 solves on padded sides 1024 and 2048 run the shared layout: the
-    // chain's three launches on the solve's stream, each with a slice of the I1
-    // columns sized to the stage's expected length (relative weights
-    // kSharedWeights).  Graph replay on MI355X: 512^2 FP32 63.7 -> 41.9 us,
-    // 1024^2 FP32 49..58 -> 50 us (the two-stream layout's time varies from run
-    // to run); where the I1 columns are the longer branch (FP64, and FP32 from
-    // 2048^2 on) the two-stream layout measured faster (2048^2 FP64 143 against
-    // 153 us, FP32 99 against 101 us).
-    d->shared = (!d->fused && !hp.two_streams && hp.width <= phi::kMaxEsWidth && dtype == PHI_F32 &&
-                 hp.log_fine >= phi::kSharedMinLogFine && hp.log_fine <= phi::kSharedMaxLogFine) ? 1 : 0;
+    // Padded sides up to 1024 (both precisions) and FP32 solves on padded side
+    // 2048 run the shared layout: the chain's three launches on the solve's
+    // stream, each with a slice of the I1 columns sized to the stage's expected
+    // length (relative weights kSharedWeights).  Graph replay on MI355X, two
+    // runs each: 64^2 FP64 42.5, 43.4 -> 38.2, 38.4 us; 64^2 FP32 45.9, 39.7 ->
+    // 33.8, 34.0; 128^2 FP32 48.9, 48.4 -> 36.2, 36.2; 256^2 FP32 51.5, 45.1 ->
+    // 39.5, 39.8 (against the one launch with device-counter waits that these
+    // sides used before); 512^2 FP32 63.7 -> 41.9, 512^2 FP64 52.5..71 -> 49.5,
+    // 49.5; 1024^2 FP32 49..58 -> 50 (against the two-stream layout, whose time
+    // there varies from run to run).  Where the I1 columns are the longer branch
+    // (FP64 from 1024^2, FP32 from 2048^2) the two-stream layout measured faster
+    // (1024^2 FP64 60..62 against 66 us, 2048^2 FP64 143 against 153 us, FP32 99
+    // against 101 us).
+    d->shared = (!hp.two_streams && hp.width <= phi::kMaxEsWidth &&
+                 hp.log_fine >= phi::kSharedMinLogFine &&
+                 (hp.log_fine <= 10 || (dtype == PHI_F32 && hp.log_fine <= phi::kSharedMaxLogFine))) ? 1 : 0;
     {
         const int g = hp.log_fine >= 12 ? 1 : (256 >> (hp.log_fine - 4));   // I1 columns per block
         const int col_blocks = (hp.n_fine / 2 + 1 + g - 1) / g;
@@ -255,7 +241,6 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
         d->shared_cols[1] = static_cast<int>(col_blocks * kSharedWeights[1] / wsum);
         d->shared_cols[2] = col_blocks - d->shared_cols[0] - d->shared_cols[1];
     }
-    d->sync = reinterpret_cast<unsigned*>(base + sp.sync.off);
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));
     d->h2 = hp.h * hp.h;
@@ -323,7 +308,6 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
     const size_t es = f32 ? 4 : 8;
     Layout L;
     const TableParts tp = layout_tables(hp, es, L);
-    const SyncPart sp = layout_sync(L);
     const WorkParts wp = layout_work(hp, es, L);
     plan->block_bytes = L.cursor;
     e = hipMalloc(&plan->block, L.cursor);
@@ -335,7 +319,6 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
     char* base = static_cast<char*>(plan->block);
     std::vector<std::vector<float>> keep;
     e = upload_tables(hp, tp, base, f32, s, keep);
-    if (e == hipSuccess) e = hipMemsetAsync(base + sp.sync.off, 0, sp.sync.bytes, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release(plan.get());
@@ -346,18 +329,7 @@ phi_status create_single(const phi_params* p, hipStream_t s, phi_plan_s** out) {
         release(plan.get());
         return st;
     }
-    fill_dev(hp, p->dtype, base, tp, wp, sp, &plan->dev);
-    if (plan->dev.fused) {
-        // the fused launch needs its waiting blocks to be fewer than the blocks
-        // the device holds at once; keep at least half the slots for the rest
-        int capacity = 0;
-        e = phi::middle_capacity(plan->dev, &capacity);
-        if (e != hipSuccess) {
-            release(plan.get());
-            return device_fail(nullptr, e, "occupancy query");
-        }
-        if (2 * phi::middle_waiting_blocks(plan->dev) > capacity) plan->dev.fused = 0;
-    }
+    fill_dev(hp, p->dtype, base, tp, wp, &plan->dev);
     *out = plan.release();
     return PHI_OK;
 }
@@ -650,7 +622,6 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         for (const phi::HostPlan& hp : plan->sets) tparts.push_back(layout_tables(hp, es, L));
         std::vector<WorkParts> wparts;
         for (int i = 0; i < count; ++i) wparts.push_back(layout_work(plan->sets[plan->member_set[i]], es, L));
-        const SyncPart bsync = layout_sync(L);   // batch kernels do not use the fused launch
         const Part p_dev = L.take(sizeof(phi::DevPlan) * count);
         const Part p_off = L.take(sizeof(int64_t) * (count + 1));
         const Part p_rows = L.take(sizeof(phi::WorkItem) * rows.size());
@@ -675,7 +646,7 @@ phi_status phi_plan_batch(const phi_params* members, int32_t count, void* stream
         std::vector<phi::DevPlan> devs(count);
         for (int i = 0; i < count; ++i)
             fill_dev(plan->sets[plan->member_set[i]], dtype, base, tparts[plan->member_set[i]], wparts[i],
-                     bsync, &devs[i]);
+                     &devs[i]);
         auto up = [&](const Part& pt, const void* src) -> hipError_t {
             if (pt.bytes == 0) return hipSuccess;
             return hipMemcpyAsync(base + pt.off, src, pt.bytes, hipMemcpyHostToDevice, s);
@@ -895,8 +866,6 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
     if (e != hipSuccess) return device_fail(plan, e, "kernel launch");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(plan, e, "hipStreamSynchronize");
-    st = phi_plan_device_status(plan);
-    if (st != PHI_OK) return st;
     *count = t.count;
     for (int i = 0; i < t.count && i < capacity; ++i) {
         float ms = 0.f;
@@ -905,23 +874,6 @@ phi_status phi_solve_timed(phi_plan_t plan, const void* in, void* out, int32_t a
         kernel_ms[i] = ms;
         names[i] = t.names[i];
     }
-    return PHI_OK;
-}
-
-phi_status phi_plan_device_status(phi_plan_t plan) {
-    phi_status st = check_plan(plan);
-    if (st != PHI_OK) return st;
-    if (plan->n_members > 0) return PHI_OK;   // batches do not use the fused launch
-    st = check_device(plan);
-    if (st != PHI_OK) return st;
-    unsigned flag = 0;
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess)
-        e = hipMemcpy(&flag, plan->dev.sync + phi::kSyncError * phi::kSyncStride, sizeof(flag),
-                      hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return device_fail(plan, e, "phi_plan_device_status");
-    if (flag != 0)
-        return fail(plan, PHI_ERR_DEVICE, "a wait inside the fused solve launch exceeded its spin limit");
     return PHI_OK;
 }
 

@@ -1,4 +1,4 @@
-// The shared layout of a solve's middle part (padded sides 1024 and 2048):
+// The shared layout of a solve's middle part (padded sides 16 .. 2048):
 // three launches on the solve's one stream, each running one stage of the
 // node-side chain in its first blocks and a slice of the I1 spectrum columns
 // in the rest.
@@ -99,8 +99,14 @@ hipError_t launch_typed(const DevPlan& P, int stage, int dir, hipStream_t s) {
 
 template <typename R>
 hipError_t launch_r(const DevPlan& P, int stage, int dir, hipStream_t s) {
-    static_assert(kSharedMinLogFine == 10 && kSharedMaxLogFine == 11, "instantiated sides");
+    static_assert(kSharedMinLogFine == 4 && kSharedMaxLogFine == 11, "instantiated sides");
     switch (P.log_fine) {
+        case 4: return launch_typed<R, 4>(P, stage, dir, s);
+        case 5: return launch_typed<R, 5>(P, stage, dir, s);
+        case 6: return launch_typed<R, 6>(P, stage, dir, s);
+        case 7: return launch_typed<R, 7>(P, stage, dir, s);
+        case 8: return launch_typed<R, 8>(P, stage, dir, s);
+        case 9: return launch_typed<R, 9>(P, stage, dir, s);
         case 10: return launch_typed<R, 10>(P, stage, dir, s);
         case 11: return launch_typed<R, 11>(P, stage, dir, s);
         default: return hipErrorInvalidValue;

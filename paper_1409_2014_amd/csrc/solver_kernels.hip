@@ -30,20 +30,14 @@
 //
 // The transposed solve runs the same kernels with every FFT direction reversed.
 //
-// Fused layout (the default on padded sides up to 512 for the DS and y
-// multipliers with the ES kernel): cols_highfreq and the node-side chain run as
-// ONE launch, `middle`.  Its first blocks are the chain, by block index: the
-// type-2 window columns, then the node subproblems (each waits for all window
-// columns), then the type-1 window columns (each waits for all node blocks);
-// the remaining blocks are the I1 spectrum columns, which wait for nothing
-// (block_sync.hpp states why every wait ends).  A solve is then three launches
-// on one stream: rows_forward (which also zeroes the chain's counters), middle,
-// rows_inverse.
+// Shared layout (the default on padded sides up to 1024, and 2048 in FP32;
+// shared_kernels.hip): the chain's three kernels run on the solve's own
+// stream, each launch also carrying a slice of the I1 spectrum columns, so the
+// solve needs no second stream.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "solver_device.hpp"
-#include "block_sync.hpp"
 
 namespace phi {
 
@@ -55,8 +49,6 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
     DevPlan P, const R* __restrict__ rho) {
     constexpr int G = rows_per_block<R, LOG>();
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
-    // the counters of the solve's middle launch start from zero
-    if (blockIdx.x == 0 && threadIdx.x == 0 && P.sync) reset_counters(P.sync);
     rows_forward_body<R, LOG, DIR, G, EXACT>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
 
@@ -98,96 +90,10 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
                                                              lds_all);
 }
 
-// Blocks of the middle launch by index: [0, t2_end) type-2 window columns,
-// [t2_end, nodes_end) subproblems (each waits for all window columns),
-// [nodes_end, chain) type-1 window columns (each waits for all node blocks),
-// [chain, total) I1 spectrum columns (wait for nothing).
-struct MiddleSplit {
-    unsigned t2_end, nodes_end, chain, total;
-};
-
-template <typename R, int LOG>
-constexpr size_t middle_lds_bytes() {
-    constexpr size_t fft = static_cast<size_t>(lines_per_block<LOG>()) * lds_group_stride(1 << LOG) * sizeof(cpx<R>);
-    constexpr size_t node = sizeof(NodeLds<R, kMaxEsWidth>);
-    return fft > node ? fft : node;
-}
-
-// One block of the node-side chain (b < S.chain), by its role.
-template <typename R, int LOG, int DIR>
-__device__ __forceinline__ void chain_block(const DevPlan& P, const MiddleSplit& S, unsigned b,
-                                            unsigned char* lds_raw) {
-    constexpr int G = lines_per_block<LOG>();
-    constexpr int NTH = FftShape<LOG>::NT * G;
-    cpx<R>* lds = reinterpret_cast<cpx<R>*>(lds_raw);
-    // the chain is the critical path: its waves issue first on a shared SIMD
-    __builtin_amdgcn_s_setprio(3);
-    if (b < S.t2_end) {
-        cols_type2_body<R, LOG, DIR, G, false>(P, static_cast<int>(b) * G, lds);
-        signal_done(P.sync, kSyncT2Done);
-    } else if (b < S.nodes_end) {
-        wait_count(P.sync, kSyncT2Done, S.t2_end);
-        nodes_body<R, 0, NTH, kMaxEsWidth>(P, static_cast<int>(b - S.t2_end), nullptr, nullptr,
-                                           *reinterpret_cast<NodeLds<R, kMaxEsWidth>*>(lds_raw));
-        signal_done(P.sync, kSyncNodesDone);
-    } else {
-        wait_count(P.sync, kSyncNodesDone, S.nodes_end - S.t2_end);
-        cols_type1_body<R, LOG, -DIR, G, 1, false>(P, static_cast<int>(b - S.nodes_end), lds);
-    }
-}
-
-template <typename R, int LOG, int DIR, bool EXACT>
-__global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_middle(DevPlan P, MiddleSplit S) {
-    constexpr int G = lines_per_block<LOG>();
-    __shared__ __align__(16) unsigned char lds_raw[middle_lds_bytes<R, LOG>()];
-    const unsigned b = blockIdx.x;
-    if (b >= S.chain) {
-        const int c = xcd_logical_block(static_cast<int>(b - S.chain), static_cast<int>(S.total - S.chain));
-        cols_highfreq_body<R, LOG, DIR, G, kKindQuadratic, EXACT>(P, c * G, reinterpret_cast<cpx<R>*>(lds_raw));
-        return;
-    }
-    chain_block<R, LOG, DIR>(P, S, b, lds_raw);
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 namespace {
-
-MiddleSplit middle_split(const DevPlan& P, int g) {
-    MiddleSplit m;
-    m.t2_end = static_cast<unsigned>((P.patch + g - 1) / g);
-    m.nodes_end = m.t2_end + static_cast<unsigned>(P.n_sub);
-    m.chain = m.nodes_end + static_cast<unsigned>(P.patch);
-    m.total = m.chain + static_cast<unsigned>((P.n_fine / 2 + 1 + g - 1) / g);
-    return m;
-}
-
-template <typename R, int LOG>
-hipError_t capacity_middle(const DevPlan& P, int* blocks) {
-    constexpr int block = FftShape<LOG>::NT * lines_per_block<LOG>();
-    int per_cu = 0, cus = 0, dev = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_middle<R, LOG, -1, false>, block, 0);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    *blocks = per_cu * cus;
-    (void)P;
-    return e;
-}
-
-template <typename R, int LOG>
-hipError_t launch_middle(const DevPlan& P, int dir, hipStream_t s) {
-    constexpr int G = lines_per_block<LOG>();
-    constexpr int block = FftShape<LOG>::NT * G;
-    const MiddleSplit m = middle_split(P, G);
-    if (!P.sync || P.component > 1 || P.width > kMaxEsWidth) return hipErrorInvalidValue;
-    const bool exact = 2 * P.n == P.n_fine;
-    if (dir < 0 && exact) PHI_LAUNCH((k_middle<R, LOG, -1, true>), dim3(m.total), dim3(block), 0, s, P, m);
-    else if (dir < 0) PHI_LAUNCH((k_middle<R, LOG, -1, false>), dim3(m.total), dim3(block), 0, s, P, m);
-    else if (exact) PHI_LAUNCH((k_middle<R, LOG, 1, true>), dim3(m.total), dim3(block), 0, s, P, m);
-    else PHI_LAUNCH((k_middle<R, LOG, 1, false>), dim3(m.total), dim3(block), 0, s, P, m);
-    return hipGetLastError();
-}
 
 template <typename R, int LOG, int DIR>
 hipError_t launch_rows_forward_dir(const DevPlan& P, const R* src, hipStream_t s) {
@@ -325,14 +231,6 @@ template <typename R>
 hipError_t run_rows_inverse(const DevPlan& P, void* out, int dir, int use_i1, int use_i2, hipStream_t s) {
     PHI_DISPATCH_LOG(P.log_fine, (launch_rows_inverse<R, L_>(P, out, dir, use_i1, use_i2, s)));
 }
-template <typename R>
-hipError_t run_middle(const DevPlan& P, int dir, hipStream_t s) {
-    PHI_DISPATCH_LOG(P.log_fine, (launch_middle<R, L_>(P, dir, s)));
-}
-template <typename R>
-hipError_t run_capacity(const DevPlan& P, int* blocks) {
-    PHI_DISPATCH_LOG(P.log_fine, (capacity_middle<R, L_>(P, blocks)));
-}
 
 template <typename R, int MODE>
 hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t s) {
@@ -368,11 +266,6 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
     switch (stage) {
         case Stage::Solve: {
             PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
-            if (P.fused) {
-                PHI_STEP("middle", s, (run_middle<R>(P, dir, s)));
-                PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
-                return hipSuccess;
-            }
             if (P.shared) {
                 PHI_STEP("shared_type2", s, (launch_shared_stage(P, 0, dir, s)));
                 PHI_STEP("shared_nodes", s, (launch_shared_stage(P, 1, dir, s)));
@@ -451,10 +344,6 @@ hipError_t mark_kernel(KernelTimer* t, const char* name, bool end, hipStream_t s
     return e;
 }
 
-hipError_t middle_capacity(const DevPlan& P, int* blocks) {
-    if (P.dtype == PHI_F32) return run_capacity<float>(P, blocks);
-    return run_capacity<double>(P, blocks);
-}
 
 hipError_t enqueue(const DevPlan& P, const StreamSet& ss, Stage stage, const void* in, void* out, int adjoint,
                    hipStream_t s, KernelTimer* timer) {

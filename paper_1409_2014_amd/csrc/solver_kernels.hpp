@@ -8,18 +8,6 @@
 
 namespace phi {
 
-// Slots of a plan's counter block for the fused middle launch (see
-// block_sync.hpp): slot k is the unsigned at index k * kSyncStride, one
-// 128-byte line each.
-enum SyncSlot : int {
-    kSyncT2Done = 0,      // type-2 window blocks finished
-    kSyncNodesDone = 1,   // node blocks finished
-    kSyncError = 2,       // sticky: a wait exceeded its spin limit
-    kSyncSlots = 3,
-};
-constexpr int kSyncStride = 32;
-constexpr int kSyncWords = kSyncSlots * kSyncStride;
-
 // Everything a kernel needs, passed by value.  All pointers are device
 // pointers into the plan's single allocation.
 struct DevPlan {
@@ -31,8 +19,7 @@ struct DevPlan {
     int partition_erfc;     // Coulomb: partition erfc(|k|/sigma) (else e^{-|k|^2/sigma^2})
     double inv_sigma;       // 1 / sigma
     int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
-    int fused;              // a solve runs the I1 columns and the node-side chain as one launch
-    int shared;             // (not fused) each node-side launch also runs a slice of the I1 columns
+    int shared;             // each node-side launch also runs a slice of the I1 columns (one stream)
     int shared_cols[3];     // I1 column blocks in the type-2, node and type-1 launches of that layout
     double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index
     int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
@@ -61,7 +48,6 @@ struct DevPlan {
     void* pts;      // M complex: a_j = q_j rho_hat_j
     void* tiles;    // n_sub x E x E complex: each subproblem's spread tile
     void* u;        // N x Q complex: type-1 column transforms, [n2][x]
-    unsigned* sync; // kSyncSlots counters of the fused launch (plan-owned, zero between launches)
 };
 
 // Streams and events a plan uses to run the node-side chain concurrently with
@@ -115,7 +101,7 @@ LaunchEvents& launch_events();
     } while (0)
 
 // Padded sides (log2) for which the shared layout's kernels are built.
-constexpr int kSharedMinLogFine = 10;
+constexpr int kSharedMinLogFine = 4;
 constexpr int kSharedMaxLogFine = 11;
 
 // One launch of the shared layout on stream s: stage 0 (type-2 window
@@ -124,13 +110,6 @@ constexpr int kSharedMaxLogFine = 11;
 // columns after them.  dir is the solve's transform direction.
 hipError_t launch_shared_stage(const DevPlan& P, int stage, int dir, hipStream_t s);
 
-// Blocks of the fused middle launch of plan P that can be resident on the
-// current device at once (the launch is deadlock-free while the blocks that
-// wait are fewer than this).
-hipError_t middle_capacity(const DevPlan& P, int* blocks);
-
-// Blocks of the fused middle launch that wait for other blocks of it.
-inline int middle_waiting_blocks(const DevPlan& P) { return P.n_sub + P.patch; }
 
 // Enqueue a stage chain on stream s (no host synchronisation).  adjoint = 1
 // reverses every transform direction (the transposed operator).

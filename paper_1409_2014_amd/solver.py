@@ -251,12 +251,6 @@ class Plan:
                                             ctypes.byref(count)), self._handle)
         return [(names[i].decode(), float(ms[i])) for i in range(min(count.value, cap))]
 
-    def device_status(self) -> None:
-        """Synchronise and raise if a wait inside the fused solve launch ran past
-        its spin limit since the plan was created."""
-        with torch.cuda.device(self.device):
-            B.check(B.lib().phi_plan_device_status(self._handle), self._handle)
-
     def nodes(self):
         """(kx, ky, q) of the plan's polar nodes as float64 numpy arrays, plan order."""
         m = self.info["n_nodes"]

@@ -1,17 +1,13 @@
-"""The one-stream layouts of a solve's middle part against the two-stream
-layout of separate launches (PHI_TWO_STREAMS):
-  * the fused middle launch (the I1 columns and the whole node-side chain in
-    one launch whose dependent blocks wait on device counters; the default on
-    padded sides up to 512): bit-identical results, forward and transposed, on
-    every padded side from 16 to 512, repeated calls (the counters are zeroed
-    by each solve's first kernel), graph replays, and the device-side
-    spin-limit flag never set;
-  * the shared layout (each of the chain's three launches also runs a slice of
-    the I1 columns; the default for FP32 on padded sides 1024 and 2048):
-    bit-identical results, forward and transposed, for every multiplier, at
-    exact and general grid bounds, and under graph replay.
-Every layout also stays within the solve's bars of the FP64 oracle (checked by
-the parity tests; here one small case per layout closes the loop)."""
+"""The one-stream shared layout of a solve's middle part (each of the node-side
+chain's three launches also runs a slice of the I1 spectrum columns; the
+default on padded sides up to 1024 in both precisions and 2048 in FP32)
+against the two-stream layout of separate launches (PHI_TWO_STREAMS):
+bit-identical results, forward and transposed, on padded sides from 16 to
+4096 (where both flags give the two-stream layout the test still checks the
+flag), for every multiplier, at exact and general grid bounds, on repeated
+calls and under graph replay.  Both layouts also stay within the solve's bars
+of the FP64 oracle (checked by the parity tests; here one small case per
+layout closes the loop)."""
 import numpy as np
 import pytest
 
@@ -46,30 +42,28 @@ CASES = [(8, 4.0), (16, 4.0), (64, 8.0), (96, 4.0), (200, 8.0), (256, 8.0), (300
 
 @pytest.mark.parametrize("n,half", CASES)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_fused_launch_equals_two_streams(ps, n, half, dtype):
-    print(f"case: fused vs two streams N={n} {dtype}", flush=True)
+def test_default_layout_equals_two_streams(ps, n, half, dtype):
+    print(f"case: default layout vs two streams N={n} {dtype}", flush=True)
     h = 2 * half / n
     rho = torch.as_tensor(density(n, half, 500 + n), dtype=dtype, device="cuda")
-    fused = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
+    plan = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
     split = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype], two_streams=True)
-    a1 = fused.solve(rho)
+    a1 = plan.solve(rho)
     b1 = split.solve(rho)
     assert torch.equal(a1, b1)
-    # repeated calls: the counters are back at zero after every launch
     for _ in range(3):
-        assert torch.equal(fused.solve(rho), a1)
-    a2 = fused.solve_adjoint(a1)
+        assert torch.equal(plan.solve(rho), a1)
+    a2 = plan.solve_adjoint(a1)
     b2 = split.solve_adjoint(b1)
     assert torch.equal(a2, b2)
-    fused.device_status()
-    fused.close()
+    plan.close()
     split.close()
 
 
+@pytest.mark.parametrize("n,half", [(64, 8.0), (200, 8.0), (512, 8.0)])
 @pytest.mark.parametrize("component", ["y", "xy", "coulomb"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_shared_layout_other_multipliers(ps, component, dtype):
-    n, half = 512, 8.0
+def test_shared_layout_other_multipliers(ps, n, half, component, dtype):
     print(f"case: shared layout vs two streams N={n} {component} {dtype}", flush=True)
     h = 2 * half / n
     rho = torch.as_tensor(density(n, half, 41), dtype=dtype, device="cuda")
@@ -84,12 +78,12 @@ def test_shared_layout_other_multipliers(ps, component, dtype):
 
 @pytest.mark.parametrize("n,half", [(256, 8.0), (1024, 16.0)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_fused_launch_under_graph_replay(ps, n, half, dtype):
+def test_default_layout_under_graph_replay(ps, n, half, dtype):
     """Ten replays of a captured forward + transposed pair, with eager solves
-    between them: every replay equals the eager result (the fused middle launch
-    at 256^2, the shared layout at 1024^2 in FP32)."""
+    between them: every replay equals the eager result (the shared layout at
+    256^2, and at 1024^2 in FP32)."""
     h = 2 * half / n
-    print(f"case: fused graph replay N={n} {dtype}", flush=True)
+    print(f"case: graph replay N={n} {dtype}", flush=True)
     plan = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
     rho = torch.as_tensor(density(n, half, 77), dtype=dtype, device="cuda")
     ref_f = plan.solve(rho)
@@ -115,12 +109,11 @@ def test_fused_launch_under_graph_replay(ps, n, half, dtype):
         assert torch.equal(out_f, ref_f), f"replay {i}"
         assert torch.equal(out_b, ref_b), f"replay {i}"
         assert torch.equal(plan.solve(rho), ref_f)
-    plan.device_status()
     plan.close()
 
 
 @pytest.mark.parametrize("n,half", [(96, 4.0), (300, 8.0)])
-def test_fused_launch_matches_oracle(ps, n, half):
+def test_default_layout_matches_oracle(ps, n, half):
     h = 2 * half / n
     print(f"case: default layout vs oracle N={n} FP64", flush=True)
     rho = density(n, half, 9)
