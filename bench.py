@@ -86,6 +86,8 @@ def kernel_bytes(info: dict, real_bytes: int) -> dict:
         "cols_type1": tiles + info["n_contrib"] * 4 + (q * q + 1) * 4 + n * q * sc,
         "rows_inverse": spec + n * q * sc + n * n * sr,
     }
+    # the one-stream layout's last launch: the type-1 window columns and every I1 column
+    out["type1_highfreq"] = out["cols_type1"] + out["cols_highfreq"]
     return out
 
 
@@ -97,6 +99,7 @@ def kernel_flops(info: dict) -> dict:
     fft = 5 * f * math.log2(f)
     out = {"rows_forward": n * fft, "cols_highfreq": 2 * (f // 2 + 1) * fft, "rows_inverse": n * fft,
            "cols_type2": q * fft, "cols_type1": q * fft}
+    out["type1_highfreq"] = out["cols_type1"] + out["cols_highfreq"]
     return out
 
 

@@ -68,9 +68,6 @@ phi_status device_fail(phi_plan_t plan, hipError_t e, const char* where) {
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-// relative lengths of the type-2, node and type-1 stages of the node-side
-// chain, by which the shared layout splits the I1 columns over its launches
-constexpr double kSharedWeights[3] = {1.0, 1.6, 2.0};
 
 phi_status check_plan(phi_plan_t plan) {
     if (!is_live(plan)) return fail(nullptr, PHI_ERR_INVALID_ARG, "plan is NULL or was destroyed");
@@ -218,29 +215,20 @@ void fill_dev(const phi::HostPlan& hp, phi_dtype dtype, char* base, const TableP
     const double col_work = (f / 2) * f * std::log2(f) * (dtype == PHI_F32 ? 4.0 : 8.0);
     d->highfreq_first = col_work >= 2048.0 * 4096.0 * 12.0 * 4.0 ? 1 : 0;
     // Padded sides up to 1024 (both precisions) and FP32 solves on padded side
-    // 2048 run the shared layout: the chain's three launches on the solve's
-    // stream, each with a slice of the I1 columns sized to the stage's expected
-    // length (relative weights kSharedWeights).  Graph replay on MI355X, two
-    // runs each: 64^2 FP64 42.5, 43.4 -> 38.2, 38.4 us; 64^2 FP32 45.9, 39.7 ->
-    // 33.8, 34.0; 128^2 FP32 48.9, 48.4 -> 36.2, 36.2; 256^2 FP32 51.5, 45.1 ->
-    // 39.5, 39.8 (against the one launch with device-counter waits that these
-    // sides used before); 512^2 FP32 63.7 -> 41.9, 512^2 FP64 52.5..71 -> 49.5,
-    // 49.5; 1024^2 FP32 49..58 -> 50 (against the two-stream layout, whose time
-    // there varies from run to run).  Where the I1 columns are the longer branch
-    // (FP64 from 1024^2, FP32 from 2048^2) the two-stream layout measured faster
-    // (1024^2 FP64 60..62 against 66 us, 2048^2 FP64 143 against 153 us, FP32 99
-    // against 101 us).
-    d->shared = (!hp.two_streams && hp.width <= phi::kMaxEsWidth &&
-                 hp.log_fine >= phi::kSharedMinLogFine &&
-                 (hp.log_fine <= 10 || (dtype == PHI_F32 && hp.log_fine <= phi::kSharedMaxLogFine))) ? 1 : 0;
-    {
-        const int g = hp.log_fine >= 12 ? 1 : (256 >> (hp.log_fine - 4));   // I1 columns per block
-        const int col_blocks = (hp.n_fine / 2 + 1 + g - 1) / g;
-        const double wsum = kSharedWeights[0] + kSharedWeights[1] + kSharedWeights[2];
-        d->shared_cols[0] = static_cast<int>(col_blocks * kSharedWeights[0] / wsum);
-        d->shared_cols[1] = static_cast<int>(col_blocks * kSharedWeights[1] / wsum);
-        d->shared_cols[2] = col_blocks - d->shared_cols[0] - d->shared_cols[1];
-    }
+    // 2048 run the one-stream layout: cols_type2, nodes, then the type-1 window
+    // columns and every I1 column in one launch.  Graph replay on MI355X, two
+    // runs each (µs): 64^2 FP64 42.5, 43.4 -> 36.3, 36.2; 128^2 FP64 44.9, 51.4
+    // -> 37.7, 37.6; 256^2 FP32 51.5, 45.1 -> 36.7, 36.8; 256^2 FP64 48.4, 50.9 ->
+    // 41.1, 41.0 (against the one launch with device-counter waits that these
+    // sides used before); 512^2 FP32 63.7 -> 38.8, 512^2 FP64 52.5..71 -> 44.8;
+    // 1024^2 FP32 49..58 -> 48.6 (against the two-stream layout, whose time
+    // there varies from run to run).  Splitting the I1 columns over the three
+    // chain launches instead was slower at every size (e.g. 512^2 FP64 50.7,
+    // 1024^2 FP32 50.1).  Where the I1 columns are the longer branch the
+    // two-stream layout is faster: 1024^2 FP64 60..63 against 63.3, 2048^2 FP32
+    // 96.5..97 against 100.3, 2048^2 FP64 143..145 against 152.
+    d->shared = (!hp.two_streams && hp.width <= phi::kMaxEsWidth && hp.log_fine >= phi::kSharedMinLogFine &&
+                 (hp.log_fine <= 10 || (dtype == PHI_F32 && hp.log_fine <= 11))) ? 1 : 0;
     d->freq_scale = 1.0 / (f * hp.h * hp.sigma);
     d->col_stride = static_cast<int>(column_stride(hp));
     d->h2 = hp.h * hp.h;

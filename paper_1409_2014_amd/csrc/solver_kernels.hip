@@ -30,10 +30,10 @@
 //
 // The transposed solve runs the same kernels with every FFT direction reversed.
 //
-// Shared layout (the default on padded sides up to 1024, and 2048 in FP32;
-// shared_kernels.hip): the chain's three kernels run on the solve's own
-// stream, each launch also carrying a slice of the I1 spectrum columns, so the
-// solve needs no second stream.
+// One-stream layout (the default on padded sides up to 1024, and 2048 in FP32;
+// shared_kernels.hip): rows_forward, cols_type2, nodes, then one launch of the
+// type-1 window columns together with every I1 spectrum column, then
+// rows_inverse, all on the solve's stream.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -267,9 +267,9 @@ hipError_t enqueue_typed(const DevPlan& P, const StreamSet& ss, Stage stage, con
         case Stage::Solve: {
             PHI_STEP("rows_forward", s, (run_rows_forward<R>(P, in, dir, s)));
             if (P.shared) {
-                PHI_STEP("shared_type2", s, (launch_shared_stage(P, 0, dir, s)));
-                PHI_STEP("shared_nodes", s, (launch_shared_stage(P, 1, dir, s)));
-                PHI_STEP("shared_type1", s, (launch_shared_stage(P, 2, dir, s)));
+                PHI_STEP("cols_type2", s, (run_cols_type2<R>(P, dir, s)));
+                PHI_STEP("nodes", s, (run_nodes<R, 0>(P, nullptr, nullptr, s)));
+                PHI_STEP("type1_highfreq", s, (launch_type1_highfreq(P, dir, s)));
                 PHI_STEP("rows_inverse", s, (run_rows_inverse<R>(P, out, -dir, 1, 1, s)));
                 return hipSuccess;
             }

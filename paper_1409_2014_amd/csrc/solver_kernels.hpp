@@ -19,8 +19,7 @@ struct DevPlan {
     int partition_erfc;     // Coulomb: partition erfc(|k|/sigma) (else e^{-|k|^2/sigma^2})
     double inv_sigma;       // 1 / sigma
     int highfreq_first;     // a solve enqueues the I1 columns before the node-side chain
-    int shared;             // each node-side launch also runs a slice of the I1 columns (one stream)
-    int shared_cols[3];     // I1 column blocks in the type-2, node and type-1 launches of that layout
+    int shared;             // one stream: the type-1 window columns and all I1 columns in one launch
     double freq_scale;      // 1 / (n_fine h sigma): k/sigma per fine-grid frequency index
     int col_stride;         // elements between consecutive columns of xt and tt (N + pad)
     double h2, inv_f2;
@@ -100,15 +99,14 @@ LaunchEvents& launch_events();
         }                                                                                              \
     } while (0)
 
-// Padded sides (log2) for which the shared layout's kernels are built.
+// Padded sides (log2) for which the one-stream layout's kernel is built.
 constexpr int kSharedMinLogFine = 4;
-constexpr int kSharedMaxLogFine = 11;
+constexpr int kSharedMaxLogFine = 12;
 
-// One launch of the shared layout on stream s: stage 0 (type-2 window
-// columns), 1 (node subproblems) or 2 (type-1 window columns) of the node-side
-// chain in its first blocks, and P.shared_cols[stage] blocks of I1 spectrum
-// columns after them.  dir is the solve's transform direction.
-hipError_t launch_shared_stage(const DevPlan& P, int stage, int dir, hipStream_t s);
+// The one-stream layout's last launch on stream s: the type-1 window columns
+// (one per block) and then every I1 spectrum column.  dir is the solve's
+// transform direction (the type-1 columns run the reverse one).
+hipError_t launch_type1_highfreq(const DevPlan& P, int dir, hipStream_t s);
 
 
 // Enqueue a stage chain on stream s (no host synchronisation).  adjoint = 1
