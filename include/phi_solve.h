@@ -88,9 +88,10 @@ typedef enum { PHI_F64 = 0, PHI_F32 = 1 } phi_dtype;
 #define PHI_TWO_STREAMS 32u /* run the node-side chain as its own three launches on a second stream,
                                 concurrently with the I1 column pass, also where a plan would
                                 otherwise keep the solve on one stream: on padded sides up to 1024
-                                (and 2048 in FP32) the chain's three launches run by default
-                                on the solve's stream, each with a slice of the I1 columns beside
-                                the chain's blocks.  Results are bit-identical in both layouts.
+                                (and 2048 in FP32) a solve by default runs cols_type2 and the node
+                                subproblems in their own launches on the solve's stream, then the
+                                type-1 window columns and every I1 column in one launch.  Results
+                                are bit-identical in both layouts.
                                 Larger sides and the Gaussian kernel above 16 cells always use
                                 the two-stream layout. */
 #define PHI_AUTOTUNE 2u      /* phi_plan / phi_plan_batch time the candidate bin sides {4, 8, 16} and

@@ -1,13 +1,13 @@
-"""The one-stream shared layout of a solve's middle part (each of the node-side
-chain's three launches also runs a slice of the I1 spectrum columns; the
-default on padded sides up to 1024 in both precisions and 2048 in FP32)
-against the two-stream layout of separate launches (PHI_TWO_STREAMS):
-bit-identical results, forward and transposed, on padded sides from 16 to
-4096 (where both flags give the two-stream layout the test still checks the
-flag), for every multiplier, at exact and general grid bounds, on repeated
-calls and under graph replay.  Both layouts also stay within the solve's bars
-of the FP64 oracle (checked by the parity tests; here one small case per
-layout closes the loop)."""
+"""The one-stream layout of a solve's middle part (cols_type2 and nodes in
+their own launches, then the type-1 window columns and every I1 spectrum
+column in one launch; the default on padded sides up to 1024 in both
+precisions and 2048 in FP32) against the two-stream layout of separate
+launches (PHI_TWO_STREAMS): bit-identical results, forward and transposed, on
+padded sides from 16 to 4096 (where both flags give the two-stream layout the
+test still checks the flag), for every multiplier, at exact and general grid
+bounds, on repeated calls and under graph replay.  Both layouts also stay
+within the solve's bars of the FP64 oracle (checked by the parity tests; here
+one small case per layout closes the loop)."""
 import numpy as np
 import pytest
 
@@ -63,8 +63,8 @@ def test_default_layout_equals_two_streams(ps, n, half, dtype):
 @pytest.mark.parametrize("n,half", [(64, 8.0), (200, 8.0), (512, 8.0)])
 @pytest.mark.parametrize("component", ["y", "xy", "coulomb"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_shared_layout_other_multipliers(ps, n, half, component, dtype):
-    print(f"case: shared layout vs two streams N={n} {component} {dtype}", flush=True)
+def test_one_stream_layout_other_multipliers(ps, n, half, component, dtype):
+    print(f"case: one-stream layout vs two streams N={n} {component} {dtype}", flush=True)
     h = 2 * half / n
     rho = torch.as_tensor(density(n, half, 41), dtype=dtype, device="cuda")
     a = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype], component=component)
@@ -80,8 +80,8 @@ def test_shared_layout_other_multipliers(ps, n, half, component, dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_default_layout_under_graph_replay(ps, n, half, dtype):
     """Ten replays of a captured forward + transposed pair, with eager solves
-    between them: every replay equals the eager result (the shared layout at
-    256^2, and at 1024^2 in FP32)."""
+    between them: every replay equals the eager result (the one-stream layout
+    at 256^2, and at 1024^2 in FP32)."""
     h = 2 * half / n
     print(f"case: graph replay N={n} {dtype}", flush=True)
     plan = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
