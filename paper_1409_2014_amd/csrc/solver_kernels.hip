@@ -44,10 +44,19 @@ namespace phi {
 // ---------------------------------------------------------------------------
 // Single-solve kernels: one work item per block
 // ---------------------------------------------------------------------------
-template <typename R, int LOG, int DIR, bool EXACT>
-__global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_forward(
-    DevPlan P, const R* __restrict__ rho) {
-    constexpr int G = rows_per_block<R, LOG>();
+// The row kernels come in two widths: rows_per_block rows per block, and one
+// wave per block (rows_per_wave) for grids with fewer rows than it takes to give
+// every CU a wide block; the rows' arithmetic is the same in both.
+template <typename R, int LOG>
+constexpr int rows_per_wave() {
+    constexpr int nt = FftShape<LOG>::NT;
+    constexpr int g = nt >= 64 ? 1 : 64 / nt;
+    return g < rows_per_block<R, LOG>() ? g : rows_per_block<R, LOG>();
+}
+constexpr int kRowsWideMinBlocks = 256;   // one wide block per CU at least, else the narrow width
+
+template <typename R, int LOG, int DIR, bool EXACT, int G>
+__global__ __launch_bounds__((FftShape<LOG>::NT * G)) void k_rows_forward(DevPlan P, const R* __restrict__ rho) {
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
     rows_forward_body<R, LOG, DIR, G, EXACT>(P, rho, xcd_logical_block(blockIdx.x, gridDim.x) * G, lds_all);
 }
@@ -81,10 +90,8 @@ __global__ __launch_bounds__(FftShape<LOG>::NT * lines_per_block<LOG>()) void k_
     cols_type1_body<R, LOG, DIR, G, 1, false>(P, blockIdx.x, lds_all);
 }
 
-template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2, bool EXACT>
-__global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) void k_rows_inverse(
-    DevPlan P, R* __restrict__ out) {
-    constexpr int G = rows_per_block<R, LOG>();
+template <typename R, int LOG, int DIR, bool USE_I1, bool USE_I2, bool EXACT, int G>
+__global__ __launch_bounds__((FftShape<LOG>::NT * G)) void k_rows_inverse(DevPlan P, R* __restrict__ out) {
     __shared__ cpx<R> lds_all[G * lds_group_stride(1 << LOG)];
     rows_inverse_body<R, LOG, DIR, USE_I1, USE_I2, G, EXACT>(P, out, xcd_logical_block(blockIdx.x, gridDim.x) * G,
                                                              lds_all);
@@ -95,15 +102,21 @@ __global__ __launch_bounds__((FftShape<LOG>::NT * rows_per_block<R, LOG>())) voi
 // ---------------------------------------------------------------------------
 namespace {
 
+template <typename R, int LOG, int DIR, int G>
+hipError_t launch_rows_forward_g(const DevPlan& P, const R* src, hipStream_t s) {
+    constexpr int block = FftShape<LOG>::NT * G;
+    const int grid = (P.n + G - 1) / G;   // one work item per block
+    if (2 * P.n == P.n_fine) PHI_LAUNCH((k_rows_forward<R, LOG, DIR, true, G>), dim3(grid), dim3(block), 0, s, P, src);
+    else PHI_LAUNCH((k_rows_forward<R, LOG, DIR, false, G>), dim3(grid), dim3(block), 0, s, P, src);
+    return hipGetLastError();
+}
+
 template <typename R, int LOG, int DIR>
 hipError_t launch_rows_forward_dir(const DevPlan& P, const R* src, hipStream_t s) {
-    constexpr int G = rows_per_block<R, LOG>();
-    constexpr int block = FftShape<LOG>::NT * G;
-    const int items = (P.n + G - 1) / G;
-    const int grid = items;   // one work item per block
-    if (2 * P.n == P.n_fine) PHI_LAUNCH((k_rows_forward<R, LOG, DIR, true>), dim3(grid), dim3(block), 0, s, P, src);
-    else PHI_LAUNCH((k_rows_forward<R, LOG, DIR, false>), dim3(grid), dim3(block), 0, s, P, src);
-    return hipGetLastError();
+    constexpr int GW = rows_per_block<R, LOG>();
+    if ((P.n + GW - 1) / GW < kRowsWideMinBlocks)
+        return launch_rows_forward_g<R, LOG, DIR, rows_per_wave<R, LOG>()>(P, src, s);
+    return launch_rows_forward_g<R, LOG, DIR, GW>(P, src, s);
 }
 
 template <typename R, int LOG>
@@ -159,18 +172,24 @@ hipError_t launch_cols_type1(const DevPlan& P, int dir, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename R, int LOG, int DIR, bool I1, bool I2>
-hipError_t launch_rows_inverse_parts(const DevPlan& P, R* dst, hipStream_t s) {
-    constexpr int G = rows_per_block<R, LOG>();
+template <typename R, int LOG, int DIR, bool I1, bool I2, int G>
+hipError_t launch_rows_inverse_g(const DevPlan& P, R* dst, hipStream_t s) {
     constexpr int block = FftShape<LOG>::NT * G;
-    const int items = (P.n + G - 1) / G;
-    const int grid = items;   // one work item per block
+    const int grid = (P.n + G - 1) / G;   // one work item per block
     // the full solve (I1 and I2) has an exact-bounds variant; the stage variants use the general one
     if (I1 && I2 && 2 * P.n == P.n_fine)
-        PHI_LAUNCH((k_rows_inverse<R, LOG, DIR, I1, I2, I1 && I2>), dim3(grid), dim3(block), 0, s, P, dst);
+        PHI_LAUNCH((k_rows_inverse<R, LOG, DIR, I1, I2, I1 && I2, G>), dim3(grid), dim3(block), 0, s, P, dst);
     else
-        PHI_LAUNCH((k_rows_inverse<R, LOG, DIR, I1, I2, false>), dim3(grid), dim3(block), 0, s, P, dst);
+        PHI_LAUNCH((k_rows_inverse<R, LOG, DIR, I1, I2, false, G>), dim3(grid), dim3(block), 0, s, P, dst);
     return hipGetLastError();
+}
+
+template <typename R, int LOG, int DIR, bool I1, bool I2>
+hipError_t launch_rows_inverse_parts(const DevPlan& P, R* dst, hipStream_t s) {
+    constexpr int GW = rows_per_block<R, LOG>();
+    if ((P.n + GW - 1) / GW < kRowsWideMinBlocks)
+        return launch_rows_inverse_g<R, LOG, DIR, I1, I2, rows_per_wave<R, LOG>()>(P, dst, s);
+    return launch_rows_inverse_g<R, LOG, DIR, I1, I2, GW>(P, dst, s);
 }
 
 template <typename R, int LOG, int DIR>
