@@ -123,3 +123,27 @@ def test_default_layout_matches_oracle(ps, n, half):
     plan.close()
     ref = O.phi(rho, O.SplitParams(n=n, h=h, n_r=64, n_theta=128, pad_side=fine))
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,half,dtype,one_stream", [
+    (64, 8.0, torch.float64, True), (256, 8.0, torch.float32, True), (512, 8.0, torch.float64, True),
+    (1024, 16.0, torch.float32, True), (1024, 16.0, torch.float64, False), (2048, 16.0, torch.float32, False)])
+def test_layout_choice_by_size(ps, n, half, dtype, one_stream):
+    """The plan's layout, read off the kernels a timed solve reports: the
+    one-stream layout on padded sides up to 1024 and on 2048 in FP32 (its last
+    launch holds the type-1 window columns and the I1 columns), the two-stream
+    layout beyond; PHI_TWO_STREAMS always gives the two-stream one."""
+    print(f"case: layout choice N={n} {dtype}", flush=True)
+    h = 2 * half / n
+    rho = torch.as_tensor(density(n, half, 7), dtype=dtype, device="cuda")
+    out = torch.empty_like(rho)
+    plan = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype])
+    names = [name for name, _ in plan.solve_timed(rho, out)]
+    plan.close()
+    expect = (["rows_forward", "cols_type2", "nodes", "type1_highfreq", "rows_inverse"] if one_stream else
+              ["rows_forward", "cols_type2", "nodes", "cols_type1", "cols_highfreq", "rows_inverse"])
+    assert sorted(names) == sorted(expect), names
+    split = ps.Plan(n, h, dtype=dtype, tol=TOLS[dtype], two_streams=True)
+    names = [name for name, _ in split.solve_timed(rho, out)]
+    split.close()
+    assert "type1_highfreq" not in names and "cols_highfreq" in names
