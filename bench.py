@@ -56,10 +56,10 @@ VALU_PEAK_PUBLISHED_F32 = 157.3
 TRAFFIC_RECORD = {
     "kernel": "cols_highfreq",
     "fetch_kib": 16745.6, "write_kib": 32784.0,
-    "copy_fetch_kib": 131088.50, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "copy_fetch_kib": 131093.75, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
     "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "fcfe05dd8a5bcf081afe6fbe56ae0c5d2d1c66896a35e5f45f07df236faf7d45",
+    "sha256": "c466104304516bda9766e35ea7aa73124adb655a6132b237d78669dd5a0ae2a9",
 }
 
 N = 2048

