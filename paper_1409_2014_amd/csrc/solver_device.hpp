@@ -418,9 +418,13 @@ __device__ __forceinline__ int small_div(int x, unsigned magic) {
     return static_cast<int>((static_cast<unsigned>(x) * magic) >> 16);
 }
 
-template <typename R, int MODE, int NTH, int WMAX>
+// W: the kernel width when it is fixed at compile time (0: read from the plan).
+// A fixed width lets the tap loops unroll, so the LDS reads of a node's whole
+// tap row issue together; the sums keep their order, so the bits are the same.
+template <typename R, int MODE, int NTH, int WMAX, int W = 0>
 __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx<R>* __restrict__ coef,
                                            cpx<R>* __restrict__ out, NodeLds<R, WMAX>& s) {
+    static_assert(W >= 0 && W <= WMAX, "a fixed width within the tap store");
     static_assert(NTH % kLanesPerNode == 0 && NTH % kSpreadParts == 0, "whole node and cell groups");
     static_assert(NTH >= kMaxNodesPerSub, "one thread per node for the node scalars");
     static_assert(kTileMax * kTileMax < 1024 && kTileMax <= 31 && WMAX * WMAX <= 1024 && WMAX <= kMaxKernelWidth,
@@ -429,7 +433,8 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
     constexpr int CPT = (kTileMax * kTileMax + NTH - 1) / NTH;                     // tile cells per thread
     const int* sub = P.sub + 4 * sidx;
     const int bx = sub[0], by = sub[1], first = sub[2], count = sub[3];
-    const int w = P.width, E = P.tile, q = P.patch, bin = P.bin;
+    const int w = W > 0 ? W : P.width;
+    const int E = P.tile, q = P.patch, bin = P.bin;
     const int w2 = 2 * w;
     const int x0 = bx * bin, y0 = by * bin;   // tile corner in window cells
     const unsigned magic_e = small_div_magic(E);
@@ -514,7 +519,7 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
                 for (int t2 = lane; t2 < w; t2 += kLanesPerNode) {
                     const cpx<R>* trow = s.tile + (o.y + t2) * ES + o.x;
                     cpx<R> row = {R(0), R(0)};
-                    for (int t0 = 0; t0 < w; t0 += 4) {
+                    auto chunk = [&](int t0) {
                         R k[4];
                         cpx<R> b[4];
 #pragma unroll
@@ -529,6 +534,12 @@ __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx
                             row.x += b[u].x * k[u];
                             row.y += b[u].y * k[u];
                         }
+                    };
+                    if constexpr (W > 0) {
+#pragma unroll
+                        for (int t0 = 0; t0 < W; t0 += 4) chunk(t0);
+                    } else {
+                        for (int t0 = 0; t0 < w; t0 += 4) chunk(t0);
                     }
                     const R ky = tj[w + t2];
                     acc.x += row.x * ky;

@@ -76,11 +76,11 @@ __global__ __launch_bounds__(FftShape<LOG>::NT) void k_cols_type2(DevPlan P) {
     cols_type2_body<R, LOG, DIR, 1, false>(P, blockIdx.x, lds_all);
 }
 
-template <typename R, int MODE, int WMAX>
+template <typename R, int MODE, int WMAX, int W>
 __global__ __launch_bounds__(kNodeThreadsSingle) void k_nodes(DevPlan P, const cpx<R>* __restrict__ coef,
                                                         cpx<R>* __restrict__ out) {
     __shared__ NodeLds<R, WMAX> s;
-    nodes_body<R, MODE, kNodeThreadsSingle, WMAX>(P, blockIdx.x, coef, out, s);
+    nodes_body<R, MODE, kNodeThreadsSingle, WMAX, W>(P, blockIdx.x, coef, out, s);
 }
 
 template <typename R, int LOG, int DIR>
@@ -253,12 +253,30 @@ hipError_t run_rows_inverse(const DevPlan& P, void* out, int dir, int use_i1, in
 
 template <typename R, int MODE>
 hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t s) {
-    if (P.width > kMaxEsWidth)
-        PHI_LAUNCH((k_nodes<R, MODE, kMaxKernelWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
-                           static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
-    else
-        PHI_LAUNCH((k_nodes<R, MODE, kMaxEsWidth>), dim3(P.n_sub), dim3(kNodeThreadsSingle), 0, s, P,
-                           static_cast<const cpx<R>*>(coef), static_cast<cpx<R>*>(out));
+    const dim3 grid(P.n_sub), block(kNodeThreadsSingle);
+    const cpx<R>* c = static_cast<const cpx<R>*>(coef);
+    cpx<R>* o = static_cast<cpx<R>*>(out);
+    // the node stage of a solve takes a compile-time width for the ES kernels
+#define PHI_NODES_W(WV) \
+    case WV: PHI_LAUNCH((k_nodes<R, MODE, kMaxEsWidth, WV>), grid, block, 0, s, P, c, o); break;
+    static_assert(kMaxEsWidth == 16, "one case per ES width");
+    if constexpr (MODE == 0) {
+        if (P.width <= kMaxEsWidth) {
+            switch (P.width) {
+                PHI_NODES_W(2) PHI_NODES_W(3) PHI_NODES_W(4) PHI_NODES_W(5) PHI_NODES_W(6) PHI_NODES_W(7)
+                PHI_NODES_W(8) PHI_NODES_W(9) PHI_NODES_W(10) PHI_NODES_W(11) PHI_NODES_W(12) PHI_NODES_W(13)
+                PHI_NODES_W(14) PHI_NODES_W(15) PHI_NODES_W(16)
+                default: PHI_LAUNCH((k_nodes<R, MODE, kMaxEsWidth, 0>), grid, block, 0, s, P, c, o); break;
+            }
+            return hipGetLastError();
+        }
+    }
+    if (P.width > kMaxEsWidth) {
+        PHI_LAUNCH((k_nodes<R, MODE, kMaxKernelWidth, 0>), grid, block, 0, s, P, c, o);
+    } else {
+        PHI_LAUNCH((k_nodes<R, MODE, kMaxEsWidth, 0>), grid, block, 0, s, P, c, o);
+    }
+#undef PHI_NODES_W
     return hipGetLastError();
 }
 
