@@ -56,10 +56,10 @@ VALU_PEAK_PUBLISHED_F32 = 157.3
 TRAFFIC_RECORD = {
     "kernel": "cols_highfreq",
     "fetch_kib": 16750.6, "write_kib": 32784.0,
-    "copy_fetch_kib": 131088.38, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
+    "copy_fetch_kib": 131088.81, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
     "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "093a3e4d22fadbfc0d1964ab3c6e3a5a9e3da816fd632bfda2f4c07e218efa07",
+    "sha256": "d5c9862d97f727bd66461d45c62514b3f06e7933f3ad6503f34b805d29c7d471",
 }
 
 N = 2048

@@ -670,6 +670,20 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
         }
         if (lane == 0) lds_all[c * LP + i2] = {vx, vy};
     }
+    // the deconvolution factors of the stored rows, fetched before the
+    // transform (slots outside the crop read the factor of row N/2)
+    const int half = EXACT ? F / 4 : (P.n >> 1);
+    const double* dy = P.deconv + half;
+    double dpre[8];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < 4 || i >= 12) {
+            const int p = tid + NT * i;
+            const int o = (i < 4) ? p : p - F;
+            const bool inside = (i < 4) ? (p < half) : (p >= F - half);
+            dpre[i < 4 ? i : i - 8] = dy[inside ? o : 0];
+        }
+    }
     __syncthreads();
     const int c = g % COLS;
     const int i1 = i1_base + c;
@@ -683,9 +697,7 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
     }
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     if (active && g < COLS) {
-        const int half = EXACT ? F / 4 : (P.n >> 1);
         cpx<R>* u = static_cast<cpx<R>*>(P.u) + static_cast<size_t>(half) * q + i1;
-        const double* dy = P.deconv + half;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int p = tid + NT * i;
@@ -693,7 +705,7 @@ __device__ __forceinline__ void cols_type1_body(const DevPlan& P, int i1_base, c
                 const int o = (i < 4) ? p : p - F;     // grid row n2 = o + N/2
                 const bool inside = (i < 4) ? (p < half) : (p >= F - half);
                 if (inside) {
-                    const double d = dy[o];
+                    const double d = dpre[i < 4 ? i : i - 8];
                     u[static_cast<ptrdiff_t>(o) * q] = {static_cast<R>(v[i].x * d), static_cast<R>(v[i].y * d)};
                 }
             }
@@ -762,22 +774,37 @@ __device__ __forceinline__ void rows_inverse_body(const DevPlan& P, R* __restric
         l[lds_pad(m)] = {x.x - hh.y, x.y + hh.x};
         if (m > 0 && m < HALF) l[lds_pad(F - m)] = {x.x + hh.y, -x.y + hh.x};
     }
+    // the deconvolution factors of the stored slots, fetched before the
+    // transform so that their latency overlaps it (slots outside the crop read
+    // the factor of row N/2)
+    const int half = EXACT ? F / 4 : (n >> 1);
+    const double* dx = P.deconv + half;
+    double dpre[8];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (i < 4 || i >= 12) {
+            const int p = tid + NT * i;
+            const int o = (i < 4) ? p : p - F;
+            const bool inside = (i < 4) ? (p < half) : (p >= F - half);
+            dpre[i < 4 ? i : i - 8] = dx[inside ? o : 0];
+        }
+    }
     __syncthreads();
     cpx<R> v[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = lds[lds_pad(tid + NT * i)];
     fft_reg<R, LOG, DIR>(v, lds, tw, tid);
     if (EXACT || row0 + g < n) {
-        const int half = EXACT ? F / 4 : (n >> 1);
         R* dst = out + static_cast<size_t>(row0 + g) * n + half;
-        const double* dx = P.deconv + half;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int p = tid + NT * i;
             if (i < 4 || i >= 12) {
                 const int o = (i < 4) ? p : p - F;
                 const bool inside = (i < 4) ? (p < half) : (p >= F - half);
-                if (inside) dst[o] = static_cast<R>(static_cast<double>(v[i].x) + static_cast<double>(v[i].y) * dx[o]);
+                if (inside)
+                    dst[o] = static_cast<R>(static_cast<double>(v[i].x) +
+                                            static_cast<double>(v[i].y) * dpre[i < 4 ? i : i - 8]);
             }
         }
     }
