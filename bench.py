@@ -59,7 +59,7 @@ TRAFFIC_RECORD = {
     "copy_fetch_kib": 131088.81, "copy_write_kib": 262144.0, "copy_true_kib": 262144.0,
     "sources": ("device_common.hpp", "fft_reg.hpp", "solver_device.hpp", "solver_kernels.hip",
                 "solver_kernels.hpp"),
-    "sha256": "d5c9862d97f727bd66461d45c62514b3f06e7933f3ad6503f34b805d29c7d471",
+    "sha256": "3d5e1e29587292106d23ea2405c8dc4333448a25899ae7fb8a3465ef031cc42a",
 }
 
 N = 2048

@@ -419,8 +419,9 @@ __device__ __forceinline__ int small_div(int x, unsigned magic) {
 }
 
 // W: the kernel width when it is fixed at compile time (0: read from the plan).
-// A fixed width lets the tap loops unroll, so the LDS reads of a node's whole
-// tap row issue together; the sums keep their order, so the bits are the same.
+// A fixed width lets the interpolation's tap loop unroll, so the LDS reads of a
+// node's whole tap row issue together; the sums keep their order, so the bits
+// are the same.
 template <typename R, int MODE, int NTH, int WMAX, int W = 0>
 __device__ __forceinline__ void nodes_body(const DevPlan& P, int sidx, const cpx<R>* __restrict__ coef,
                                            cpx<R>* __restrict__ out, NodeLds<R, WMAX>& s) {

@@ -256,7 +256,8 @@ hipError_t run_nodes(const DevPlan& P, const void* coef, void* out, hipStream_t 
     const dim3 grid(P.n_sub), block(kNodeThreadsSingle);
     const cpx<R>* c = static_cast<const cpx<R>*>(coef);
     cpx<R>* o = static_cast<cpx<R>*>(out);
-    // the node stage of a solve takes a compile-time width for the ES kernels
+    // the node stage of a solve takes its kernel width as a template argument
+    // whenever the width fits the ES tap store (every ES kernel, narrow Gaussians)
 #define PHI_NODES_W(WV) \
     case WV: PHI_LAUNCH((k_nodes<R, MODE, kMaxEsWidth, WV>), grid, block, 0, s, P, c, o); break;
     static_assert(kMaxEsWidth == 16, "one case per ES width");
